@@ -1,0 +1,92 @@
+"""Layer partition and extended grids along the sweep axis.  Parity pinned
+(printed layer sizes of Sections 3.2 and 4.2, printed index sets of
+Sections 2.1 and 3.1; tests/test_oracle_partition.py).
+
+All indices are 1-based grid lines along the sweep axis (x2 in 2D, x3 in 3D,
+Sections 3.1 and 4.1), inclusive ranges.  g = gamma - 1 is the number of grid
+lines strictly inside one PML (sigma > 0): with eta = gamma*h the lines
+1..gamma-1 carry sigma > 0 and line gamma is the first physical line.
+
+Partition (Section 2, X_1..X_m; generalised to n != 2*gamma + m*b - 2 as the
+experiments of Sections 3.2 and 4.2 require, where the first layer has b+gamma-1
+lines and the last b+gamma-2):
+
+    n_phys = n - 2g,  m = ceil(n_phys / b)
+    X_1 = [1, g+b],  X_p = [gamma+(p-1)b, gamma+pb-1] (1<p<m),  X_m = [gamma+(m-1)b, n]
+
+so the last layer holds r = n_phys - (m-1)b in [1, b] physical lines plus the
+g PML lines; with n = 2*gamma + m*b - 2 this is exactly the paper's partition.
+
+Extended grids and the zero regions of their sweep-axis PML profiles
+(Section 2.1 definitions of D^M_q, X^M_q, sigma^M_q, D^R_p, X^R_p, sigma^R_p,
+D^L_p, X^L_p, sigma^L_p; the same sets in 2D and 3D):
+
+    M_q: zero region [phi_q, psi_q],      lines [phi_q - g, psi_q + g]
+    R_p: zero region [s_p - 1, psi_p],    lines [s_p, psi_p + g]        (p >= 2)
+    L_p: zero region [phi_p, e_p + 1],    lines [phi_p - g, e_p]        (p <= m-1)
+
+with [s_p, e_p] = X_p and its physical part phi_p = max(s_p, gamma),
+psi_p = min(e_p, n+1-gamma).  sigma^R_p vanishes from the Dirichlet line
+s_p - 1 (the left boundary of D^R_p) and sigma^L_p up to the Dirichlet line
+e_p + 1 (the right boundary of D^L_p), as in their definitions.
+"""
+from dataclasses import dataclass
+
+
+@dataclass(frozen=True)
+class Sub:
+    kind: str   # "M", "R" or "L"
+    p: int      # layer index, 1-based
+    lo: int     # first grid line of the extended grid
+    hi: int     # last grid line of the extended grid
+    phi: float  # zero region of the sweep-axis PML profile
+    psi: float
+
+    @property
+    def L(self):
+        return self.hi - self.lo + 1
+
+
+def check_args(n, b, gamma):
+    if gamma < 2 or b < 1 or n - 2 * (gamma - 1) < 1:
+        raise ValueError(f"invalid partition n={n} b={b} gamma={gamma}")
+
+
+def layers(n, b, gamma):
+    """[(s_p, e_p)] for p = 1..m."""
+    check_args(n, b, gamma)
+    g = gamma - 1
+    n_phys = n - 2 * g
+    m = -(-n_phys // b)
+    if m == 1:
+        return [(1, n)]
+    X = [(1, g + b)]
+    for p in range(2, m):
+        X.append((gamma + (p - 1) * b, gamma + p * b - 1))
+    X.append((gamma + (m - 1) * b, n))
+    return X
+
+
+def physical(n, gamma, layer):
+    s_p, e_p = layer
+    return max(s_p, gamma), min(e_p, n + 1 - gamma)
+
+
+def subproblems(n, b, gamma):
+    """Dict with lists 'M' (q=1..m), 'R' (p=2..m) and 'L' (p=1..m-1) of Sub."""
+    X = layers(n, b, gamma)
+    m = len(X)
+    g = gamma - 1
+    M, R, L = [], [], []
+    for q in range(1, m + 1):
+        phi, psi = physical(n, gamma, X[q - 1])
+        M.append(Sub("M", q, phi - g, psi + g, phi, psi))
+    for p in range(2, m + 1):
+        s_p, _ = X[p - 1]
+        _, psi = physical(n, gamma, X[p - 1])
+        R.append(Sub("R", p, s_p, psi + g, s_p - 1, psi))
+    for p in range(1, m):
+        _, e_p = X[p - 1]
+        phi, _ = physical(n, gamma, X[p - 1])
+        L.append(Sub("L", p, phi - g, e_p, phi, e_p + 1))
+    return {"M": M, "R": R, "L": L}

@@ -1,0 +1,105 @@
+"""The additive sweeping preconditioner: setup (Algorithms 1 and 3) and apply
+(Algorithms 2 and 4).  Parity pinned (the O(m^2) per-component recursion of
+Section 2.1 it must equal exactly; m = 1 gives A^-1; the iteration counts of
+Tables 1-3 at the paper's settings; tests/test_oracle_sweep.py).
+
+Notation follows Section 2.1 ("Accumulating the boundary values") and the
+"Putting together" paragraph of Section 3.1: for a vector on X_p (column-major,
+sweep axis slowest) its left boundary value g^L is the first grid line and its
+right boundary value g^R the last one.
+"""
+import numpy as np
+
+from . import partition
+from .subproblem import Subproblem
+
+
+class Preconditioner:
+    """M^-1 for the symmetric-form system of ``prob`` (an operator.Problem).
+
+    keep_factors=False factors each subproblem when it is used and drops it
+    afterwards: same arithmetic, bounded memory, for large grids."""
+
+    def __init__(self, prob, keep_factors=True):
+        self.prob = prob
+        self.X = partition.layers(prob.n, prob.b, prob.gamma)
+        self.m = len(self.X)
+        subs = partition.subproblems(prob.n, prob.b, prob.gamma)
+        self.keep = keep_factors
+        # Algorithm 1 / 3: factor H^M_q (q=1..m), H^R_p (p=2..m), H^L_p (p=1..m-1).
+        mk = lambda s: Subproblem(prob, s, self.X[s.p - 1], factor=keep_factors)
+        self.M = {s.p: mk(s) for s in subs["M"]}
+        self.R = {s.p: mk(s) for s in subs["R"]}
+        self.L = {s.p: mk(s) for s in subs["L"]}
+
+    # -- pieces -------------------------------------------------------------------------
+    def layer(self, vec, p):
+        s_p, e_p = self.X[p - 1]
+        return self.prob.lines(vec, s_p, e_p)
+
+    def left(self, v):
+        return v[: self.prob.S]
+
+    def right(self, v):
+        return v[-self.prob.S:]
+
+    def _G(self, sp_, data):
+        out = sp_.G(data)
+        if not self.keep:
+            sp_.lu = None
+        return out
+
+    def GM(self, q, y):
+        return self._G(self.M[q], y)
+
+    def GR(self, p, w):
+        return self._G(self.R[p], w)
+
+    def GL(self, p, w):
+        return self._G(self.L[p], w)
+
+    # -- Algorithm 2 / 4 -------------------------------------------------------------------
+    def apply(self, f):
+        """u~ = M^-1 f, step by step as in Algorithms 2 and 4."""
+        m = self.m
+        f = np.asarray(f, dtype=np.complex128)
+        u_qq = {q: self.GM(q, self.layer(f, q)) for q in range(1, m + 1)}
+        # right-going waves: u~_{p,1:p-1} and the accumulated boundary value u~^R_{p,1:p}
+        u_rt = {}
+        acc_R = self.right(u_qq[1])                      # u~^R_{1,1:1} = u~^R_{1,1}
+        for p in range(2, m + 1):
+            u_rt[p] = self.GR(p, acc_R)                  # u~_{p,1:p-1} = G~^R_p u~^R_{p-1,1:p-1}
+            acc_R = self.right(u_rt[p]) + self.right(u_qq[p])
+        # left-going waves: u~_{p,p+1:m} and u~^L_{p,p:m}
+        u_lt = {}
+        acc_L = self.left(u_qq[m])                       # u~^L_{m,m:m} = u~^L_{m,m}
+        for p in range(m - 1, 0, -1):
+            u_lt[p] = self.GL(p, acc_L)                  # u~_{p,p+1:m} = G~^L_p u~^L_{p+1,p+1:m}
+            acc_L = self.left(u_qq[p]) + self.left(u_lt[p])
+        # u~_p = u~_{p,1:p-1} + u~_{p,p} + u~_{p,p+1:m} (two terms at the ends)
+        out = []
+        for p in range(1, m + 1):
+            v = u_qq[p].copy()
+            if p > 1:
+                v = u_rt[p] + v
+            if p < m:
+                v = v + u_lt[p]
+            out.append(v)
+        return np.concatenate(out)
+
+    def apply_componentwise(self, f):
+        """The O(m^2) form of Section 2.1: every u~_{p,q} by its own recursion,
+        u~_{p,q} = G~^R_p u~^R_{p-1,q} (p > q), G~^L_p u~^L_{p+1,q} (p < q),
+        then u~_p = sum_q u~_{p,q}."""
+        m = self.m
+        f = np.asarray(f, dtype=np.complex128)
+        total = {p: 0 for p in range(1, m + 1)}
+        for q in range(1, m + 1):
+            u = {q: self.GM(q, self.layer(f, q))}
+            for p in range(q + 1, m + 1):
+                u[p] = self.GR(p, self.right(u[p - 1]))
+            for p in range(q - 1, 0, -1):
+                u[p] = self.GL(p, self.left(u[p + 1]))
+            for p in range(1, m + 1):
+                total[p] = total[p] + u[p]
+        return np.concatenate([total[p] for p in range(1, m + 1)])

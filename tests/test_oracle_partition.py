@@ -1,0 +1,96 @@
+"""Pins of oracle.partition: the layer sizes printed with the experiments
+(Sections 3.2, 4.2), the index sets printed in Sections 2.1 and 3.1 (under
+the paper's assumption n = 2 gamma + m b - 2), and structural invariants."""
+import json
+import os
+
+import pytest
+
+from oracle import partition
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_printed_first_and_last_layer_sizes():
+    data = json.load(open(os.path.join(GOLDEN, "paper_layer_sizes.json")))
+    for case in data["cases"]:
+        for n in case["n"]:
+            X = partition.layers(n, case["b"], case["gamma"])
+            assert X[0][1] - X[0][0] + 1 == case["first"], (case, n)
+            assert X[-1][1] - X[-1][0] + 1 == case["last"], (case, n)
+
+
+@pytest.mark.parametrize("gamma,b,m", [(9, 8, 6), (12, 4, 9), (5, 3, 3), (2, 1, 4)])
+def test_printed_index_sets(gamma, b, m):
+    n = 2 * gamma + m * b - 2
+    X = partition.layers(n, b, gamma)
+    assert len(X) == m
+    # Section 2 / 3.1: X_1, X_p, X_m
+    assert X[0] == (1, gamma + b - 1)
+    for p in range(2, m):
+        assert X[p - 1] == (gamma + (p - 1) * b, gamma + p * b - 1)
+    assert X[-1] == (gamma + (m - 1) * b, 2 * gamma + m * b - 2)
+    subs = partition.subproblems(n, b, gamma)
+    # X^M_q = {(q-1)b+1 <= i <= 2 gamma + q b - 2}  (Section 2.1)
+    for s in subs["M"]:
+        q = s.p
+        assert (s.lo, s.hi) == ((q - 1) * b + 1, 2 * gamma + q * b - 2)
+    # X^R_p = {gamma + (p-1)b <= i <= 2 gamma + p b - 2}, p = 2..m
+    assert [s.p for s in subs["R"]] == list(range(2, m + 1))
+    for s in subs["R"]:
+        p = s.p
+        assert (s.lo, s.hi) == (gamma + (p - 1) * b, 2 * gamma + p * b - 2)
+        # left boundary of D^R_p is at x = eta + ((p-1)b - 1)h, i.e. the last line of X_{p-1}
+        assert s.lo - 1 == gamma + (p - 1) * b - 1 == X[p - 2][1]
+    # X^L_p = {(p-1)b+1 <= i <= gamma + p b - 1}, p = 1..m-1
+    assert [s.p for s in subs["L"]] == list(range(1, m))
+    for s in subs["L"]:
+        p = s.p
+        assert (s.lo, s.hi) == ((p - 1) * b + 1, gamma + p * b - 1)
+        # right boundary of D^L_p is at x = eta + p b h, i.e. the first line of X_{p+1}
+        assert s.hi + 1 == gamma + p * b == X[p][0]
+    # X^R_m = X_m and X^L_1 = X_1
+    assert (subs["R"][-1].lo, subs["R"][-1].hi) == X[-1]
+    assert (subs["L"][0].lo, subs["L"][0].hi) == X[0]
+
+
+@pytest.mark.parametrize("n", [63, 64, 65, 66, 127, 511, 1023, 31, 39, 79, 159])
+@pytest.mark.parametrize("gamma,b", [(12, 4), (9, 8), (8, 4), (9, 4), (3, 5)])
+def test_partition_invariants(n, gamma, b):
+    if n - 2 * (gamma - 1) < 1:
+        pytest.skip("grid too small for the PML")
+    X = partition.layers(n, b, gamma)
+    m = len(X)
+    # contiguous, disjoint, covering 1..n
+    assert X[0][0] == 1 and X[-1][1] == n
+    for a, c in zip(X, X[1:]):
+        assert c[0] == a[1] + 1
+    # every layer holds physical lines; interior layers exactly b of them
+    g = gamma - 1
+    for p, (s_p, e_p) in enumerate(X, start=1):
+        phi, psi = partition.physical(n, gamma, (s_p, e_p))
+        assert 1 <= psi - phi + 1 <= b
+        if 1 < p < m:
+            assert e_p - s_p + 1 == b
+    subs = partition.subproblems(n, b, gamma)
+    for s in subs["M"] + subs["R"] + subs["L"]:
+        assert 1 <= s.lo <= s.hi <= n
+        s_p, e_p = X[s.p - 1]
+        assert s.lo <= s_p and e_p <= s.hi       # the extended grid contains X_p
+    for s in subs["M"]:
+        assert s.L == (s.psi - s.phi + 1) + 2 * g
+    for s in subs["R"]:
+        assert s.lo - 1 == X[s.p - 2][1]
+    for s in subs["L"]:
+        assert s.hi + 1 == X[s.p][0]
+
+
+def test_single_layer_and_invalid():
+    X = partition.layers(30, 8, 12)     # n_phys = 8 <= b
+    assert X == [(1, 30)]
+    subs = partition.subproblems(30, 8, 12)
+    assert [(s.lo, s.hi) for s in subs["M"]] == [(1, 30)]
+    assert subs["R"] == [] and subs["L"] == []
+    for bad in [(20, 4, 12), (63, 0, 12), (63, 4, 1)]:
+        with pytest.raises(ValueError):
+            partition.layers(*bad)

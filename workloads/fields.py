@@ -1,0 +1,130 @@
+"""Velocity fields and sources for the synthetic Helmholtz workloads.
+
+The paper shows its velocity fields (a converging Gaussian lens, a Gaussian
+waveguide, a random field) only as figures and gives no formulas for them
+(Sections 3.2 and 4.2), so the fields below are explicit, seeded stand-ins:
+
+* constant:   c = 1
+* lens (2D):  c = (4/3) (1 - 0.5 exp(-32 |x - (1/2, 1/2)|^2))
+* lens (3D):  c = 1 + 0.3 exp(-32 |x - (1/2, 1/2, 1/2)|^2)
+* random:     i.i.d. N(0,1) samples on the grid (NumPy PCG64, fixed seed),
+              Gaussian-smoothed with standard deviation ``width`` grid cells
+              (reflecting boundary, truncated at 4 standard deviations), then
+              mapped affinely so that min -> 0.8 and max -> 1.2
+* source:     f = exp(-(4 omega / pi)^2 |x - x0|^2), a Gaussian point source
+              whose width shrinks with the wavelength.
+
+Nothing here knows about PML, layers or solvers.
+"""
+import math
+
+import numpy as np
+
+
+def grid_coords(n, d):
+    """Coordinates of the interior grid points, one array per axis, shape (n,)*d.
+
+    Point (i1, ..., id) sits at (i1*h, ..., id*h) with h = 1/(n+1)."""
+    h = 1.0 / (n + 1)
+    t = np.arange(1, n + 1, dtype=np.float64) * h
+    return np.meshgrid(*([t] * d), indexing="ij")
+
+
+def flat(a):
+    """Column-major flattening (first index fastest)."""
+    return np.asarray(a).reshape(-1, order="F")
+
+
+def velocity_constant(n, d, value=1.0):
+    return np.full((n,) * d, float(value))
+
+
+def velocity_lens2d(n):
+    x1, x2 = grid_coords(n, 2)
+    r2 = (x1 - 0.5) ** 2 + (x2 - 0.5) ** 2
+    return (4.0 / 3.0) * (1.0 - 0.5 * np.exp(-32.0 * r2))
+
+
+def velocity_lens3d(n):
+    x1, x2, x3 = grid_coords(n, 3)
+    r2 = (x1 - 0.5) ** 2 + (x2 - 0.5) ** 2 + (x3 - 0.5) ** 2
+    return 1.0 + 0.3 * np.exp(-32.0 * r2)
+
+
+def velocity_random(n, d, seed, width=8.0, lo=0.8, hi=1.2):
+    from scipy.ndimage import gaussian_filter
+
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n,) * d)
+    z = gaussian_filter(z, sigma=width, mode="reflect", truncate=4.0)
+    zmin, zmax = float(z.min()), float(z.max())
+    return lo + (hi - lo) * (z - zmin) / (zmax - zmin)
+
+
+def gaussian_source(n, d, omega, centre):
+    xs = grid_coords(n, d)
+    r2 = sum((x - c0) ** 2 for x, c0 in zip(xs, centre))
+    a = 4.0 * omega / math.pi
+    return np.exp(-(a * a) * r2)
+
+
+def seeded_centres(count, d, seed, lo=0.2, hi=0.8):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(count, d))
+
+
+# Named workloads.  Each entry: dimension, interior points per side, angular
+# frequency, PML width gamma (eta = gamma*h), PML constant C, lines per
+# interior layer b, number of right-hand sides, GMRES restart and tolerance.
+WORKLOADS = {
+    "2d_n63_const": dict(d=2, n=63, omega=2 * math.pi * 8, gamma=12, C=25.0, b=4,
+                         nrhs=1, restart=20, tol=1e-6, velocity="constant",
+                         centres="fixed"),
+    "2d_n511_lens": dict(d=2, n=511, omega=2 * math.pi * 64, gamma=12, C=25.0, b=4,
+                         nrhs=8, restart=20, tol=1e-6, velocity="lens",
+                         centres=2),
+    "2d_n1023_random": dict(d=2, n=1023, omega=2 * math.pi * 128, gamma=12, C=25.0,
+                            b=4, nrhs=64, restart=20, tol=1e-6, velocity="random",
+                            velocity_seed=3, centres=33),
+    "3d_n63_lens": dict(d=3, n=63, omega=2 * math.pi * 8, gamma=8, C=25.0, b=4,
+                        nrhs=16, restart=20, tol=1e-6, velocity="lens",
+                        centres=4),
+}
+
+
+def _velocity(spec):
+    d, n, kind = spec["d"], spec["n"], spec["velocity"]
+    if kind == "constant":
+        return velocity_constant(n, d)
+    if kind == "lens":
+        return velocity_lens2d(n) if d == 2 else velocity_lens3d(n)
+    if kind == "random":
+        return velocity_random(n, d, spec.get("velocity_seed", 3))
+    raise ValueError(f"unknown velocity family {kind!r}")
+
+
+def workload(name, n=None, nrhs=None):
+    """Materialise a named workload.
+
+    ``n`` and ``nrhs`` optionally shrink the workload (same recipe, smaller
+    grid or fewer right-hand sides); omega then scales with n so that the
+    number of points per wavelength is unchanged.
+
+    Returns a dict with keys d, n, omega, gamma, C, b, restart, tol,
+    c (float64, shape (n,)*d) and f (complex128, shape (nrhs, n**d), each row
+    column-major)."""
+    spec = dict(WORKLOADS[name])
+    if n is not None and n != spec["n"]:
+        spec["omega"] = spec["omega"] * (n + 1) / (spec["n"] + 1)
+        spec["n"] = n
+    if nrhs is not None:
+        spec["nrhs"] = nrhs
+    d, n = spec["d"], spec["n"]
+    c = _velocity(spec)
+    if spec["centres"] == "fixed":
+        cents = np.array([[0.5, 0.25]] * spec["nrhs"])
+    else:
+        cents = seeded_centres(spec["nrhs"], d, spec["centres"])
+    f = np.stack([flat(gaussian_source(n, d, spec["omega"], x0)) for x0 in cents])
+    spec.update(c=c, f=f.astype(np.complex128), centres_xy=cents, name=name)
+    return spec
