@@ -1,0 +1,177 @@
+/*
+ * asp.h -- C ABI of the additive sweeping preconditioner for the PML-truncated
+ * Helmholtz equation (F. Liu and L. Ying, "Additive Sweeping Preconditioner for
+ * the Helmholtz Equation"), running inside restarted GMRES on one AMD MI355X.
+ *
+ * The problem (Section 1, eq. (helm); Section 2 PML; eq. (2D) of Section 3.1,
+ * eq. (3D) of Section 4.1): on the unit square / cube with n interior grid points
+ * per side, h = 1/(n+1), find u with
+ *
+ *     sum_k s_k d_k (s_k d_k u) + omega^2 / c(x)^2 u = f,   u = 0 on the boundary,
+ *
+ * discretized by the centered scheme, with a PML of width eta = pml_eta*h and
+ * strength C on every side (the setting of the experiments, Sections 3.2 and
+ * 4.2).  The library works on the symmetric form of that system (each row
+ * divided by prod_k s_k(i_k), Section 3.1 remark 4), A u = f / prod_k s_k, which
+ * has the same solution u.
+ *
+ * Conventions shared by every entry point:
+ *   - Grid vectors are column-major (x1 fastest, Section 3.1), length N = n^dim.
+ *   - Complex vectors are interleaved (re, im) IEEE double, i.e. complex128.
+ *     A batch of nrhs vectors is stored vector after vector (nrhs * N entries).
+ *   - Vector arguments marked "device" are device pointers on the current HIP
+ *     device; the caller owns them and keeps them alive until the work that the
+ *     call enqueued on the plan's stream has finished.
+ *   - All device work is enqueued on the plan's stream (asp_opts.stream or
+ *     asp_set_stream).  Calls that return results to host memory (asp_gmres,
+ *     asp_layers, asp_tables, asp_info) synchronize that stream.
+ *   - No call aborts or throws: every failure is reported by the return code;
+ *     asp_last_error() gives a text description.  After ASP_ERR_DEVICE the plan
+ *     must only be destroyed.
+ *   - A plan is not thread safe; use one plan per host thread or lock it.
+ */
+#ifndef ASP_H
+#define ASP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct asp_plan asp_plan;
+
+typedef enum {
+    ASP_OK = 0,
+    ASP_ERR_ARG = 1,       /* invalid argument (sizes, NaN/non-positive c, bad pointers) */
+    ASP_ERR_OOM = 2,       /* device or host allocation failed */
+    ASP_ERR_STATE = 3,     /* call out of order (apply/gmres before factor) */
+    ASP_ERR_BREAKDOWN = 4, /* zero or non-finite pivot in a layer factorization */
+    ASP_ERR_NOCONV = 5,    /* GMRES reached maxit; iters/relres/u still filled in */
+    ASP_ERR_DEVICE = 6     /* a HIP runtime call failed */
+} asp_status;
+
+typedef enum {
+    ASP_PREC_FP64 = 0,     /* layer factors and layer solves in complex double */
+    ASP_PREC_FP32 = 1      /* layer factors and layer solves in complex float;
+                              GMRES, stencil and all grid vectors stay complex double */
+} asp_prec;
+
+typedef enum { ASP_SUB_M = 0, ASP_SUB_R = 1, ASP_SUB_L = 2 } asp_sub_kind;
+
+typedef struct {
+    double C;       /* PML strength (Section 2, "an appropriate positive constant"); default 25 */
+    int prec;       /* asp_prec; default ASP_PREC_FP64 */
+    void* stream;   /* hipStream_t for all device work; default 0 (the null stream) */
+    int host_only;  /* nonzero: build the partition and tables on the host only, touch no
+                       device; the plan then supports asp_layers, asp_tables, asp_info,
+                       asp_last_error and asp_destroy (other calls return ASP_ERR_STATE) */
+} asp_opts;
+
+typedef struct {
+    int dim, n, m;            /* dimension, points per side, number of layers (Section 2) */
+    int n_sub;                /* 3m - 2 auxiliary problems (Algorithms 1 and 3) */
+    int max_lines;            /* largest number of sweep lines of one auxiliary problem */
+    size_t factor_bytes;      /* device bytes held by the layer factors */
+    size_t workspace_bytes;   /* device bytes of the apply/GMRES workspaces now allocated */
+} asp_plan_info;
+
+/* Fill *opts with the defaults (C = 25, FP64, null stream, device plan). */
+void asp_default_opts(asp_opts* opts);
+
+/* asp_setup -- build a plan for one discretized problem (Section 1 eq. (helm),
+ * Section 2 PML and partition, Sections 3.1 / 4.1 auxiliary domains).
+ *   plan     out: new plan; owned by the caller, release with asp_destroy.  On
+ *            failure *plan is either NULL or a plan that only supports
+ *            asp_last_error and asp_destroy.
+ *   dim      2 or 3; the sweep axis is x2 (2D) or x3 (3D), the slowest index.
+ *   c        HOST pointer, n^dim velocities (column-major), finite and > 0;
+ *            copied, the caller may free it on return.
+ *   omega    angular frequency, > 0.
+ *   n        interior points per side; n - 2(pml_eta - 1) >= 1.
+ *   layer_b  grid lines per interior layer (Section 2, b), >= 1.
+ *   pml_eta  PML width in grid units (eta = pml_eta * h, Section 2), >= 2.
+ *   opts     NULL for defaults.
+ * Only host work and uploads of small tables; no factorization.
+ * Errors: ASP_ERR_ARG, ASP_ERR_OOM, ASP_ERR_DEVICE. */
+asp_status asp_setup(asp_plan** plan, int dim, const double* c, double omega, int n,
+                     int layer_b, int pml_eta, const asp_opts* opts);
+
+/* asp_factor -- Algorithm 1 (2D) / 3 (3D): factor every auxiliary problem
+ * H^M_q (q = 1..m), H^R_p (p = 2..m), H^L_p (p = 1..m-1).  The factors stay
+ * resident in device memory until asp_destroy.  Idempotent.
+ * Errors: ASP_ERR_OOM, ASP_ERR_BREAKDOWN (singular or non-finite pivot),
+ * ASP_ERR_DEVICE, ASP_ERR_ARG (dimension not supported by this build). */
+asp_status asp_factor(asp_plan* plan);
+
+/* asp_apply -- z = M^-1 r, Algorithm 2 (2D) / 4 (3D): the m M-solves, the
+ * right-going and left-going sweeps over the boundary values, and the sum.
+ *   r  device, nrhs * N complex128, symmetric-form residuals; read only.
+ *   z  device, nrhs * N complex128, written; must not alias r.
+ * Errors: ASP_ERR_STATE (not factored), ASP_ERR_ARG, ASP_ERR_OOM, ASP_ERR_DEVICE. */
+asp_status asp_apply(asp_plan* plan, const void* r, void* z, int nrhs);
+
+/* asp_matvec -- y = A x with the symmetric-form 5-point (2D) / 7-point (3D)
+ * PML operator of eq. (2D) / (3D), complex double.
+ *   x  device, nrhs * N complex128;  y  device, nrhs * N complex128, no alias.
+ * Errors: ASP_ERR_ARG, ASP_ERR_DEVICE. */
+asp_status asp_matvec(asp_plan* plan, const void* x, void* y, int nrhs);
+
+/* asp_gmres -- solve A u = f / prod s for nrhs independent right-hand sides
+ * with restarted GMRES (Sections 3.2, 4.2) right-preconditioned by asp_apply
+ * (flexible form, so a reduced-precision preconditioner is allowed).  x0 = 0;
+ * a right-hand side stops when its true relative residual
+ * ||f/prod s - A u|| / ||f/prod s|| is <= tol.
+ *   f       device, nrhs * N complex128, the PHYSICAL right-hand side f.
+ *   u       device, nrhs * N complex128, written with the solution.
+ *   tol     > 0;  restart >= 1;  maxit >= 1 (total Arnoldi steps per RHS).
+ *   iters   HOST, [nrhs]: Arnoldi steps (= preconditioner applies) per RHS.
+ *   relres  HOST, [nrhs]: final true relative residual per RHS.
+ * Factors the plan first if needed.  Workspaces ((2 restart + 3) * nrhs * N
+ * complex128) are allocated on first use and kept by the plan.
+ * Errors: ASP_ERR_NOCONV (some RHS not converged; outputs filled), ASP_ERR_ARG,
+ * ASP_ERR_OOM, ASP_ERR_BREAKDOWN, ASP_ERR_DEVICE. */
+asp_status asp_gmres(asp_plan* plan, const void* f, void* u, int nrhs, double tol,
+                     int restart, int maxit, int* iters, double* relres);
+
+/* asp_subsolve -- one auxiliary Green's operator on its own (Section 3.1,
+ * "Auxiliary Green's operators"): G~^M_p (kind ASP_SUB_M, p = 1..m),
+ * G~^R_p (ASP_SUB_R, p = 2..m) or G~^L_p (ASP_SUB_L, p = 1..m-1).
+ *   in   device; M: nrhs * (N_p) values y on X_p (column-major restriction);
+ *        R/L: nrhs * n^(dim-1) boundary values w.  complex128.
+ *   out  device; nrhs * N_p complex128: the solution restricted to X_p.
+ * N_p = n^(dim-1) * |X_p|.  Requires a factored plan.
+ * Errors: ASP_ERR_ARG, ASP_ERR_STATE, ASP_ERR_OOM, ASP_ERR_DEVICE. */
+asp_status asp_subsolve(asp_plan* plan, int kind, int p, const void* in, void* out, int nrhs);
+
+/* asp_layers -- the partition and auxiliary grids (Section 2; Sections 3.1 /
+ * 4.1 "Auxiliary domains"), 1-based grid lines along the sweep axis.
+ *   m       HOST out: number of layers.
+ *   layers  HOST, NULL or [m][2]: (first, last) line of X_p.
+ *   subs    HOST, NULL or [3m-2][6]: (kind, p, lo, hi, phi, psi) for M_1..M_m,
+ *           R_2..R_m, L_1..L_{m-1}: the lines lo..hi of the extended grid and
+ *           the zero region [phi, psi] of its sweep-axis PML profile. */
+asp_status asp_layers(const asp_plan* plan, int* m, int* layers, int* subs);
+
+/* asp_tables -- the PML tables the plan uses (Section 2; eq. (1D) evaluation
+ * at integer and half-integer points), for checking.
+ *   sub     -1: the boundary PML of one axis (lines 1..n);
+ *           0..3m-3: the sweep-axis profile of auxiliary problem `sub`
+ *           (order of asp_layers).
+ *   s_int   HOST [len][2] complex: s at the lines (len = n or the problem's lines).
+ *   s_half  HOST [len+1][2] complex: s at the half lines before/after them. */
+asp_status asp_tables(const asp_plan* plan, int sub, double* s_int, double* s_half);
+
+/* asp_info -- sizes and memory of the plan.  asp_set_stream -- change the stream
+ * used by later calls.  asp_destroy -- free everything (NULL is ignored).
+ * asp_last_error -- description of the last failure of this plan (never NULL). */
+asp_status asp_info(const asp_plan* plan, asp_plan_info* info);
+asp_status asp_set_stream(asp_plan* plan, void* stream);
+void asp_destroy(asp_plan* plan);
+const char* asp_last_error(const asp_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASP_H */

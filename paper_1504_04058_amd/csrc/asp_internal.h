@@ -1,0 +1,225 @@
+// Internal declarations of the asp library: plan layout, descriptors of the
+// auxiliary problems, complex arithmetic helpers and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/asp.h"
+
+// ---------------------------------------------------------------------------
+// complex arithmetic (interleaved re/im, the layout of complex128 / complex64)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) cplx {
+    T x, y;
+};
+using zd = cplx<double>;
+using zf = cplx<float>;
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T a, T b) { return cplx<T>{a, b}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator-(cplx<T> a) { return {-a.x, -a.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator*(T s, cplx<T> a) { return {s * a.x, s * a.y}; }
+// acc + a*b
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cfma(cplx<T> a, cplx<T> b, cplx<T> acc) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a)*b
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cfma_conj(cplx<T> a, cplx<T> b, cplx<T> acc) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+template <typename T>
+__host__ __device__ __forceinline__ T abs2(cplx<T> a) { return a.x * a.x + a.y * a.y; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cinv(cplx<T> a) {
+    T d = a.x * a.x + a.y * a.y;
+    return {a.x / d, -a.y / d};
+}
+template <typename To, typename Ti>
+__host__ __device__ __forceinline__ cplx<To> ccast(cplx<Ti> a) { return {(To)a.x, (To)a.y}; }
+
+// ---------------------------------------------------------------------------
+// auxiliary problems
+// ---------------------------------------------------------------------------
+// Block-tridiagonal layout of a 2D auxiliary problem on sweep lines lo..hi
+// (L lines): block k (k = i1 = 1..n) holds the L unknowns (i1 = k, lo..hi).
+// The factor stores, for every k, S_k^-1 (S_k the Schur complement of the
+// block recurrence) in a lane-major layout for the solve kernel: the 64 lanes
+// of a wavefront are split into 64/Q rows and Q column groups; lane l holds
+// entries (i = l / Q, j = (l % Q) + Q u), u = 0..U-1, stored at
+// [(k-1) * 64 U + u * 64 + l].
+struct SubDesc {
+    int kind;            // ASP_SUB_M / R / L
+    int p;               // layer index (1-based)
+    int lo, hi, L;       // sweep lines of the extended grid
+    int Q, U;            // solve lane split (Q column groups, U entries per lane)
+    int xs, xe;          // lines of X_p (output lines)
+    int src_line;        // R: last line of X_{p-1};  L: first line of X_{p+1};  M: 0
+    int phi, psi;        // zero region of the sweep-axis PML profile
+    long long fac_off;   // offset of block k = 1 in the factor buffer (complex entries)
+    long long tab_off;   // offset of this problem's tables in the table buffer
+};
+
+// Per-problem sweep-axis tables, complex double, at tab_off:
+//   [0 .. L]        s at the half lines lo-1/2 .. hi+1/2
+//   [L+1 .. 2L]     1 / (s h^2) at the lines lo .. hi
+//   [2L+1 .. 3L]    1 / s at the lines lo .. hi
+inline long long sub_table_len(int L) { return 3LL * L + 1; }
+
+// Global axis tables (the boundary PML, the same on every axis), complex double:
+//   sh[k]      s at t = k + 1/2, k = 0..n
+//   inv_sh2[i] 1 / (s(i+1) h^2), i = 0..n-1
+//   inv_s[i]   1 / s(i+1)
+struct AxisTables {
+    const zd* sh;
+    const zd* inv_sh2;
+    const zd* inv_s;
+};
+
+// ---------------------------------------------------------------------------
+// the plan
+// ---------------------------------------------------------------------------
+struct asp_plan {
+    // problem
+    int dim = 0, n = 0, b = 0, gamma = 0, g = 0, m = 0;
+    double omega = 0, h = 0, C = 25.0;
+    int prec = ASP_PREC_FP64;
+    hipStream_t stream = nullptr;
+    bool host_only = false;  // partition and tables only, no device state
+    long long N = 0, S = 0;  // unknowns, unknowns per line
+    std::vector<double> c;   // host copy of the velocity
+
+    // partition (1-based lines)
+    std::vector<std::array<int, 2>> X;
+    std::vector<SubDesc> subs;   // M_1..M_m, R_2..R_m, L_1..L_{m-1}
+    int idx_M(int q) const { return q - 1; }
+    int idx_R(int p) const { return m + (p - 2); }
+    int idx_L(int p) const { return m + (m - 1) + (p - 1); }
+    int max_L = 0, Q_M = 0, Q_RL = 0;
+
+    // host tables
+    std::vector<std::complex<double>> ax_int, ax_half;                   // s on lines, half lines
+    std::vector<std::vector<std::complex<double>>> sub_int, sub_half;    // per problem
+
+    // device data
+    double* d_ksq = nullptr;          // omega^2 / c^2, N
+    zd* d_axis = nullptr;             // sh | inv_sh2 | inv_s  (n+1 + n + n)
+    zd* d_subtab = nullptr;           // per-problem tables
+    SubDesc* d_desc = nullptr;
+    int* d_jobs = nullptr;            // [0..m): M jobs; then 2 per sweep step
+    void* d_fac = nullptr;
+    size_t fac_bytes = 0;
+    long long fac_elems = 0;
+    int* d_flag = nullptr;            // breakdown flag of the factorization
+    bool factored = false;
+
+    // apply workspaces (grown on demand)
+    int ws_rhs = 0;
+    zd* d_U = nullptr;      // u~_{p,p} on every layer
+    zd* d_AR = nullptr;     // u~_{p,1:p-1}
+    zd* d_CL = nullptr;     // u~_{p,p+1:m}
+    void* d_y = nullptr;    // forward-substitution scratch
+    long long y_per_wave = 0;
+    int* d_rhs_id = nullptr;   // identity map 0..ws_rhs-1
+    size_t ws_bytes = 0;
+
+    // GMRES workspaces
+    int kr_rhs = 0, kr_restart = 0;
+    zd* d_V = nullptr;      // (restart+1) * nrhs * N
+    zd* d_Z = nullptr;      // restart * nrhs * N
+    zd* d_b = nullptr;      // nrhs * N
+    zd* d_red = nullptr;    // reduction partials
+    zd* d_small = nullptr;  // small per-RHS arrays (h, norms, coefficients)
+    int* d_act = nullptr;   // active RHS list
+    size_t kr_bytes = 0;
+
+    std::string err;
+};
+
+// status helpers
+asp_status plan_fail(asp_plan* p, asp_status s, const std::string& msg);
+#define ASP_HIP(plan, call)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return plan_fail((plan), ASP_ERR_DEVICE,                                     \
+                             std::string(#call) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// launchers (stream-ordered; return hipSuccess or the launch error)
+// ---------------------------------------------------------------------------
+// y = A x (symmetric form), rhs indices act[0..nact) of the batch (nullptr: 0..nact-1)
+hipError_t launch_stencil(const asp_plan* P, const zd* x, zd* y, const int* act, int nact,
+                          hipStream_t st);
+// out = b - A x and per-RHS partial sums of |out|^2 into red (nblk per RHS)
+hipError_t launch_residual(const asp_plan* P, const zd* b, const zd* x, zd* out,
+                           const int* act, int nact, zd* red, int* nblk_out, hipStream_t st);
+
+// factorization of every auxiliary problem (2D)
+hipError_t launch_factor2d(const asp_plan* P, hipStream_t st);
+
+// batched layer solves for the jobs d_jobs[job0 .. job0+njobs) and the rhs
+// list act[0..nact):  M jobs read r and write U;  R/L jobs read their boundary
+// line from bU (+ bR / bL when not null) and write AR / CL.
+struct SolveIO {
+    const zd* r;
+    const zd* bU;
+    const zd* bR;
+    const zd* bL;
+    zd* U;
+    zd* AR;
+    zd* CL;
+};
+hipError_t launch_solve2d(const asp_plan* P, int job0, int njobs, bool rl, const int* act,
+                          int nact, const SolveIO& io, hipStream_t st);
+
+// host-side pieces shared by the entry points
+asp_status ensure_apply_ws(asp_plan* P, int nrhs);
+asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
+// z = U + AR (lines >= s_2) + CL (lines <= e_{m-1})
+hipError_t launch_combine(const asp_plan* P, const zd* U, const zd* AR, const zd* CL, zd* z,
+                          const int* act, int nact, hipStream_t st);
+
+// Krylov kernels (complex double)
+hipError_t launch_scale_by_s(const asp_plan* P, const zd* f, zd* b, int nrhs, hipStream_t st);
+// partial[r][blk][i] = sum conj(V_i[r]) w[r] for i in [i0, i1)
+int krylov_blocks(long long N);
+hipError_t launch_multidot(const zd* V, long long vstride, int i0, int i1, const zd* w,
+                           long long N, const int* act, int nact, zd* partial, hipStream_t st);
+// out[r][i] = sum_blk partial[r][blk][i], i < ni, fixed order
+hipError_t launch_reduce(const zd* partial, int nblk, int ni, const int* act, int nact,
+                         zd* out, int out_stride, hipStream_t st);
+// w[r] -= sum_i coef[r][i] V_i[r], i in [i0,i1); partial |w|^2 if norm_partial
+hipError_t launch_axpy_multi(const zd* V, long long vstride, int i0, int i1, const zd* coef,
+                             int coef_stride, zd* w, long long N, const int* act, int nact,
+                             zd* norm_partial, hipStream_t st);
+// v[r] = w[r] * scal[r]  (scal complex, per rhs slot)
+hipError_t launch_scale_vec(const zd* w, zd* v, const zd* scal, long long N, const int* act,
+                            int nact, hipStream_t st);

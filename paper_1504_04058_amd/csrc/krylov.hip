@@ -1,0 +1,286 @@
+// Complex-double kernels outside the layer solves: the symmetric-form PML
+// stencil of eq. (2D) / eq. (3D) and the batched vector operations of GMRES
+// (multi-dot products, multi-axpy with the norm of the result, scaling).
+// Every per-right-hand-side reduction runs in a fixed order that does not
+// depend on how many right-hand sides share the launch.
+#include "asp_internal.h"
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int CHUNK = 8;   // Krylov vectors per multi-dot / multi-axpy pass
+
+// y = A x for the symmetric form.  One thread per grid point; the stencil
+// coefficients are formed once from the 1D PML tables and omega^2/c^2 and used
+// for every right-hand side.
+//   coupling along axis a at the half line t+1/2:  s(t+1/2) / (h^2 prod_{b != a} s(i_b))
+//   diagonal: -(sum of the couplings) + omega^2 / (c^2 prod_b s(i_b))
+__global__ __launch_bounds__(BS) void stencil2d_kernel(const zd* __restrict__ x,
+                                                     zd* __restrict__ y,
+                                                     const int* __restrict__ act,
+                                                     AxisTables ax,
+                                                     const double* __restrict__ ksq, int n,
+                                                     long long N) {
+    const int i1 = blockIdx.x * BS + threadIdx.x;
+    const int i2 = blockIdx.y;
+    if (i1 >= n) return;
+    const int rhs = act ? act[blockIdx.z] : (int)blockIdx.z;
+    const long long idx = (long long)i2 * n + i1;
+    const zd ce = ax.sh[i1 + 1] * ax.inv_sh2[i2];
+    const zd cw = ax.sh[i1] * ax.inv_sh2[i2];
+    const zd cn = ax.sh[i2 + 1] * ax.inv_sh2[i1];
+    const zd cs = ax.sh[i2] * ax.inv_sh2[i1];
+    const zd dg = (ksq[idx] * ax.inv_s[i1]) * ax.inv_s[i2] - (ce + cw + cn + cs);
+    const zd* xr = x + (long long)rhs * N;
+    zd acc = dg * xr[idx];
+    if (i1 + 1 < n) acc = cfma(ce, xr[idx + 1], acc);
+    if (i1 > 0) acc = cfma(cw, xr[idx - 1], acc);
+    if (i2 + 1 < n) acc = cfma(cn, xr[idx + n], acc);
+    if (i2 > 0) acc = cfma(cs, xr[idx - n], acc);
+    y[(long long)rhs * N + idx] = acc;
+}
+
+__global__ __launch_bounds__(BS) void stencil3d_kernel(const zd* __restrict__ x,
+                                                     zd* __restrict__ y,
+                                                     const int* __restrict__ act,
+                                                     AxisTables ax,
+                                                     const double* __restrict__ ksq, int n,
+                                                     long long N, int nz) {
+    const int i1 = blockIdx.x * BS + threadIdx.x;
+    const int i2 = blockIdx.y;
+    const int i3 = blockIdx.z % nz;
+    if (i1 >= n) return;
+    const int slot = blockIdx.z / nz;
+    const int rhs = act ? act[slot] : slot;
+    const long long nn = (long long)n * n;
+    const long long idx = (long long)i3 * nn + (long long)i2 * n + i1;
+    const zd s23 = ax.inv_sh2[i2] * ax.inv_s[i3];   // 1/(h^2 s2 s3)
+    const zd s13 = ax.inv_sh2[i1] * ax.inv_s[i3];
+    const zd s12 = ax.inv_sh2[i1] * ax.inv_s[i2];
+    const zd c1p = ax.sh[i1 + 1] * s23, c1m = ax.sh[i1] * s23;
+    const zd c2p = ax.sh[i2 + 1] * s13, c2m = ax.sh[i2] * s13;
+    const zd c3p = ax.sh[i3 + 1] * s12, c3m = ax.sh[i3] * s12;
+    const zd dg = ((ksq[idx] * ax.inv_s[i1]) * ax.inv_s[i2]) * ax.inv_s[i3] -
+                  (c1p + c1m + c2p + c2m + c3p + c3m);
+    const zd* xr = x + (long long)rhs * N;
+    zd acc = dg * xr[idx];
+    if (i1 + 1 < n) acc = cfma(c1p, xr[idx + 1], acc);
+    if (i1 > 0) acc = cfma(c1m, xr[idx - 1], acc);
+    if (i2 + 1 < n) acc = cfma(c2p, xr[idx + n], acc);
+    if (i2 > 0) acc = cfma(c2m, xr[idx - n], acc);
+    if (i3 + 1 < n) acc = cfma(c3p, xr[idx + nn], acc);
+    if (i3 > 0) acc = cfma(c3m, xr[idx - nn], acc);
+    y[(long long)rhs * N + idx] = acc;
+}
+
+// b = f / prod_k s_k(i_k)
+__global__ void scale_by_s_kernel(const zd* __restrict__ f, zd* __restrict__ b, AxisTables ax,
+                                  int n, int dim, long long N) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N) return;
+    const long long o = (long long)blockIdx.y * N + idx;
+    long long t = idx;
+    zd sc = mk(1.0, 0.0);
+    for (int a = 0; a < dim; ++a) {
+        sc = sc * ax.inv_s[t % n];
+        t /= n;
+    }
+    b[o] = f[o] * sc;
+}
+
+// fixed-order tree reduction of BS values per lane slot
+template <int NV>
+__device__ __forceinline__ void block_reduce(zd (&v)[NV], zd* sh) {
+    const int t = threadIdx.x;
+    for (int k = 0; k < NV; ++k) sh[k * BS + t] = v[k];
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < NV; ++k) sh[k * BS + t] = sh[k * BS + t] + sh[k * BS + t + s];
+        __syncthreads();
+    }
+    for (int k = 0; k < NV; ++k) v[k] = sh[k * BS];
+}
+
+__global__ __launch_bounds__(BS) void multidot_kernel(const zd* __restrict__ V, long long vstride,
+                                                    int i0, int ni, const zd* __restrict__ w,
+                                                    long long N, const int* __restrict__ act,
+                                                    zd* __restrict__ partial) {
+    __shared__ zd sh[CHUNK * BS];
+    const int rhs = act ? act[blockIdx.y] : (int)blockIdx.y;
+    const int nblk = gridDim.x;
+    zd acc[CHUNK];
+    for (int k = 0; k < CHUNK; ++k) acc[k] = mk(0.0, 0.0);
+    const zd* wr = w + (long long)rhs * N;
+    for (long long idx = (long long)blockIdx.x * BS + threadIdx.x; idx < N;
+         idx += (long long)nblk * BS) {
+        const zd wv = wr[idx];
+#pragma unroll
+        for (int k = 0; k < CHUNK; ++k)
+            if (k < ni) acc[k] = cfma_conj(V[(long long)(i0 + k) * vstride + (long long)rhs * N + idx], wv, acc[k]);
+    }
+    block_reduce<CHUNK>(acc, sh);
+    if (threadIdx.x < CHUNK)
+        partial[((long long)rhs * nblk + blockIdx.x) * CHUNK + threadIdx.x] = acc[threadIdx.x];
+}
+
+__global__ __launch_bounds__(64) void reduce_kernel(const zd* __restrict__ partial, int nblk,
+                                                  int ni, const int* __restrict__ act,
+                                                  zd* __restrict__ out, int out_stride) {
+    __shared__ zd sh[CHUNK][64];
+    const int rhs = act ? act[blockIdx.x] : (int)blockIdx.x;
+    const int t = threadIdx.x;
+    zd acc[CHUNK];
+    for (int k = 0; k < CHUNK; ++k) acc[k] = mk(0.0, 0.0);
+    for (int b = t; b < nblk; b += 64)
+        for (int k = 0; k < CHUNK; ++k)
+            acc[k] = acc[k] + partial[((long long)rhs * nblk + b) * CHUNK + k];
+    for (int k = 0; k < CHUNK; ++k) sh[k][t] = acc[k];
+    __syncthreads();
+    for (int s = 32; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < CHUNK; ++k) sh[k][t] = sh[k][t] + sh[k][t + s];
+        __syncthreads();
+    }
+    if (t < ni) out[(long long)rhs * out_stride + t] = sh[t][0];
+}
+
+__global__ __launch_bounds__(BS) void axpy_multi_kernel(const zd* __restrict__ V, long long vstride,
+                                                      int i0, int ni, const zd* __restrict__ coef,
+                                                      int coef_stride, zd* __restrict__ w,
+                                                      long long N, const int* __restrict__ act,
+                                                      zd* __restrict__ norm_partial) {
+    __shared__ zd sh[BS];
+    const int rhs = act ? act[blockIdx.y] : (int)blockIdx.y;
+    const int nblk = gridDim.x;
+    zd cf[CHUNK];
+    for (int k = 0; k < CHUNK; ++k)
+        cf[k] = (k < ni) ? coef[(long long)rhs * coef_stride + i0 + k] : mk(0.0, 0.0);
+    zd* wr = w + (long long)rhs * N;
+    double nrm = 0.0;
+    for (long long idx = (long long)blockIdx.x * BS + threadIdx.x; idx < N;
+         idx += (long long)nblk * BS) {
+        zd v = wr[idx];
+#pragma unroll
+        for (int k = 0; k < CHUNK; ++k)   // a zero coefficient skips its vector (it may be unset)
+            if (k < ni && (cf[k].x != 0.0 || cf[k].y != 0.0))
+                v = v - cf[k] * V[(long long)(i0 + k) * vstride + (long long)rhs * N + idx];
+        wr[idx] = v;
+        nrm += abs2(v);
+    }
+    if (norm_partial) {
+        zd r[1] = {mk(nrm, 0.0)};
+        block_reduce<1>(r, sh);
+        if (threadIdx.x == 0)
+            norm_partial[((long long)rhs * nblk + blockIdx.x) * CHUNK] = r[0];
+    }
+}
+
+__global__ void scale_vec_kernel(const zd* __restrict__ w, zd* __restrict__ v,
+                                 const zd* __restrict__ scal, long long N,
+                                 const int* __restrict__ act) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N) return;
+    const int rhs = act ? act[blockIdx.y] : (int)blockIdx.y;
+    const long long o = (long long)rhs * N + idx;
+    v[o] = w[o] * scal[rhs];
+}
+
+// out = b - out (out holds A x), partial sums of |out|^2
+__global__ __launch_bounds__(BS) void residual_kernel(const zd* __restrict__ b, zd* __restrict__ out,
+                                                    long long N, const int* __restrict__ act,
+                                                    zd* __restrict__ norm_partial) {
+    __shared__ zd sh[BS];
+    const int rhs = act ? act[blockIdx.y] : (int)blockIdx.y;
+    const int nblk = gridDim.x;
+    double nrm = 0.0;
+    for (long long idx = (long long)blockIdx.x * BS + threadIdx.x; idx < N;
+         idx += (long long)nblk * BS) {
+        const long long o = (long long)rhs * N + idx;
+        const zd v = b[o] - out[o];
+        out[o] = v;
+        nrm += abs2(v);
+    }
+    zd r[1] = {mk(nrm, 0.0)};
+    block_reduce<1>(r, sh);
+    if (threadIdx.x == 0) norm_partial[((long long)rhs * nblk + blockIdx.x) * CHUNK] = r[0];
+}
+
+AxisTables axis_of(const asp_plan* P) {
+    return AxisTables{P->d_axis, P->d_axis + (P->n + 1), P->d_axis + (2 * P->n + 1)};
+}
+
+}  // namespace
+
+int krylov_blocks(long long N) {
+    long long b = (N + BS * 4 - 1) / (BS * 4);
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+hipError_t launch_stencil(const asp_plan* P, const zd* x, zd* y, const int* act, int nact,
+                          hipStream_t st) {
+    if (nact <= 0) return hipSuccess;
+    const int n = P->n;
+    if (P->dim == 2) {
+        dim3 grid((n + BS - 1) / BS, n, nact);
+        hipLaunchKernelGGL(stencil2d_kernel, grid, dim3(BS), 0, st, x, y, act, axis_of(P), P->d_ksq,
+                           n, P->N);
+    } else {
+        dim3 grid((n + BS - 1) / BS, n, (unsigned)n * nact);
+        hipLaunchKernelGGL(stencil3d_kernel, grid, dim3(BS), 0, st, x, y, act, axis_of(P), P->d_ksq,
+                           n, P->N, n);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const asp_plan* P, const zd* b, const zd* x, zd* out, const int* act,
+                           int nact, zd* red, int* nblk_out, hipStream_t st) {
+    hipError_t e = launch_stencil(P, x, out, act, nact, st);
+    if (e != hipSuccess) return e;
+    const int nblk = krylov_blocks(P->N);
+    *nblk_out = nblk;
+    hipLaunchKernelGGL(residual_kernel, dim3(nblk, nact), dim3(BS), 0, st, b, out, P->N, act, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_by_s(const asp_plan* P, const zd* f, zd* b, int nrhs, hipStream_t st) {
+    dim3 grid((unsigned)((P->N + 255) / 256), nrhs);
+    hipLaunchKernelGGL(scale_by_s_kernel, grid, dim3(256), 0, st, f, b, axis_of(P), P->n, P->dim,
+                       P->N);
+    return hipGetLastError();
+}
+
+hipError_t launch_multidot(const zd* V, long long vstride, int i0, int i1, const zd* w,
+                           long long N, const int* act, int nact, zd* partial, hipStream_t st) {
+    if (i1 - i0 > CHUNK || i1 <= i0) return hipErrorInvalidValue;   // one chunk per call
+    const int nblk = krylov_blocks(N);
+    hipLaunchKernelGGL(multidot_kernel, dim3(nblk, nact), dim3(BS), 0, st, V, vstride, i0,
+                       i1 - i0, w, N, act, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const zd* partial, int nblk, int ni, const int* act, int nact, zd* out,
+                         int out_stride, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(nact), dim3(64), 0, st, partial, nblk, ni, act, out,
+                       out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_multi(const zd* V, long long vstride, int i0, int i1, const zd* coef,
+                             int coef_stride, zd* w, long long N, const int* act, int nact,
+                             zd* norm_partial, hipStream_t st) {
+    if (i1 - i0 > CHUNK || i1 < i0) return hipErrorInvalidValue;
+    const int nblk = krylov_blocks(N);
+    hipLaunchKernelGGL(axpy_multi_kernel, dim3(nblk, nact), dim3(BS), 0, st, V, vstride, i0,
+                       i1 - i0, coef, coef_stride, w, N, act, norm_partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_vec(const zd* w, zd* v, const zd* scal, long long N, const int* act,
+                            int nact, hipStream_t st) {
+    dim3 grid((unsigned)((N + 255) / 256), nact);
+    hipLaunchKernelGGL(scale_vec_kernel, grid, dim3(256), 0, st, w, v, scal, N, act);
+    return hipGetLastError();
+}

@@ -1,0 +1,329 @@
+// Plan construction: argument checks, the layer partition and auxiliary grids
+// (Section 2; Section 3.1 / 4.1 "Auxiliary domains"), the PML tables
+// (Section 2 PML profile, evaluated at integer and half-integer lines as in
+// eq. (1D)), the descriptors of the 3m-2 auxiliary problems and their upload.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "asp_internal.h"
+
+asp_status plan_fail(asp_plan* p, asp_status s, const std::string& msg) {
+    if (p) p->err = msg;
+    return s;
+}
+
+namespace {
+
+using cd = std::complex<double>;
+
+// sigma at grid coordinate t for a profile vanishing on [phi, psi] (line units):
+// (C/eta) (dist/eta)^2 with eta = gamma h and dist the distance to [phi, psi].
+double sigma_at(double t, double phi, double psi, double C, int gamma, double h) {
+    double dist = 0.0;
+    if (t < phi) dist = phi - t;
+    if (t > psi) dist = t - psi;
+    const double eta = gamma * h;
+    const double r = dist * h / eta;
+    return (C / eta) * r * r;
+}
+
+cd s_at(double t, double phi, double psi, double C, int gamma, double h, double omega) {
+    return 1.0 / cd(1.0, sigma_at(t, phi, psi, C, gamma, h) / omega);
+}
+
+void fill_tables(int lo, int hi, double phi, double psi, const asp_plan* P,
+                 std::vector<cd>& s_int, std::vector<cd>& s_half) {
+    s_int.resize(hi - lo + 1);
+    s_half.resize(hi - lo + 2);
+    for (int t = lo; t <= hi; ++t) s_int[t - lo] = s_at(t, phi, psi, P->C, P->gamma, P->h, P->omega);
+    for (int k = 0; k <= hi - lo + 1; ++k)
+        s_half[k] = s_at(lo - 0.5 + k, phi, psi, P->C, P->gamma, P->h, P->omega);
+}
+
+template <typename T>
+asp_status upload(asp_plan* P, T** dst, const T* src, size_t count) {
+    if (hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T)) != hipSuccess)
+        return plan_fail(P, ASP_ERR_OOM, "hipMalloc of a plan table failed");
+    ASP_HIP(P, hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, P->stream));
+    return ASP_OK;
+}
+
+zd to_zd(cd v) { return mk(v.real(), v.imag()); }
+
+}  // namespace
+
+// Partition along the sweep axis (1-based lines).  g = gamma - 1 lines carry
+// sigma > 0 in each boundary PML; n_phys = n - 2g physical lines are cut into
+// m = ceil(n_phys / b) layers: X_1 = [1, g+b], X_p = [gamma+(p-1)b, gamma+pb-1],
+// X_m = [gamma+(m-1)b, n] (the last one holds the r <= b remaining physical lines).
+static void build_partition(asp_plan* P) {
+    const int n = P->n, b = P->b, gamma = P->gamma, g = P->g;
+    const int n_phys = n - 2 * g;
+    const int m = (n_phys + b - 1) / b;
+    P->X.clear();
+    if (m == 1) {
+        P->X.push_back({1, n});
+    } else {
+        P->X.push_back({1, g + b});
+        for (int p = 2; p < m; ++p) P->X.push_back({gamma + (p - 1) * b, gamma + p * b - 1});
+        P->X.push_back({gamma + (m - 1) * b, n});
+    }
+    P->m = m;
+}
+
+// Auxiliary problems: M_q on [phi_q - g, psi_q + g] with the sweep-axis PML
+// vanishing on X_q's physical part [phi_q, psi_q]; R_p on [s_p, psi_p + g]
+// vanishing on [s_p - 1, psi_p] (from the Dirichlet line of D^R_p); L_p on
+// [phi_p - g, e_p] vanishing on [phi_p, e_p + 1] (up to the Dirichlet line of D^L_p).
+static void build_subproblems(asp_plan* P) {
+    const int n = P->n, gamma = P->gamma, g = P->g, m = P->m;
+    P->subs.clear();
+    auto phys = [&](int p, int& phi, int& psi) {
+        phi = std::max(P->X[p - 1][0], gamma);
+        psi = std::min(P->X[p - 1][1], n + 1 - gamma);
+    };
+    for (int q = 1; q <= m; ++q) {
+        SubDesc d{};
+        int phi, psi;
+        phys(q, phi, psi);
+        d.kind = ASP_SUB_M; d.p = q; d.lo = phi - g; d.hi = psi + g; d.phi = phi; d.psi = psi;
+        d.src_line = 0;
+        P->subs.push_back(d);
+    }
+    for (int p = 2; p <= m; ++p) {
+        SubDesc d{};
+        int phi, psi;
+        phys(p, phi, psi);
+        d.kind = ASP_SUB_R; d.p = p; d.lo = P->X[p - 1][0]; d.hi = psi + g;
+        d.phi = P->X[p - 1][0] - 1; d.psi = psi;
+        d.src_line = P->X[p - 2][1];
+        P->subs.push_back(d);
+    }
+    for (int p = 1; p < m; ++p) {
+        SubDesc d{};
+        int phi, psi;
+        phys(p, phi, psi);
+        d.kind = ASP_SUB_L; d.p = p; d.lo = phi - g; d.hi = P->X[p - 1][1];
+        d.phi = phi; d.psi = P->X[p - 1][1] + 1;
+        d.src_line = P->X[p][0];
+        P->subs.push_back(d);
+    }
+    for (auto& d : P->subs) {
+        d.L = d.hi - d.lo + 1;
+        d.xs = P->X[d.p - 1][0];
+        d.xe = P->X[d.p - 1][1];
+    }
+}
+
+static int lanes_q(int L) { return L <= 16 ? 4 : 2; }
+
+extern "C" void asp_default_opts(asp_opts* o) {
+    if (!o) return;
+    o->C = 25.0;
+    o->prec = ASP_PREC_FP64;
+    o->stream = nullptr;
+    o->host_only = 0;
+}
+
+extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double omega, int n,
+                                int layer_b, int pml_eta, const asp_opts* opts) {
+    if (!out) return ASP_ERR_ARG;
+    *out = nullptr;
+    asp_plan* P = new (std::nothrow) asp_plan();
+    if (!P) return ASP_ERR_OOM;
+    asp_opts o;
+    asp_default_opts(&o);
+    if (opts) o = *opts;
+    auto fail = [&](asp_status s, const char* msg) {
+        // a plan is returned even on failure so that asp_last_error can explain it
+        P->err = msg;
+        *out = P;
+        return s;
+    };
+    if (dim != 2 && dim != 3) return fail(ASP_ERR_ARG, "dim must be 2 or 3");
+    if (!c) return fail(ASP_ERR_ARG, "c is NULL");
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(ASP_ERR_ARG, "omega must be finite and > 0");
+    if (pml_eta < 2) return fail(ASP_ERR_ARG, "pml_eta must be >= 2");
+    if (layer_b < 1) return fail(ASP_ERR_ARG, "layer_b must be >= 1");
+    if (n < 1 || n - 2 * (pml_eta - 1) < 1) return fail(ASP_ERR_ARG, "n too small for the PML");
+    if (!(o.C >= 0.0) || !std::isfinite(o.C)) return fail(ASP_ERR_ARG, "C must be finite and >= 0");
+    if (o.prec != ASP_PREC_FP64 && o.prec != ASP_PREC_FP32) return fail(ASP_ERR_ARG, "unknown precision");
+    if (dim == 3 && (long long)n * n * n > (1LL << 31)) return fail(ASP_ERR_ARG, "grid too large");
+
+    P->dim = dim;
+    P->n = n;
+    P->b = layer_b;
+    P->gamma = pml_eta;
+    P->g = pml_eta - 1;
+    P->omega = omega;
+    P->h = 1.0 / (n + 1);
+    P->C = o.C;
+    P->prec = o.prec;
+    P->stream = reinterpret_cast<hipStream_t>(o.stream);
+    P->S = (dim == 2) ? n : (long long)n * n;
+    P->N = P->S * n;
+    try {
+        P->c.assign(c, c + P->N);
+    } catch (...) {
+        return fail(ASP_ERR_OOM, "host allocation of c failed");
+    }
+    for (long long i = 0; i < P->N; ++i)
+        if (!(P->c[i] > 0.0) || !std::isfinite(P->c[i])) return fail(ASP_ERR_ARG, "c must be finite and > 0");
+
+    build_partition(P);
+    build_subproblems(P);
+
+    // PML tables: the boundary profile of one axis, and the sweep-axis profile
+    // of every auxiliary problem
+    fill_tables(1, n, P->gamma, n + 1 - P->gamma, P, P->ax_int, P->ax_half);
+    P->sub_int.resize(P->subs.size());
+    P->sub_half.resize(P->subs.size());
+    int maxL_M = 0, maxL_RL = 0;
+    for (size_t s = 0; s < P->subs.size(); ++s) {
+        const SubDesc& d = P->subs[s];
+        fill_tables(d.lo, d.hi, d.phi, d.psi, P, P->sub_int[s], P->sub_half[s]);
+        if (d.kind == ASP_SUB_M) maxL_M = std::max(maxL_M, d.L);
+        else maxL_RL = std::max(maxL_RL, d.L);
+    }
+    P->max_L = std::max(maxL_M, maxL_RL);
+    if (dim == 2 && P->max_L > 32) {
+        return fail(ASP_ERR_ARG, "2D auxiliary problems are limited to 32 sweep lines (b + 2(pml_eta-1) <= 32)");
+    }
+    P->Q_M = lanes_q(maxL_M);
+    P->Q_RL = lanes_q(maxL_RL > 0 ? maxL_RL : 1);
+    long long fac_off = 0, tab_off = 0;
+    for (auto& d : P->subs) {
+        d.Q = (d.kind == ASP_SUB_M) ? P->Q_M : P->Q_RL;
+        d.U = (d.L + d.Q - 1) / d.Q;
+        d.fac_off = fac_off;
+        d.tab_off = tab_off;
+        fac_off += (long long)n * 64 * d.U;
+        tab_off += sub_table_len(d.L);
+    }
+    P->fac_elems = fac_off;
+    P->fac_bytes = (size_t)fac_off * (P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd));
+
+    // device tables
+    const double h2 = P->h * P->h;
+    std::vector<zd> axis(3 * (size_t)n + 1);
+    for (int k = 0; k <= n; ++k) axis[k] = to_zd(P->ax_half[k]);
+    for (int i = 0; i < n; ++i) axis[n + 1 + i] = to_zd(1.0 / (P->ax_int[i] * h2));
+    for (int i = 0; i < n; ++i) axis[2 * n + 1 + i] = to_zd(1.0 / P->ax_int[i]);
+    std::vector<zd> subtab((size_t)tab_off);
+    for (size_t s = 0; s < P->subs.size(); ++s) {
+        const SubDesc& d = P->subs[s];
+        zd* t = subtab.data() + d.tab_off;
+        for (int k = 0; k <= d.L; ++k) t[k] = to_zd(P->sub_half[s][k]);
+        for (int j = 0; j < d.L; ++j) t[d.L + 1 + j] = to_zd(1.0 / (P->sub_int[s][j] * h2));
+        for (int j = 0; j < d.L; ++j) t[2 * d.L + 1 + j] = to_zd(1.0 / P->sub_int[s][j]);
+    }
+    std::vector<double> ksq((size_t)P->N);
+    for (long long i = 0; i < P->N; ++i) ksq[i] = (omega * omega) / (P->c[i] * P->c[i]);
+    P->host_only = (o.host_only != 0);
+    if (P->host_only) {
+        *out = P;
+        return ASP_OK;
+    }
+    // job lists: the m M-solves; the m-1 sweep steps (R_{t+1}, L_{m-t}); every problem once
+    std::vector<int> jobs;
+    for (int q = 1; q <= P->m; ++q) jobs.push_back(P->idx_M(q));
+    for (int t = 1; t < P->m; ++t) {
+        jobs.push_back(P->idx_R(t + 1));
+        jobs.push_back(P->idx_L(P->m - t));
+    }
+    for (size_t s = 0; s < P->subs.size(); ++s) jobs.push_back((int)s);
+
+    asp_status st;
+    if ((st = upload(P, &P->d_axis, axis.data(), axis.size())) != ASP_OK) return fail(st, P->err.c_str());
+    if ((st = upload(P, &P->d_subtab, subtab.data(), subtab.size())) != ASP_OK) return fail(st, P->err.c_str());
+    if ((st = upload(P, &P->d_ksq, ksq.data(), ksq.size())) != ASP_OK) return fail(st, P->err.c_str());
+    if ((st = upload(P, &P->d_desc, P->subs.data(), P->subs.size())) != ASP_OK) return fail(st, P->err.c_str());
+    if ((st = upload(P, &P->d_jobs, jobs.data(), jobs.size())) != ASP_OK) return fail(st, P->err.c_str());
+    if (hipMalloc(reinterpret_cast<void**>(&P->d_flag), sizeof(int)) != hipSuccess)
+        return fail(ASP_ERR_OOM, "hipMalloc failed");
+    // the host vectors above are released on return: finish the copies first
+    if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(ASP_ERR_DEVICE, "upload failed");
+    *out = P;
+    return ASP_OK;
+}
+
+extern "C" void asp_destroy(asp_plan* P) {
+    if (!P) return;
+    if (P->host_only) {
+        delete P;
+        return;
+    }
+    void* bufs[] = {P->d_ksq, P->d_axis, P->d_subtab, P->d_desc, P->d_jobs, P->d_fac, P->d_flag,
+                    P->d_U, P->d_AR, P->d_CL, P->d_y, P->d_rhs_id, P->d_V, P->d_Z, P->d_b,
+                    P->d_red, P->d_small, P->d_act};
+    (void)hipStreamSynchronize(P->stream);
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete P;
+}
+
+extern "C" const char* asp_last_error(const asp_plan* P) {
+    if (!P) return "no plan";
+    return P->err.c_str();
+}
+
+extern "C" asp_status asp_set_stream(asp_plan* P, void* stream) {
+    if (!P) return ASP_ERR_ARG;
+    P->stream = reinterpret_cast<hipStream_t>(stream);
+    return ASP_OK;
+}
+
+extern "C" asp_status asp_info(const asp_plan* P, asp_plan_info* info) {
+    if (!P || !info) return ASP_ERR_ARG;
+    info->dim = P->dim;
+    info->n = P->n;
+    info->m = P->m;
+    info->n_sub = (int)P->subs.size();
+    info->max_lines = P->max_L;
+    info->factor_bytes = P->factored ? P->fac_bytes : 0;
+    info->workspace_bytes = P->ws_bytes + P->kr_bytes;
+    return ASP_OK;
+}
+
+extern "C" asp_status asp_layers(const asp_plan* P, int* m, int* layers, int* subs) {
+    if (!P || !m) return ASP_ERR_ARG;
+    *m = P->m;
+    if (layers)
+        for (int p = 0; p < P->m; ++p) {
+            layers[2 * p] = P->X[p][0];
+            layers[2 * p + 1] = P->X[p][1];
+        }
+    if (subs)
+        for (size_t s = 0; s < P->subs.size(); ++s) {
+            const SubDesc& d = P->subs[s];
+            int* o = subs + 6 * s;
+            o[0] = d.kind; o[1] = d.p; o[2] = d.lo; o[3] = d.hi; o[4] = d.phi; o[5] = d.psi;
+        }
+    return ASP_OK;
+}
+
+extern "C" asp_status asp_tables(const asp_plan* P, int sub, double* s_int, double* s_half) {
+    if (!P || !s_int || !s_half) return ASP_ERR_ARG;
+    const std::vector<cd>* a;
+    const std::vector<cd>* b;
+    if (sub < 0) {
+        a = &P->ax_int;
+        b = &P->ax_half;
+    } else {
+        if (sub >= (int)P->subs.size()) return ASP_ERR_ARG;
+        a = &P->sub_int[sub];
+        b = &P->sub_half[sub];
+    }
+    for (size_t k = 0; k < a->size(); ++k) {
+        s_int[2 * k] = (*a)[k].real();
+        s_int[2 * k + 1] = (*a)[k].imag();
+    }
+    for (size_t k = 0; k < b->size(); ++k) {
+        s_half[2 * k] = (*b)[k].real();
+        s_half[2 * k + 1] = (*b)[k].imag();
+    }
+    return ASP_OK;
+}
