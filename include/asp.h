@@ -99,7 +99,8 @@ asp_status asp_setup(asp_plan** plan, int dim, const double* c, double omega, in
 
 /* asp_factor -- Algorithm 1 (2D) / 3 (3D): factor every auxiliary problem
  * H^M_q (q = 1..m), H^R_p (p = 2..m), H^L_p (p = 1..m-1).  The factors stay
- * resident in device memory until asp_destroy.  Idempotent.
+ * resident in device memory until asp_destroy.  Every call recomputes them
+ * (deterministically: the result is the same each time).
  * Errors: ASP_ERR_OOM, ASP_ERR_BREAKDOWN (singular or non-finite pivot),
  * ASP_ERR_DEVICE, ASP_ERR_ARG (dimension not supported by this build). */
 asp_status asp_factor(asp_plan* plan);
@@ -161,6 +162,30 @@ asp_status asp_layers(const asp_plan* plan, int* m, int* layers, int* subs);
  *   s_int   HOST [len][2] complex: s at the lines (len = n or the problem's lines).
  *   s_half  HOST [len+1][2] complex: s at the half lines before/after them. */
 asp_status asp_tables(const asp_plan* plan, int sub, double* s_int, double* s_half);
+
+/* Kernel classes for asp_timing_read. */
+typedef enum {
+    ASP_K_FACTOR = 0,     /* layer factorizations (Algorithm 1) */
+    ASP_K_TRANSFER = 1,   /* boundary-to-boundary maps of the auxiliary problems (setup) */
+    ASP_K_SOLVE_M = 2,    /* the M-solves G~^M_q of an apply */
+    ASP_K_SOLVE_RL = 3,   /* G~^R_p / G~^L_p solves of an apply */
+    ASP_K_SWEEP = 4,      /* the sequential boundary-value sweeps of an apply */
+    ASP_K_COMBINE = 5,    /* the final sum of an apply */
+    ASP_K_STENCIL = 6,    /* y = A x */
+    ASP_K_KRYLOV = 7,     /* Gram-Schmidt, norms, updates of GMRES */
+    ASP_K_COUNT = 8
+} asp_kernel_class;
+
+/* asp_timing_enable -- start (enable != 0, counters reset) or stop recording a
+ * HIP event pair around every kernel launch of the plan, on the plan's stream.
+ * asp_timing_read -- for one class: number of launches, summed device time
+ * (ms), and the algorithmic bytes moved and floating-point operations of
+ * those launches (the minimum traffic and work of the operation, counted by
+ * the host from the launch sizes).  Synchronizes the stream.  Any pointer may
+ * be NULL. */
+asp_status asp_timing_enable(asp_plan* plan, int enable);
+asp_status asp_timing_read(asp_plan* plan, int cls, int* launches, double* ms, double* bytes,
+                           double* flops);
 
 /* asp_info -- sizes and memory of the plan.  asp_set_stream -- change the stream
  * used by later calls.  asp_destroy -- free everything (NULL is ignored).

@@ -1,5 +1,5 @@
-// Factor (Algorithm 1), apply (Algorithm 2), the stencil and the single
-// auxiliary-operator hook of the C ABI.
+// Factor (Algorithm 1 and the boundary-to-boundary maps), apply (Algorithm 2),
+// the stencil, the single-operator hook and per-kernel timing of the C ABI.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,80 +21,259 @@ asp_status dev_alloc(asp_plan* P, T** p, size_t count) {
     return ASP_OK;
 }
 
-}  // namespace
+void dev_free(void* p) {
+    if (p) (void)hipFree(p);
+}
 
-// apply workspaces for right-hand-side ids 0..nrhs-1
-asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
-    if (nrhs <= P->ws_rhs) return ASP_OK;
+int groups_of(int nact) { return (nact + SOLVE_RW - 1) / SOLVE_RW; }
+
+// forward-substitution scratch for at least `waves` wavefronts
+asp_status ensure_y(asp_plan* P, long long waves) {
+    if (waves <= P->y_waves) return ASP_OK;
     ASP_HIP(P, hipStreamSynchronize(P->stream));
-    zd** vecs[] = {&P->d_U, &P->d_AR, &P->d_CL};
-    for (zd** v : vecs)
-        if (*v) {
-            (void)hipFree(*v);
-            *v = nullptr;
-        }
-    if (P->d_y) (void)hipFree(P->d_y);
-    if (P->d_rhs_id) (void)hipFree(P->d_rhs_id);
+    dev_free(P->d_y);
     P->d_y = nullptr;
-    P->d_rhs_id = nullptr;
-    P->ws_rhs = 0;
-    P->ws_bytes = 0;
-    const size_t vec = (size_t)nrhs * P->N;
-    for (zd** v : vecs)
-        if (dev_alloc(P, v, vec) != ASP_OK) return ASP_ERR_OOM;
-    // forward-substitution scratch: one n x L block column per (problem, rhs) wave
-    P->y_per_wave = (long long)P->n * P->max_L;
-    const long long waves = (long long)std::max(P->m, 2) * nrhs;
+    P->y_waves = 0;
+    P->y_per_wave = (long long)P->n * P->max_L * SOLVE_RW;
     char* y = nullptr;
     if (dev_alloc(P, &y, (size_t)waves * P->y_per_wave * elem_bytes(P)) != ASP_OK) return ASP_ERR_OOM;
     P->d_y = y;
-    std::vector<int> ids(nrhs);
-    for (int i = 0; i < nrhs; ++i) ids[i] = i;
-    if (dev_alloc(P, &P->d_rhs_id, ids.size()) != ASP_OK) return ASP_ERR_OOM;
-    ASP_HIP(P, hipMemcpyAsync(P->d_rhs_id, ids.data(), ids.size() * sizeof(int),
-                              hipMemcpyHostToDevice, P->stream));
-    ASP_HIP(P, hipStreamSynchronize(P->stream));
-    P->ws_rhs = nrhs;
-    P->ws_bytes = 3 * vec * sizeof(zd) + (size_t)waves * P->y_per_wave * elem_bytes(P);
+    P->y_waves = waves;
     return ASP_OK;
 }
 
-// z = M^-1 r for the right-hand-side ids act[0..nact) (device list) of batches
-// laid out with stride N; Algorithm 2.
+// algorithmic bytes and flops of a batch of layer solves: each factor entry
+// read once per launch, each grid value read and written once per right-hand side
+void solve_cost(const asp_plan* P, int sub0, int nsub, int nact, double io_vectors, double* bytes,
+                double* flops) {
+    double fb = 0, fl = 0;
+    for (int s = sub0; s < sub0 + nsub; ++s) {
+        fb += factor_bytes_of(P, P->subs[s]);
+        const double L = P->subs[s].L;
+        fl += 2.0 * P->n * L * L * 8.0;   // forward + backward, L^2 complex MACs per block
+    }
+    *bytes = fb + io_vectors * nact * (double)P->N * sizeof(zd);
+    *flops = fl * nact;
+}
+
+}  // namespace
+
+double factor_bytes_of(const asp_plan* P, const SubDesc& d) {
+    return (double)P->n * d.L * d.L * elem_bytes(P);
+}
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+KTimer::KTimer(asp_plan* p, int c, double bytes, double flops) : P(p), cls(c), on(p->timing) {
+    if (!on) return;
+    if (P->tpool_used + 2 > P->tpool.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                on = false;
+                return;
+            }
+            P->tpool.push_back(e);
+        }
+    }
+    hipEvent_t a = P->tpool[P->tpool_used++], b = P->tpool[P->tpool_used++];
+    P->tev[cls].push_back({a, b});
+    P->tbytes[cls] += bytes;
+    P->tflops[cls] += flops;
+    (void)hipEventRecord(a, P->stream);
+}
+
+void KTimer::end() {
+    if (on) (void)hipEventRecord(P->tev[cls].back().second, P->stream);
+    on = false;
+}
+
+extern "C" asp_status asp_timing_enable(asp_plan* P, int enable) {
+    if (!P) return ASP_ERR_ARG;
+    if (enable) {
+        ASP_HIP(P, hipStreamSynchronize(P->stream));
+        for (int c = 0; c < ASP_K_COUNT; ++c) {
+            P->tev[c].clear();
+            P->tbytes[c] = P->tflops[c] = 0;
+        }
+        P->tpool_used = 0;
+    }
+    P->timing = enable != 0;
+    return ASP_OK;
+}
+
+extern "C" asp_status asp_timing_read(asp_plan* P, int cls, int* launches, double* ms,
+                                      double* bytes, double* flops) {
+    if (!P || cls < 0 || cls >= ASP_K_COUNT) return ASP_ERR_ARG;
+    ASP_HIP(P, hipStreamSynchronize(P->stream));
+    double tot = 0;
+    for (auto& pr : P->tev[cls]) {
+        float t = 0;
+        ASP_HIP(P, hipEventElapsedTime(&t, pr.first, pr.second));
+        tot += t;
+    }
+    if (launches) *launches = (int)P->tev[cls].size();
+    if (ms) *ms = tot;
+    if (bytes) *bytes = P->tbytes[cls];
+    if (flops) *flops = P->tflops[cls];
+    return ASP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces
+// ---------------------------------------------------------------------------
+asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
+    if (nrhs <= P->ws_rhs) return ASP_OK;
+    ASP_HIP(P, hipStreamSynchronize(P->stream));
+    dev_free(P->d_U);
+    dev_free(P->d_W);
+    dev_free(P->d_stage);
+    P->d_U = P->d_W = P->d_stage = nullptr;
+    P->ws_rhs = 0;
+    P->ws_bytes = 0;
+    const size_t vec = (size_t)nrhs * P->N;
+    const size_t wlen = (size_t)std::max(2 * P->m - 2, 1) * nrhs * P->n;
+    if (dev_alloc(P, &P->d_U, vec) != ASP_OK) return ASP_ERR_OOM;
+    if (dev_alloc(P, &P->d_W, wlen) != ASP_OK) return ASP_ERR_OOM;
+    if (dev_alloc(P, &P->d_stage, vec) != ASP_OK) return ASP_ERR_OOM;
+    asp_status s = ensure_y(P, (long long)std::max(P->m, 2) * groups_of(std::max(nrhs, 64)));
+    if (s != ASP_OK) return s;
+    P->ws_rhs = nrhs;
+    P->ws_bytes = (2 * vec + wlen) * sizeof(zd) + (size_t)P->y_waves * P->y_per_wave * elem_bytes(P);
+    return ASP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// apply (Algorithm 2)
+// ---------------------------------------------------------------------------
+// z = M^-1 r for the right-hand-side ids act[0..nact) (device list, NULL for
+// 0..nact-1) of batches laid out with stride N.
 asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact) {
     hipStream_t st = P->stream;
     const int m = P->m;
-    // u~_{q,q} = G~^M_q f_q, q = 1..m, all at once
-    SolveIO io{r, nullptr, nullptr, nullptr, P->d_U, P->d_AR, P->d_CL};
-    ASP_HIP(P, launch_solve2d(P, 0, m, false, act, nact, io, st));
-    // step t: u~_{t+1,1:t} = G~^R_{t+1}(...) and u~_{m-t,m-t+1:m} = G~^L_{m-t}(...),
-    // their boundary data being the accumulated value on the adjacent line
-    // (u~_{p,p} plus the wave accumulated so far).
-    for (int t = 1; t < m; ++t) {
-        SolveIO s{nullptr, P->d_U, t > 1 ? P->d_AR : nullptr, t > 1 ? P->d_CL : nullptr,
-                  P->d_U, P->d_AR, P->d_CL};
-        ASP_HIP(P, launch_solve2d(P, m + 2 * (t - 1), 2, true, act, nact, s, st));
+    const int w_rhs = P->ws_rhs;
+    double by, fl;
+    // u~_{q,q} = G~^M_q f_q for q = 1..m, all at once
+    {
+        SolveLaunch L;
+        L.job0 = 0;
+        L.njobs = m;
+        L.act = act;
+        L.nact = nact;
+        L.in_mode = IN_GRID;
+        L.out_mode = OUT_GRID_STORE;
+        L.r = r;
+        L.out = (m == 1) ? z : P->d_U;
+        solve_cost(P, 0, m, nact, 2.0, &by, &fl);
+        KTimer t(P, ASP_K_SOLVE_M, by, fl);
+        ASP_HIP(P, launch_solve2d(P, L, st));
+        t.end();
     }
-    ASP_HIP(P, launch_combine(P, P->d_U, P->d_AR, P->d_CL, z, act, nact, st));
+    if (m == 1) return ASP_OK;
+    // the two sweeps: the boundary values u~^R_{p,1:p} and u~^L_{p,p:m}
+    // accumulated layer by layer (W rows hold the data entering R_p / L_p)
+    {
+        const long long rowR = (long long)P->wrow(P->idx_R(2)) * w_rhs * P->n;
+        const long long rowL = (long long)P->wrow(P->idx_L(m - 1)) * w_rhs * P->n;
+        KTimer t(P, ASP_K_SWEEP, 4.0 * nact * P->n * sizeof(zd), 0.0);
+        ASP_HIP(P, launch_sweep_seed(P, P->d_W, rowR, rowL, act, nact, st));
+        t.end();
+    }
+    const double esz = elem_bytes(P);
+    for (int s = 1; s <= m - 2; ++s) {
+        const double nn = (double)P->n * P->n;
+        KTimer t(P, ASP_K_SWEEP, 2.0 * nn * esz + 6.0 * nact * P->n * sizeof(zd),
+                 2.0 * nn * nact * 8.0);
+        ASP_HIP(P, launch_sweep_step(P, s, P->d_W, w_rhs, act, nact, st));
+        t.end();
+    }
+    // u~_p = u~_{p,1:p-1} + u~_{p,p} + u~_{p,p+1:m}: all R_p solves write z = U + a,
+    // then all L_p solves add c
+    for (int side = 0; side < 2; ++side) {
+        SolveLaunch L;
+        L.job0 = side == 0 ? P->idx_R(2) : P->idx_L(1);
+        L.njobs = m - 1;
+        L.rl = true;
+        L.act = act;
+        L.nact = nact;
+        L.in_mode = IN_BOUNDARY;
+        L.out_mode = side == 0 ? OUT_GRID_ADD_U : OUT_GRID_ACC;
+        L.W = P->d_W;
+        L.w_rhs = w_rhs;
+        L.out = z;
+        L.Ugrid = P->d_U;
+        solve_cost(P, L.job0, m - 1, nact, 2.0, &by, &fl);
+        KTimer t(P, ASP_K_SOLVE_RL, by, fl);
+        ASP_HIP(P, launch_solve2d(P, L, st));
+        t.end();
+    }
+    return ASP_OK;
+}
+
+// boundary-to-boundary maps: T^R_p = (G~^R_p e_c) on the last line of X_p and
+// T^L_p = (G~^L_p e_c) on the first line of X_p, c = 1..n, for 1 < p < m
+static asp_status compute_transfer(asp_plan* P) {
+    const int m = P->m;
+    if (m < 3) return ASP_OK;
+    const int per_job = groups_of(P->n);
+    const long long chunk = std::max<long long>(1, P->y_waves / per_job);
+    for (int side = 0; side < 2; ++side) {
+        const int first = side == 0 ? P->idx_R(2) : P->idx_L(2);
+        for (int j0 = 0; j0 < m - 2; j0 += (int)chunk) {
+            const int nj = (int)std::min<long long>(chunk, m - 2 - j0);
+            SolveLaunch L;
+            L.job0 = first + j0;
+            L.njobs = nj;
+            L.rl = true;
+            L.nact = P->n;
+            L.in_mode = IN_UNIT;
+            L.out_mode = OUT_LINE;
+            double by, fl;
+            solve_cost(P, L.job0, nj, P->n, 0.0, &by, &fl);
+            by += (double)nj * P->n * P->n * elem_bytes(P);
+            KTimer t(P, ASP_K_TRANSFER, by, fl);
+            ASP_HIP(P, launch_solve2d(P, L, P->stream));
+            t.end();
+        }
+    }
     return ASP_OK;
 }
 
 extern "C" asp_status asp_factor(asp_plan* P) {
     if (!P) return ASP_ERR_ARG;
-    if (P->factored) return ASP_OK;
     if (P->host_only) return plan_fail(P, ASP_ERR_STATE, "host-only plan");
     if (P->dim != 2) return plan_fail(P, ASP_ERR_ARG, "3D factorization is not available in this build");
+    P->factored = false;
     if (!P->d_fac) {
         char* f = nullptr;
         if (dev_alloc(P, &f, P->fac_bytes) != ASP_OK) return ASP_ERR_OOM;
         P->d_fac = f;
     }
+    if (!P->d_T && P->t_bytes > 0) {
+        char* t = nullptr;
+        if (dev_alloc(P, &t, P->t_bytes) != ASP_OK) return ASP_ERR_OOM;
+        P->d_T = t;
+    }
+    asp_status s = ensure_y(P, (long long)std::max(P->m, 2) * groups_of(64));
+    if (s != ASP_OK) return s;
     ASP_HIP(P, hipMemsetAsync(P->d_flag, 0, sizeof(int), P->stream));
-    ASP_HIP(P, launch_factor2d(P, P->stream));
+    {
+        double fb = 0, fl = 0;
+        for (const auto& d : P->subs) {
+            fb += factor_bytes_of(P, d);
+            fl += (double)P->n * ((double)d.L * d.L * d.L + 2.0 * d.L * d.L) * 8.0;
+        }
+        KTimer t(P, ASP_K_FACTOR, fb + P->N * sizeof(double), fl);
+        ASP_HIP(P, launch_factor2d(P, P->stream));
+        t.end();
+    }
     int flag = 0;
     ASP_HIP(P, hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, P->stream));
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     if (flag) return plan_fail(P, ASP_ERR_BREAKDOWN, "zero or non-finite pivot in a layer factorization");
+    if ((s = compute_transfer(P)) != ASP_OK) return s;
+    ASP_HIP(P, hipStreamSynchronize(P->stream));
     P->factored = true;
     return ASP_OK;
 }
@@ -113,8 +292,10 @@ extern "C" asp_status asp_matvec(asp_plan* P, const void* x, void* y, int nrhs) 
     if (!P) return ASP_ERR_ARG;
     if (!x || !y || nrhs < 1 || x == y) return plan_fail(P, ASP_ERR_ARG, "asp_matvec: bad arguments");
     if (P->host_only) return plan_fail(P, ASP_ERR_STATE, "host-only plan");
+    KTimer t(P, ASP_K_STENCIL, (double)nrhs * P->N * 32.0 + P->N * 8.0, 40.0 * nrhs * P->N);
     ASP_HIP(P, launch_stencil(P, static_cast<const zd*>(x), static_cast<zd*>(y), nullptr, nrhs,
                               P->stream));
+    t.end();
     return ASP_OK;
 }
 
@@ -135,19 +316,29 @@ extern "C" asp_status asp_subsolve(asp_plan* P, int kind, int p, const void* in,
     hipStream_t st = P->stream;
     const size_t row = sizeof(zd);
     const long long Np = P->S * (d.xe - d.xs + 1);
-    zd* tin = P->d_AR;    // grid-shaped staging of the input
-    zd* tout = P->d_CL;   // grid-shaped output
+    SolveLaunch L;
+    L.job0 = idx;
+    L.njobs = 1;
+    L.rl = kind != ASP_SUB_M;
+    L.nact = nrhs;
+    L.out_mode = OUT_GRID_STORE;
+    L.out = P->d_stage;
     if (kind == ASP_SUB_M) {
-        ASP_HIP(P, hipMemcpy2DAsync(tin + (long long)(d.xs - 1) * P->S, P->N * row, in, Np * row,
-                                    Np * row, nrhs, hipMemcpyDeviceToDevice, st));
+        // y on X_p into a grid-shaped copy of the input
+        ASP_HIP(P, hipMemcpy2DAsync(P->d_U + (long long)(d.xs - 1) * P->S, P->N * row, in,
+                                    Np * row, Np * row, nrhs, hipMemcpyDeviceToDevice, st));
+        L.in_mode = IN_GRID;
+        L.r = P->d_U;
     } else {
-        ASP_HIP(P, hipMemcpy2DAsync(tin + (long long)(d.src_line - 1) * P->S, P->N * row, in,
-                                    P->S * row, P->S * row, nrhs, hipMemcpyDeviceToDevice, st));
+        // w into this problem's boundary-data rows
+        ASP_HIP(P, hipMemcpyAsync(P->d_W + (long long)d.wrow * P->ws_rhs * P->n, in,
+                                  (size_t)nrhs * P->n * row, hipMemcpyDeviceToDevice, st));
+        L.in_mode = IN_BOUNDARY;
+        L.W = P->d_W;
+        L.w_rhs = P->ws_rhs;
     }
-    const int job0 = m + 2 * (m - 1) + idx;   // the "every problem once" job list
-    SolveIO io{tin, tin, nullptr, nullptr, tout, tout, tout};
-    ASP_HIP(P, launch_solve2d(P, job0, 1, kind != ASP_SUB_M, nullptr, nrhs, io, st));
-    ASP_HIP(P, hipMemcpy2DAsync(out, Np * row, tout + (long long)(d.xs - 1) * P->S, P->N * row,
-                                Np * row, nrhs, hipMemcpyDeviceToDevice, st));
+    ASP_HIP(P, launch_solve2d(P, L, st));
+    ASP_HIP(P, hipMemcpy2DAsync(out, Np * row, P->d_stage + (long long)(d.xs - 1) * P->S,
+                                P->N * row, Np * row, nrhs, hipMemcpyDeviceToDevice, st));
     return ASP_OK;
 }

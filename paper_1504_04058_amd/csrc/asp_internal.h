@@ -84,7 +84,14 @@ struct SubDesc {
     int phi, psi;        // zero region of the sweep-axis PML profile
     long long fac_off;   // offset of block k = 1 in the factor buffer (complex entries)
     long long tab_off;   // offset of this problem's tables in the table buffer
+    long long tr_off;    // offset of its boundary-to-boundary map (R_p, L_p with 1 < p < m), else -1
+    int wrow;            // R/L problems: row of its boundary data in the sweep buffer, else -1
 };
+
+// solve launch modes
+enum { IN_GRID = 0, IN_BOUNDARY = 1, IN_UNIT = 2 };
+enum { OUT_GRID_STORE = 0, OUT_GRID_ADD_U = 1, OUT_GRID_ACC = 2, OUT_LINE = 3 };
+constexpr int SOLVE_RW = 4;   // right-hand sides per wavefront in the layer solves
 
 // Per-problem sweep-axis tables, complex double, at tab_off:
 //   [0 .. L]        s at the half lines lo-1/2 .. hi+1/2
@@ -122,6 +129,7 @@ struct asp_plan {
     int idx_R(int p) const { return m + (p - 2); }
     int idx_L(int p) const { return m + (m - 1) + (p - 1); }
     int max_L = 0, Q_M = 0, Q_RL = 0;
+    int wrow(int sub) const { return subs[sub].wrow; }
 
     // host tables
     std::vector<std::complex<double>> ax_int, ax_half;                   // s on lines, half lines
@@ -139,15 +147,28 @@ struct asp_plan {
     int* d_flag = nullptr;            // breakdown flag of the factorization
     bool factored = false;
 
+    // boundary-to-boundary maps T^R_p, T^L_p (1 < p < m), n x n each, column-major
+    void* d_T = nullptr;
+    size_t t_bytes = 0;
+    long long t_elems = 0;
+
     // apply workspaces (grown on demand)
     int ws_rhs = 0;
     zd* d_U = nullptr;      // u~_{p,p} on every layer
-    zd* d_AR = nullptr;     // u~_{p,1:p-1}
-    zd* d_CL = nullptr;     // u~_{p,p+1:m}
+    zd* d_W = nullptr;      // sweep boundary data: (2m-2) rows x ws_rhs x n
+    zd* d_stage = nullptr;  // grid-shaped staging for asp_subsolve
     void* d_y = nullptr;    // forward-substitution scratch
     long long y_per_wave = 0;
-    int* d_rhs_id = nullptr;   // identity map 0..ws_rhs-1
+    long long y_waves = 0;
     size_t ws_bytes = 0;
+
+    // per-kernel-class timing (asp_timing_enable / asp_timing_read)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[ASP_K_COUNT];
+    std::vector<hipEvent_t> tpool;
+    size_t tpool_used = 0;
+    double tbytes[ASP_K_COUNT] = {0};
+    double tflops[ASP_K_COUNT] = {0};
 
     // GMRES workspaces
     int kr_rhs = 0, kr_restart = 0;
@@ -185,27 +206,42 @@ hipError_t launch_residual(const asp_plan* P, const zd* b, const zd* x, zd* out,
 // factorization of every auxiliary problem (2D)
 hipError_t launch_factor2d(const asp_plan* P, hipStream_t st);
 
-// batched layer solves for the jobs d_jobs[job0 .. job0+njobs) and the rhs
-// list act[0..nact):  M jobs read r and write U;  R/L jobs read their boundary
-// line from bU (+ bR / bL when not null) and write AR / CL.
-struct SolveIO {
-    const zd* r;
-    const zd* bU;
-    const zd* bR;
-    const zd* bL;
-    zd* U;
-    zd* AR;
-    zd* CL;
+// batched layer solves for the jobs d_jobs[job0 .. job0+njobs) (all M, or all
+// R/L: rl) and the right-hand sides act[0..nact) (NULL: 0..nact-1).
+//   in_mode   IN_GRID: data = r on X_p;  IN_BOUNDARY: boundary data from the
+//             W rows of the problems;  IN_UNIT: unit data at i1 = slot + 1
+//             (nact virtual right-hand sides, act ignored)
+//   out_mode  OUT_GRID_STORE: out = v on X_p;  OUT_GRID_ADD_U: out = U + v;
+//             OUT_GRID_ACC: out += v (out = U + v for L_1);  OUT_LINE: the
+//             outgoing boundary line into the problem's transfer map
+struct SolveLaunch {
+    int job0 = 0, njobs = 0;
+    bool rl = false;
+    const int* act = nullptr;
+    int nact = 0;
+    int in_mode = IN_GRID, out_mode = OUT_GRID_STORE;
+    const zd* r = nullptr;
+    const zd* W = nullptr;
+    int w_rhs = 0;
+    zd* out = nullptr;
+    const zd* Ugrid = nullptr;
 };
-hipError_t launch_solve2d(const asp_plan* P, int job0, int njobs, bool rl, const int* act,
-                          int nact, const SolveIO& io, hipStream_t st);
+hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st);
+// the W rows that start the two sweeps (from u~_{1,1} and u~_{m,m} in U)
+hipError_t launch_sweep_seed(const asp_plan* P, zd* W, long long outR, long long outL,
+                             const int* act, int nact, hipStream_t st);
+// sweep step t = 1..m-2 (both directions)
+hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const int* act, int nact,
+                             hipStream_t st);
 
-// host-side pieces shared by the entry points
-asp_status ensure_apply_ws(asp_plan* P, int nrhs);
-asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
-// z = U + AR (lines >= s_2) + CL (lines <= e_{m-1})
-hipError_t launch_combine(const asp_plan* P, const zd* U, const zd* AR, const zd* CL, zd* z,
-                          const int* act, int nact, hipStream_t st);
+// timing of one launch: constructed before the launch, end() after it
+struct KTimer {
+    asp_plan* P;
+    int cls;
+    bool on;
+    KTimer(asp_plan* p, int c, double bytes, double flops);
+    void end();
+};
 
 // Krylov kernels (complex double)
 hipError_t launch_scale_by_s(const asp_plan* P, const zd* f, zd* b, int nrhs, hipStream_t st);
@@ -223,3 +259,17 @@ hipError_t launch_axpy_multi(const zd* V, long long vstride, int i0, int i1, con
 // v[r] = w[r] * scal[r]  (scal complex, per rhs slot)
 hipError_t launch_scale_vec(const zd* w, zd* v, const zd* scal, long long N, const int* act,
                             int nact, hipStream_t st);
+
+// host-side pieces shared by the entry points
+asp_status ensure_apply_ws(asp_plan* P, int nrhs);
+asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
+// algorithmic bytes of one auxiliary problem's factor (n dense L x L blocks)
+double factor_bytes_of(const asp_plan* P, const SubDesc& d);
+
+// a launch bracketed by a KTimer of class cls
+#define ASP_TIMED(plan, cls, bytes, flops, call)        \
+    do {                                                \
+        KTimer t_((plan), (cls), (bytes), (flops));     \
+        ASP_HIP((plan), call);                          \
+        t_.end();                                       \
+    } while (0)

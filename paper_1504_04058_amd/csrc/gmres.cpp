@@ -110,13 +110,14 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
     };
     // |v[r]|^2 for the active list into small[r][OFF_NRM]
     auto norms = [&](const zd* v, int nact) -> asp_status {
-        ASP_HIP(P, launch_multidot(v, 0, 0, 1, v, N, P->d_act, nact, P->d_red, st));
+        ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * nact * N, 8.0 * nact * N,
+                  launch_multidot(v, 0, 0, 1, v, N, P->d_act, nact, P->d_red, st));
         ASP_HIP(P, launch_reduce(P->d_red, nblk, 1, P->d_act, nact, small + OFF_NRM, SMALL, st));
         return ASP_OK;
     };
 
     // b = f / prod s (symmetric form), x0 = 0
-    ASP_HIP(P, launch_scale_by_s(P, f, b, nrhs, st));
+    ASP_TIMED(P, ASP_K_KRYLOV, 32.0 * nrhs * N, 6.0 * nrhs * N, launch_scale_by_s(P, f, b, nrhs, st));
     ASP_HIP(P, hipMemsetAsync(x, 0, (size_t)nrhs * N * sizeof(zd), st));
     std::vector<RhsState> R(nrhs);
     act.resize(nrhs);
@@ -150,11 +151,13 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
             for (int r : act) hsmall[(size_t)nrhs * SMALL + r] = mk(1.0, 0.0);
             ASP_HIP(P, hipMemcpyAsync(scal, hsmall.data() + (size_t)nrhs * SMALL, nrhs * sizeof(zd),
                                       hipMemcpyHostToDevice, st));
-            ASP_HIP(P, launch_scale_vec(b, V, scal, N, P->d_act, na, st));  // V_0 = b (x0 = 0)
+            ASP_TIMED(P, ASP_K_KRYLOV, 32.0 * na * N, 0.0,
+                      launch_scale_vec(b, V, scal, N, P->d_act, na, st));  // V_0 = b (x0 = 0)
             if ((s = norms(V, na)) != ASP_OK) return s;
         } else {
             int nb = 0;
-            ASP_HIP(P, launch_residual(P, b, x, V, P->d_act, na, P->d_red, &nb, st));
+            ASP_TIMED(P, ASP_K_STENCIL, 64.0 * na * N + 8.0 * N, 48.0 * na * N,
+                      launch_residual(P, b, x, V, P->d_act, na, P->d_red, &nb, st));
             ASP_HIP(P, launch_reduce(P->d_red, nb, 1, P->d_act, na, small + OFF_NRM, SMALL, st));
         }
         first = false;
@@ -181,7 +184,8 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
         if ((s = upload_act(cyc)) != ASP_OK) return s;
         ASP_HIP(P, hipMemcpyAsync(scal, hsmall.data() + (size_t)nrhs * SMALL, nrhs * sizeof(zd),
                                   hipMemcpyHostToDevice, st));
-        ASP_HIP(P, launch_scale_vec(V, V, scal, N, P->d_act, (int)cyc.size(), st));
+        ASP_TIMED(P, ASP_K_KRYLOV, 32.0 * cyc.size() * N, 6.0 * cyc.size() * N,
+                  launch_scale_vec(V, V, scal, N, P->d_act, (int)cyc.size(), st));
 
         std::vector<int> inner = cyc;
         for (int j = 0; j < restart && !inner.empty(); ++j) {
@@ -192,21 +196,24 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
             zd* w = V + (long long)(j + 1) * vs;
             // z_j = M^-1 v_j ; w = A z_j
             if ((s = apply_internal(P, vj, zj, P->d_act, ni)) != ASP_OK) return s;
-            ASP_HIP(P, launch_stencil(P, zj, w, P->d_act, ni, st));
+            ASP_TIMED(P, ASP_K_STENCIL, 32.0 * ni * N + 8.0 * N, 40.0 * ni * N,
+                      launch_stencil(P, zj, w, P->d_act, ni, st));
             // two passes of classical Gram-Schmidt against v_0..v_j
             for (int pass = 0; pass < 2; ++pass) {
                 const int off = pass == 0 ? OFF_H1 : OFF_H2;
                 for (int c0 = 0; c0 <= j; c0 += CH) {
                     const int c1 = std::min(j + 1, c0 + CH);
-                    ASP_HIP(P, launch_multidot(V, vs, c0, c1, w, N, P->d_act, ni, P->d_red, st));
+                    ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * (c1 - c0 + 1) * ni * N, 8.0 * (c1 - c0) * ni * N,
+                              launch_multidot(V, vs, c0, c1, w, N, P->d_act, ni, P->d_red, st));
                     ASP_HIP(P, launch_reduce(P->d_red, nblk, c1 - c0, P->d_act, ni, small + off + c0,
                                              SMALL, st));
                 }
                 for (int c0 = 0; c0 <= j; c0 += CH) {
                     const int c1 = std::min(j + 1, c0 + CH);
                     const bool last = (pass == 1) && (c1 == j + 1);
-                    ASP_HIP(P, launch_axpy_multi(V, vs, c0, c1, small + off, SMALL, w, N, P->d_act, ni,
-                                                 last ? P->d_red : nullptr, st));
+                    ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * (c1 - c0 + 2) * ni * N, 8.0 * (c1 - c0) * ni * N,
+                              launch_axpy_multi(V, vs, c0, c1, small + off, SMALL, w, N, P->d_act,
+                                                ni, last ? P->d_red : nullptr, st));
                 }
             }
             ASP_HIP(P, launch_reduce(P->d_red, nblk, 1, P->d_act, ni, small + OFF_NRM, SMALL, st));
@@ -259,7 +266,8 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
                 if ((s = upload_act(inner)) != ASP_OK) return s;
                 ASP_HIP(P, hipMemcpyAsync(scal, hsmall.data() + (size_t)nrhs * SMALL, nrhs * sizeof(zd),
                                           hipMemcpyHostToDevice, st));
-                ASP_HIP(P, launch_scale_vec(w, w, scal, N, P->d_act, (int)inner.size(), st));
+                ASP_TIMED(P, ASP_K_KRYLOV, 32.0 * inner.size() * N, 6.0 * inner.size() * N,
+                          launch_scale_vec(w, w, scal, N, P->d_act, (int)inner.size(), st));
             }
         }
         // x += Z y with R y = g (upper triangular), per right-hand side
@@ -283,8 +291,10 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
         if ((s = upload_act(cyc)) != ASP_OK) return s;
         for (int c0 = 0; c0 < kmax; c0 += CH) {
             const int c1 = std::min(kmax, c0 + CH);
-            ASP_HIP(P, launch_axpy_multi(Z, vs, c0, c1, small + OFF_COEF, SMALL, x, N, P->d_act,
-                                         (int)cyc.size(), nullptr, st));
+            ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * (c1 - c0 + 2) * cyc.size() * N,
+                      8.0 * (c1 - c0) * cyc.size() * N,
+                      launch_axpy_multi(Z, vs, c0, c1, small + OFF_COEF, SMALL, x, N, P->d_act,
+                                        (int)cyc.size(), nullptr, st));
         }
     }
     ASP_HIP(P, hipStreamSynchronize(st));

@@ -194,17 +194,29 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     }
     P->Q_M = lanes_q(maxL_M);
     P->Q_RL = lanes_q(maxL_RL > 0 ? maxL_RL : 1);
-    long long fac_off = 0, tab_off = 0;
-    for (auto& d : P->subs) {
+    long long fac_off = 0, tab_off = 0, tr_off = 0;
+    for (size_t s = 0; s < P->subs.size(); ++s) {
+        SubDesc& d = P->subs[s];
         d.Q = (d.kind == ASP_SUB_M) ? P->Q_M : P->Q_RL;
         d.U = (d.L + d.Q - 1) / d.Q;
         d.fac_off = fac_off;
         d.tab_off = tab_off;
         fac_off += (long long)n * 64 * d.U;
         tab_off += sub_table_len(d.L);
+        d.wrow = (d.kind == ASP_SUB_M) ? -1 : (int)s - P->m;
+        // the sweeps step through R_p and L_p for 1 < p < m with their dense maps
+        if (d.kind != ASP_SUB_M && d.p > 1 && d.p < P->m) {
+            d.tr_off = tr_off;
+            tr_off += (long long)n * n;
+        } else {
+            d.tr_off = -1;
+        }
     }
+    const size_t esz = (P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd));
     P->fac_elems = fac_off;
-    P->fac_bytes = (size_t)fac_off * (P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd));
+    P->fac_bytes = (size_t)fac_off * esz;
+    P->t_elems = tr_off;
+    P->t_bytes = (size_t)tr_off * esz;
 
     // device tables
     const double h2 = P->h * P->h;
@@ -227,14 +239,10 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
         *out = P;
         return ASP_OK;
     }
-    // job lists: the m M-solves; the m-1 sweep steps (R_{t+1}, L_{m-t}); every problem once
-    std::vector<int> jobs;
-    for (int q = 1; q <= P->m; ++q) jobs.push_back(P->idx_M(q));
-    for (int t = 1; t < P->m; ++t) {
-        jobs.push_back(P->idx_R(t + 1));
-        jobs.push_back(P->idx_L(P->m - t));
-    }
-    for (size_t s = 0; s < P->subs.size(); ++s) jobs.push_back((int)s);
+    // job list: every auxiliary problem once (M_1..M_m, R_2..R_m, L_1..L_{m-1});
+    // a launch takes a contiguous range of it
+    std::vector<int> jobs(P->subs.size());
+    for (size_t s = 0; s < P->subs.size(); ++s) jobs[s] = (int)s;
 
     asp_status st;
     if ((st = upload(P, &P->d_axis, axis.data(), axis.size())) != ASP_OK) return fail(st, P->err.c_str());
@@ -257,11 +265,12 @@ extern "C" void asp_destroy(asp_plan* P) {
         return;
     }
     void* bufs[] = {P->d_ksq, P->d_axis, P->d_subtab, P->d_desc, P->d_jobs, P->d_fac, P->d_flag,
-                    P->d_U, P->d_AR, P->d_CL, P->d_y, P->d_rhs_id, P->d_V, P->d_Z, P->d_b,
+                    P->d_T, P->d_U, P->d_W, P->d_stage, P->d_y, P->d_V, P->d_Z, P->d_b,
                     P->d_red, P->d_small, P->d_act};
     (void)hipStreamSynchronize(P->stream);
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (hipEvent_t e : P->tpool) (void)hipEventDestroy(e);
     delete P;
 }
 
