@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the additive sweeping preconditioner inside GMRES on one MI355X.
+
+A step is one pass of the whole hot path over one batch: factor every
+auxiliary problem (Algorithm 1, plus the boundary maps of the sweeps) and solve
+all right-hand sides of the batch with right-preconditioned GMRES(20) to
+relative residual 1e-6 (Algorithm 2 applies, stencil applies, Arnoldi).  The
+velocity field and sources are synthetic (workloads.py recipes) and resident
+in device memory before the timed region.
+
+Prints one JSON line (see the keys below).  `roofline` describes the kernel
+class with the largest device time inside the timed region, measured with HIP
+events around every launch by the library itself (asp_timing_*).
+`cpu_baseline` times the CPU FP64 oracle on a bounded sample of the same
+workload and scales it to solves/s.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Helmholtz solves/s to relres 1e-6 (2D n=1023, 3D n=63); PC-apply GB/s, MFMA%"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # vector FP32 / FP64
+
+KCLASS = ["factor", "transfer", "solve_m", "solve_rl", "sweep", "combine", "stencil", "krylov"]
+# classes whose launches are VALU-bound (arithmetic intensity above the ridge)
+ALU_CLASSES = {"factor", "transfer", "solve_m", "solve_rl", "sweep"}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="2d_n1023_random")
+    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--restart", type=int, default=None)
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=64,
+                    help="auxiliary problems of each kind the oracle factors and solves")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, iters_mean, sample):
+    """Time the CPU FP64 oracle on a bounded sample of the workload and scale it
+    to solves/s of the whole batch: factor `sample` auxiliary problems of each
+    kind (M, R, L) and apply each G~ once; the full setup and one full
+    preconditioner apply are the per-kind means times the counts; one solve of
+    one right-hand side is then iters x (apply + stencil + Arnoldi), with the
+    setup shared by the batch."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import partition
+    from oracle.operator import Problem
+    from oracle.subproblem import Subproblem
+
+    with threadpool_limits(limits=1):
+        t_all = time.perf_counter()
+        P = Problem.from_workload(w)
+        X = partition.layers(P.n, P.b, P.gamma)
+        subs = partition.subproblems(P.n, P.b, P.gamma)
+        rng = np.random.default_rng(0)
+        per_kind = {}
+        for kind in ("M", "R", "L"):
+            lst = subs[kind]
+            picks = np.linspace(0, len(lst) - 1, min(sample, len(lst))).round().astype(int)
+            tf = ts = 0.0
+            for idx in sorted(set(picks.tolist())):
+                s = lst[idx]
+                t0 = time.perf_counter()
+                sp = Subproblem(P, s, X[s.p - 1])
+                t1 = time.perf_counter()
+                k = P.S * (X[s.p - 1][1] - X[s.p - 1][0] + 1) if kind == "M" else P.S
+                data = rng.standard_normal(k) + 1j * rng.standard_normal(k)
+                sp.G(data)
+                t2 = time.perf_counter()
+                tf += t1 - t0
+                ts += t2 - t1
+            cnt = len(set(picks.tolist()))
+            per_kind[kind] = (tf / cnt, ts / cnt, len(lst))
+        A = P.A()
+        v = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
+        t0 = time.perf_counter()
+        A @ v
+        t_mv = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        hv = np.vdot(v, v)
+        t_dot = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        v = v - hv * v
+        t_axpy = time.perf_counter() - t0
+        sample_s = time.perf_counter() - t_all
+    setup = sum(f * c for f, _, c in per_kind.values())
+    apply_ = sum(s * c for _, s, c in per_kind.values())
+    # modified Gram-Schmidt at Arnoldi step j: j+1 dot products and updates
+    arnoldi = (iters_mean / 2 + 1) * (t_dot + t_axpy)
+    per_rhs = iters_mean * (apply_ + t_mv + arnoldi)
+    nrhs = w["f"].shape[0]
+    total = setup + nrhs * per_rhs
+    return {
+        "value": nrhs / total,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{sum(min(sample, c) for _, _, c in per_kind.values())} of "
+                   f"{sum(c for _, _, c in per_kind.values())} auxiliary problems factored and "
+                   f"solved once (banded LU, 1 thread) + one stencil apply on the full grid, "
+                   f"{sample_s:.1f} s; scaled by the problem counts and {iters_mean:.2f} GMRES "
+                   f"iterations per RHS (the GPU run's mean), setup shared by {nrhs} RHS"),
+        "setup_s": setup,
+        "apply_s": apply_,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1504_04058_amd import asp
+
+    w = workloads.workload(args.workload)
+    restart = args.restart or w["restart"]
+    tol = args.tol or w["tol"]
+    prec = asp.ASP_PREC_FP32 if args.prec == "fp32" else asp.ASP_PREC_FP64
+    nrhs = w["f"].shape[0]
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(w["f"]).to(dev)
+    u = torch.empty_like(f)
+    plan = asp.Plan(w["d"], w["c"], w["omega"], w["n"], w["b"], w["gamma"], C=w["C"], prec=prec)
+    h = plan.handle
+    L = asp.lib()
+
+    def step():
+        asp.asp_factor(h)
+        return asp.asp_gmres(h, f, u, nrhs, tol, restart, 400)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    L.asp_timing_enable(h, 1)
+    t_factor = t_gmres = 0.0
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        asp.asp_factor(h)
+        b = time.perf_counter()
+        results.append(asp.asp_gmres(h, f, u, nrhs, tol, restart, 400))
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        t_factor += b - a
+        t_gmres += c - b
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.asp_timing_enable(h, 0)
+
+    import ctypes
+    kstats = {}
+    for ci, name in enumerate(KCLASS):
+        nl, ms, by, fl = ctypes.c_int(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        L.asp_timing_read(h, ci, ctypes.byref(nl), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl))
+        if nl.value:
+            kstats[name] = {"launches": nl.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+    st, iters, relres = results[-1]
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = nrhs / (ms_step / 1e3)
+
+    dom = max(kstats, key=lambda k: kstats[k]["ms"])
+    ks = kstats[dom]
+    avg_ms = ks["ms"] / ks["launches"]
+    if dom in ALU_CLASSES:
+        achieved = ks["flops"] / (ks["ms"] / 1e3) / 1e12
+        peak = PEAK_TFLOPS[args.prec]
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None}
+    else:
+        achieved = ks["bytes"] / (ks["ms"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof.update({"kernel_class": dom, "avg_launch_ms": avg_ms, "launches": ks["launches"],
+                 "per_launch_bytes": ks["bytes"] / ks["launches"],
+                 "per_launch_flops": ks["flops"] / ks["launches"]})
+
+    pc_ms = sum(kstats.get(k, {"ms": 0})["ms"] for k in ("solve_m", "solve_rl", "sweep"))
+    pc_bytes = sum(kstats.get(k, {"bytes": 0})["bytes"] for k in ("solve_m", "solve_rl", "sweep"))
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": w["d"], "n": w["n"], "nrhs": nrhs,
+                   "omega_over_2pi": round(w["omega"] / (2 * math.pi), 6), "pml_eta": w["gamma"],
+                   "C": w["C"], "layer_b": w["b"], "restart": restart, "tol": tol,
+                   "layer_precision": args.prec, "krylov_precision": "fp64"},
+        "warm_solves_per_s": nrhs / (t_gmres / args.steps),
+        "factor_ms": t_factor * 1e3 / args.steps,
+        "gmres_ms": t_gmres * 1e3 / args.steps,
+        "iters": {"min": int(iters.min()), "max": int(iters.max()), "mean": float(iters.mean())},
+        "max_relres": float(relres.max()),
+        "status": asp.STATUS_NAMES.get(st, st),
+        "pc_apply_gbps": pc_bytes / (pc_ms / 1e3) / 1e9 if pc_ms else None,
+        "kernels": kstats,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    plan.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, float(iters.mean()), args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

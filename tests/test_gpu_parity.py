@@ -73,6 +73,19 @@ def test_stencil(n, gamma, b):
         assert rel(y[r], A @ x[r]) < 1e-13
 
 
+@pytest.mark.parametrize("n,gamma", [(15, 3), (31, 8)])
+def test_stencil_3d(n, gamma):
+    rng = np.random.default_rng(n)
+    c = 1.0 + 0.3 * rng.random((n, n, n))
+    P = Problem(3, n, 2 * math.pi * 3, gamma, 25.0, 4, c)
+    x = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
+    with asp.Plan(3, c, P.omega, n, 4, gamma) as plan:
+        y = host(plan.matvec(dev(x)))
+    A = P.A()
+    for r in range(2):
+        assert rel(y[r], A @ x[r]) < 1e-13
+
+
 @pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 2e-4)])
 @pytest.mark.parametrize("n,gamma,b", CASES)
 def test_auxiliary_operators(n, gamma, b, prec, tol):
