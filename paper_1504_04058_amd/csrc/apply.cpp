@@ -25,7 +25,10 @@ void dev_free(void* p) {
     if (p) (void)hipFree(p);
 }
 
-int groups_of(int nact) { return (nact + SOLVE_RW - 1) / SOLVE_RW; }
+// workgroups of a solve launch per problem over `nact` right-hand sides
+int groups_of(int nact) {
+    return (nact + solve_rhs_per_block() - 1) / solve_rhs_per_block();
+}
 
 // forward-substitution scratch for at least `waves` wavefronts
 asp_status ensure_y(asp_plan* P, long long waves) {
@@ -34,7 +37,7 @@ asp_status ensure_y(asp_plan* P, long long waves) {
     dev_free(P->d_y);
     P->d_y = nullptr;
     P->y_waves = 0;
-    P->y_per_wave = (long long)P->n * P->max_L * SOLVE_RW;
+    P->y_per_wave = (long long)P->n * 32 * solve_rhs_per_block();   // n blocks x LR rows x rhs
     char* y = nullptr;
     if (dev_alloc(P, &y, (size_t)waves * P->y_per_wave * elem_bytes(P)) != ASP_OK) return ASP_ERR_OOM;
     P->d_y = y;
@@ -129,7 +132,10 @@ asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
     dev_free(P->d_U);
     dev_free(P->d_W);
     dev_free(P->d_stage);
+    dev_free(P->d_wt);
     P->d_U = P->d_W = P->d_stage = nullptr;
+    P->d_wt = nullptr;
+    P->wt_elems = 0;
     P->ws_rhs = 0;
     P->ws_bytes = 0;
     const size_t vec = (size_t)nrhs * P->N;
@@ -137,6 +143,13 @@ asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
     if (dev_alloc(P, &P->d_U, vec) != ASP_OK) return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_W, wlen) != ASP_OK) return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_stage, vec) != ASP_OK) return ASP_ERR_OOM;
+    {
+        const long long we = sweep_wt_len(P, nrhs);
+        char* wt = nullptr;
+        if (dev_alloc(P, &wt, (size_t)we * elem_bytes(P)) != ASP_OK) return ASP_ERR_OOM;
+        P->d_wt = wt;
+        P->wt_elems = we;
+    }
     asp_status s = ensure_y(P, (long long)std::max(P->m, 2) * groups_of(std::max(nrhs, 64)));
     if (s != ASP_OK) return s;
     P->ws_rhs = nrhs;

@@ -70,15 +70,15 @@ __host__ __device__ __forceinline__ cplx<To> ccast(cplx<Ti> a) { return {(To)a.x
 // Block-tridiagonal layout of a 2D auxiliary problem on sweep lines lo..hi
 // (L lines): block k (k = i1 = 1..n) holds the L unknowns (i1 = k, lo..hi).
 // The factor stores, for every k, S_k^-1 (S_k the Schur complement of the
-// block recurrence) in a lane-major layout for the solve kernel: the 64 lanes
-// of a wavefront are split into 64/Q rows and Q column groups; lane l holds
-// entries (i = l / Q, j = (l % Q) + Q u), u = 0..U-1, stored at
-// [(k-1) * 64 U + u * 64 + l].
+// block recurrence) column-major with leading dimension LR >= L (rows past L
+// zero): entry (i, j) of block k at [(k-1) L LR + j LR + i], so that the LR
+// lanes holding the rows of one solve load each column coalesced.
 struct SubDesc {
     int kind;            // ASP_SUB_M / R / L
     int p;               // layer index (1-based)
     int lo, hi, L;       // sweep lines of the extended grid
-    int Q, U;            // solve lane split (Q column groups, U entries per lane)
+    int LR;              // rows per solve wavefront (16 or 32, >= L)
+    int pad_;
     int xs, xe;          // lines of X_p (output lines)
     int src_line;        // R: last line of X_{p-1};  L: first line of X_{p+1};  M: 0
     int phi, psi;        // zero region of the sweep-axis PML profile
@@ -91,7 +91,6 @@ struct SubDesc {
 // solve launch modes
 enum { IN_GRID = 0, IN_BOUNDARY = 1, IN_UNIT = 2 };
 enum { OUT_GRID_STORE = 0, OUT_GRID_ADD_U = 1, OUT_GRID_ACC = 2, OUT_LINE = 3 };
-constexpr int SOLVE_RW = 4;   // right-hand sides per wavefront in the layer solves
 
 // Per-problem sweep-axis tables, complex double, at tab_off:
 //   [0 .. L]        s at the half lines lo-1/2 .. hi+1/2
@@ -128,7 +127,7 @@ struct asp_plan {
     int idx_M(int q) const { return q - 1; }
     int idx_R(int p) const { return m + (p - 2); }
     int idx_L(int p) const { return m + (m - 1) + (p - 1); }
-    int max_L = 0, Q_M = 0, Q_RL = 0;
+    int max_L = 0, LR_M = 0, LR_RL = 0;
     int wrow(int sub) const { return subs[sub].wrow; }
 
     // host tables
@@ -157,6 +156,8 @@ struct asp_plan {
     zd* d_U = nullptr;      // u~_{p,p} on every layer
     zd* d_W = nullptr;      // sweep boundary data: (2m-2) rows x ws_rhs x n
     zd* d_stage = nullptr;  // grid-shaped staging for asp_subsolve
+    void* d_wt = nullptr;   // sweep data, transposed, in the factor precision
+    long long wt_elems = 0;
     void* d_y = nullptr;    // forward-substitution scratch
     long long y_per_wave = 0;
     long long y_waves = 0;
@@ -227,10 +228,13 @@ struct SolveLaunch {
     const zd* Ugrid = nullptr;
 };
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st);
+// right-hand sides handled by one solve workgroup
+int solve_rhs_per_block();
 // the W rows that start the two sweeps (from u~_{1,1} and u~_{m,m} in U)
 hipError_t launch_sweep_seed(const asp_plan* P, zd* W, long long outR, long long outL,
                              const int* act, int nact, hipStream_t st);
-// sweep step t = 1..m-2 (both directions)
+// sweep step t = 1..m-2 (both directions); workspace sizes for nrhs right-hand sides
+int sweep_wt_len(const asp_plan* P, int nrhs);
 hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const int* act, int nact,
                              hipStream_t st);
 

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
     const zd* ssh = tab;                // s at half lines lo-1/2 .. hi+1/2
     const zd* sinv2 = tab + L + 1;      // 1/(s h^2) on lines lo..hi
     const zd* sinv = tab + 2 * L + 1;   // 1/s on lines lo..hi
-    const int Q = d.Q, U = d.U;
+    const int LR = d.LR;
     bool bad = false;
 
     for (int k = 1; k <= n; ++k) {
@@ -121,13 +121,11 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
             }
             __syncthreads();
         }
-        // store S_k^-1 in the solve layout
-        cplx<TS>* out = fac + d.fac_off + (long long)(k - 1) * WAVE * U;
-        const int i = lane / Q, q = lane % Q;
-        for (int u = 0; u < U; ++u) {
-            const int j = q + Q * u;
-            const zd v = (i < L && j < L) ? M[i][j] : mk(0.0, 0.0);
-            out[u * WAVE + lane] = ccast<TS>(v);
+        // store S_k^-1 column-major with leading dimension LR (rows past L zero)
+        cplx<TS>* out = fac + d.fac_off + (long long)(k - 1) * L * LR;
+        for (int e = lane; e < L * LR; e += WAVE) {
+            const int j = e / LR, i = e % LR;
+            out[e] = ccast<TS>(i < L ? M[i][j] : mk(0.0, 0.0));
         }
         __syncthreads();
     }
@@ -135,12 +133,12 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
 }
 
 // ----------------------------------------------------------------------------
-// batched solves: one wavefront per (auxiliary problem, group of RW
-// right-hand sides).  Lane l = Q*i + q owns row i of the L x L block products
-// and the column group q (columns q, q+Q, ...); a step is a row-split
-// matrix-vector product for each of the RW right-hand sides followed by a
-// reduction over the Q lanes of a row.  The vectors entering each step go
-// through LDS, stored per column group so each lane reads them contiguously.
+// batched solves: one 256-thread workgroup per (auxiliary problem, chunk of up
+// to 64 right-hand sides).  The L x L block S_k^-1 of each step is loaded once
+// into an LDS ring (the load of block k+1 overlaps step k) and shared by all
+// right-hand sides of the chunk.  Thread (row group, rhs group) owns RG rows x
+// RPT right-hand sides: it forms their step inputs, writes them to LDS, and
+// after the barrier computes their rows of the block product.
 // ----------------------------------------------------------------------------
 struct SolveArgs {
     const SubDesc* desc;
@@ -159,187 +157,215 @@ struct SolveArgs {
     const zd* Ugrid;     // OUT_GRID_ADD_U / ACC: u~_{p,p}
     void* Tout;          // OUT_LINE: boundary-to-boundary maps
     void* y;
-    long long y_per_wave;
+    long long y_per_wave;   // scratch entries per workgroup
     int n;
     long long N;
 };
 
-template <typename T>
-__device__ __forceinline__ cplx<T> shfl_xor_c(cplx<T> v, int m) {
-    return mk<T>(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
-}
+constexpr int SB = 256;        // threads per solve workgroup
+constexpr int SRB = 64;        // right-hand sides per solve workgroup
 
-template <typename T, int Q, int RW>
-__global__ __launch_bounds__(WAVE) void solve2d_kernel(SolveArgs a) {
-    constexpr int R = WAVE / Q;
-    constexpr int UMAX = R / Q;
-    __shared__ cplx<T> tb[2][RW][Q][UMAX];
+template <int LR> struct SolveShape;
+template <> struct SolveShape<32> { static constexpr int RG = 4, RPT = 2; };
+template <> struct SolveShape<16> { static constexpr int RG = 2, RPT = 2; };
 
-    // XCD-aware order: consecutive work items (the right-hand-side groups of one
-    // problem) land on the same XCD so that they share its L2 copy of the factor.
-    const int ngroups = (a.nact + RW - 1) / RW;
-    const int B = a.njobs * ngroups;
+template <typename T, int LR>
+__global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
+    constexpr int RG = SolveShape<LR>::RG, RPT = SolveShape<LR>::RPT;
+    constexpr int NRG = LR / RG;            // row groups
+    constexpr int NCG = SB / NRG;           // right-hand-side groups
+    static_assert(NCG * RPT == SRB, "shape covers the chunk");
+    constexpr int FMAX = 32 * LR;           // largest block (L <= 32)
+    constexpr int FPT = (FMAX + SB - 1) / SB;
+    __shared__ cplx<T> Fs[2][FMAX];
+    __shared__ cplx<T> tb[2][SRB][LR];
+
+    // XCD-aware order: the chunks of one problem are consecutive work items
+    const int nchunk = (a.nact + SRB - 1) / SRB;
+    const int B = a.njobs * nchunk;
     const int per = (B + 7) / 8;
     const int w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
     if (w >= B) return;
-    const int jl = w / ngroups, grp = w % ngroups;
+    const int jl = w / nchunk, ch = w % nchunk;
     const SubDesc d = a.desc[a.jobs[jl]];
-    const int L = d.L, U = d.U, n = a.n;
+    const int L = d.L, n = a.n;
     const long long N = a.N;
-    const int lane = threadIdx.x, i = lane / Q, q = lane % Q;
-    const bool rowlane = (q == 0) && (i < L);
+    const int tid = threadIdx.x;
+    const int rgi = tid % NRG, cgi = tid / NRG;
+    const int i0 = rgi * RG;
     const cplx<T>* F = reinterpret_cast<const cplx<T>*>(a.fac) + d.fac_off;
+    const int FS = L * LR;                  // entries of one block
     const zd* tab = a.subtab + d.tab_off;
-    const cplx<T> sinv2_i = (i < L) ? ccast<T>(tab[L + 1 + i]) : mk<T>(0, 0);
     cplx<T>* Y = reinterpret_cast<cplx<T>*>(a.y) + (long long)w * a.y_per_wave;
 
-    int slot[RW];
-    bool valid[RW];
-    long long base[RW];
+    int slot[RPT];
+    bool valid[RPT];
+    long long base[RPT];
+    int rid[RPT];
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        slot[r] = grp * RW + r;
-        valid[r] = slot[r] < a.nact;
-        const int id = valid[r] ? (a.act ? a.act[slot[r]] : slot[r]) : 0;
-        base[r] = (long long)id * N;
-        if (a.in_mode == IN_BOUNDARY)   // W row of this problem and rhs
-            base[r] = ((long long)d.wrow * a.w_rhs + id) * n;
+    for (int j = 0; j < RPT; ++j) {
+        const int r = cgi * RPT + j;
+        slot[j] = ch * SRB + r;
+        valid[j] = slot[j] < a.nact;
+        rid[j] = valid[j] ? (a.act ? a.act[slot[j]] : slot[j]) : 0;
+        base[j] = (a.in_mode == IN_BOUNDARY) ? ((long long)d.wrow * a.w_rhs + rid[j]) * n
+                                             : (long long)rid[j] * N;
     }
-    // slots of tb past row L are read (against zero factor entries) but never
-    // written: clear them once so that no stale LDS value can reach the sums
-    for (int e = lane; e < 2 * RW * Q * UMAX; e += WAVE) (&tb[0][0][0][0])[e] = mk<T>(0, 0);
-    __syncthreads();
+    bool rowv[RG];
+    bool in_X[RG];
+    int line[RG];
+    cplx<T> sinv2[RG];
+#pragma unroll
+    for (int q = 0; q < RG; ++q) {
+        const int i = i0 + q;
+        rowv[q] = i < L;
+        line[q] = d.lo + i;
+        in_X[q] = rowv[q] && line[q] >= d.xs && line[q] <= d.xe;
+        sinv2[q] = rowv[q] ? ccast<T>(tab[L + 1 + i]) : mk<T>(0, 0);
+    }
     const int grow = (d.kind == ASP_SUB_R) ? 0 : L - 1;          // row carrying boundary data
     const zd coupl = (d.kind == ASP_SUB_R) ? tab[0] : tab[L];    // s at lo-1/2 or hi+1/2
-    const int line_i = d.lo + i;
-    const bool in_X = (line_i >= d.xs) && (line_i <= d.xe);
-    const int tq = i % Q, tu = i / Q;   // where row i's entry sits in tb
 
-    cplx<T> A[UMAX], An[UMAX];
+    // rows past L are read against zero factor entries but never written
+    for (int e = tid; e < 2 * SRB * LR; e += SB) (&tb[0][0][0])[e] = mk<T>(0, 0);
+    cplx<T> pf[FPT];
+    auto fetch = [&](int blk) {
+        const cplx<T>* Fk = F + (long long)blk * FS;
 #pragma unroll
-    for (int u = 0; u < UMAX; ++u)
-        A[u] = (u < U) ? F[u * WAVE + lane] : mk<T>(0, 0);
-
-    // forward sweep
-    cplx<T> yk[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) yk[r] = mk<T>(0, 0);
-    for (int k = 1; k <= n; ++k) {
-        const int buf = k & 1;
-        if (k < n) {
-            const cplx<T>* Fk = F + (long long)k * WAVE * U;
-#pragma unroll
-            for (int u = 0; u < UMAX; ++u)
-                An[u] = (u < U) ? Fk[u * WAVE + lane] : mk<T>(0, 0);
-        }
-        if (rowlane) {
-            const cplx<T> e = ccast<T>(a.ax.sh[k - 1]) * sinv2_i;    // E_{k-1}, row i
-            zd cin = mk(0.0, 0.0);
-            if (a.in_mode != IN_GRID && i == grow) cin = -(coupl * a.ax.inv_sh2[k - 1]);
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                cplx<T> g = mk<T>(0, 0);
-                if (a.in_mode == IN_GRID) {
-                    if (in_X) g = ccast<T>(a.r[base[r] + (k - 1) + (long long)n * (line_i - 1)]);
-                } else if (i == grow) {
-                    if (a.in_mode == IN_BOUNDARY)
-                        g = ccast<T>(a.W[base[r] + (k - 1)] * cin);
-                    else if (slot[r] == k - 1)   // IN_UNIT: unit data at i1 = slot + 1
-                        g = ccast<T>(cin);
-                }
-                if (k > 1) g = g - e * yk[r];
-                tb[buf][r][tq][tu] = g;
-            }
-        }
-        __syncthreads();
-        cplx<T> acc[RW];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            acc[r] = mk<T>(0, 0);
-#pragma unroll
-            for (int u = 0; u < UMAX; ++u)
-                if (u < U) acc[r] = cfma(A[u], tb[buf][r][q][u], acc[r]);
-            if (Q >= 2) acc[r] = acc[r] + shfl_xor_c(acc[r], 1);
-            if (Q >= 4) acc[r] = acc[r] + shfl_xor_c(acc[r], 2);
-            yk[r] = acc[r];
-        }
-        if (rowlane) {
-            cplx<T>* Yk = Y + ((long long)(k - 1) * L + i) * RW;
-#pragma unroll
-            for (int r = 0; r < RW; ++r) Yk[r] = yk[r];
-        }
-#pragma unroll
-        for (int u = 0; u < UMAX; ++u) A[u] = An[u];
-    }
-
-    // backward sweep; v_n = y_n
-    const int jout = (d.kind == ASP_SUB_R) ? (d.xe - d.lo) : (d.xs - d.lo);   // OUT_LINE row
-    auto emit = [&](int k, const cplx<T>* v) {
-        if (!rowlane) return;
-        if (a.out_mode == OUT_LINE) {
-            if (i != jout) return;
-            cplx<T>* Tp = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off;
-#pragma unroll
-            for (int r = 0; r < RW; ++r)
-                if (valid[r]) Tp[(long long)slot[r] * n + (k - 1)] = v[r];
-            return;
-        }
-        if (!in_X) return;
-        const long long off = (k - 1) + (long long)n * (line_i - 1);
-        const bool set_u = (a.out_mode == OUT_GRID_ADD_U) ||
-                           (a.out_mode == OUT_GRID_ACC && d.kind == ASP_SUB_L && d.p == 1);
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            if (!valid[r]) continue;
-            const long long o = (long long)(a.act ? a.act[slot[r]] : slot[r]) * N + off;
-            zd val = ccast<double>(v[r]);
-            if (set_u) val = val + a.Ugrid[o];
-            else if (a.out_mode == OUT_GRID_ACC) val = val + a.out[o];
-            a.out[o] = val;
+        for (int u = 0; u < FPT; ++u) {
+            const int e = tid + u * SB;
+            pf[u] = (e < FS) ? Fk[e] : mk<T>(0, 0);
         }
     };
-    cplx<T> vk[RW];
+    auto stash = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < RW; ++r) vk[r] = yk[r];
-    emit(n, vk);
-    if (n >= 2) {
-        const cplx<T>* Fk = F + (long long)(n - 2) * WAVE * U;
-#pragma unroll
-        for (int u = 0; u < UMAX; ++u)
-            A[u] = (u < U) ? Fk[u * WAVE + lane] : mk<T>(0, 0);
-    }
-    for (int k = n - 1; k >= 1; --k) {
-        const int buf = k & 1;
-        if (k > 1) {
-            const cplx<T>* Fk = F + (long long)(k - 2) * WAVE * U;
-#pragma unroll
-            for (int u = 0; u < UMAX; ++u)
-                An[u] = (u < U) ? Fk[u * WAVE + lane] : mk<T>(0, 0);
+        for (int u = 0; u < FPT; ++u) {
+            const int e = tid + u * SB;
+            if (e < FS) Fs[buf][e] = pf[u];
         }
-        cplx<T> ykk[RW];
-        if (rowlane) {
-            const cplx<T> e = ccast<T>(a.ax.sh[k]) * sinv2_i;        // E_k, row i
-            const cplx<T>* Yk = Y + ((long long)(k - 1) * L + i) * RW;
+    };
+    // block product of rows i0.. for the chunk's vectors in tb[buf] with Fs[fb]
+    auto product = [&](int fb, int buf, cplx<T> (&acc)[RG][RPT]) {
 #pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                ykk[r] = Yk[r];
-                tb[buf][r][tq][tu] = e * vk[r];
+        for (int q = 0; q < RG; ++q)
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) acc[q][j] = mk<T>(0, 0);
+        for (int c = 0; c < L; ++c) {
+            cplx<T> f[RG], t[RPT];
+#pragma unroll
+            for (int q = 0; q < RG; ++q) f[q] = Fs[fb][c * LR + i0 + q];
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) t[j] = tb[buf][cgi * RPT + j][c];
+#pragma unroll
+            for (int q = 0; q < RG; ++q)
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) acc[q][j] = cfma(f[q], t[j], acc[q][j]);
+        }
+    };
+
+    fetch(0);
+    stash(1);
+    __syncthreads();
+
+    // forward sweep: y_k = S_k^-1 (g_k - E_{k-1} y_{k-1}); block k sits in ring slot k & 1
+    cplx<T> yk[RG][RPT];
+#pragma unroll
+    for (int q = 0; q < RG; ++q)
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) yk[q][j] = mk<T>(0, 0);
+    for (int k = 1; k <= n; ++k) {
+        const int buf = k & 1;
+        if (k < n) fetch(k);
+        const cplx<T> shm = ccast<T>(a.ax.sh[k - 1]);
+        zd cin = mk(0.0, 0.0);
+        if (a.in_mode != IN_GRID) cin = -(coupl * a.ax.inv_sh2[k - 1]);
+#pragma unroll
+        for (int q = 0; q < RG; ++q) {
+            if (!rowv[q]) continue;
+            const int i = i0 + q;
+            const cplx<T> e = shm * sinv2[q];                       // E_{k-1}, row i
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                cplx<T> g = mk<T>(0, 0);
+                if (a.in_mode == IN_GRID) {
+                    if (in_X[q]) g = ccast<T>(a.r[base[j] + (k - 1) + (long long)n * (line[q] - 1)]);
+                } else if (i == grow) {
+                    if (a.in_mode == IN_BOUNDARY)
+                        g = ccast<T>(a.W[base[j] + (k - 1)] * cin);
+                    else if (slot[j] == k - 1)      // IN_UNIT: unit data at i1 = slot + 1
+                        g = ccast<T>(cin);
+                }
+                if (k > 1) g = g - e * yk[q][j];
+                tb[buf][cgi * RPT + j][i] = g;
             }
         }
         __syncthreads();
+        product(buf, buf, yk);
 #pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            cplx<T> acc = mk<T>(0, 0);
+        for (int q = 0; q < RG; ++q)
 #pragma unroll
-            for (int u = 0; u < UMAX; ++u)
-                if (u < U) acc = cfma(A[u], tb[buf][r][q][u], acc);
-            if (Q >= 2) acc = acc + shfl_xor_c(acc, 1);
-            if (Q >= 4) acc = acc + shfl_xor_c(acc, 2);
-            vk[r] = rowlane ? ykk[r] - acc : acc;
+            for (int j = 0; j < RPT; ++j)
+                if (rowv[q]) Y[((long long)(k - 1) * SRB + cgi * RPT + j) * LR + i0 + q] = yk[q][j];
+        if (k < n) stash((k + 1) & 1);
+    }
+
+    // backward sweep: v_n = y_n, v_k = y_k - S_k^-1 E_k v_{k+1}.  Block n-1 is
+    // still in slot (n-1) & 1; block k-1 is loaded during step k.
+    const int jout = (d.kind == ASP_SUB_R) ? (d.xe - d.lo) : (d.xs - d.lo);   // OUT_LINE row
+    auto emit = [&](int k, const cplx<T> (&v)[RG][RPT]) {
+#pragma unroll
+        for (int q = 0; q < RG; ++q) {
+            if (!rowv[q]) continue;
+            const int i = i0 + q;
+            if (a.out_mode == OUT_LINE) {
+                if (i != jout) continue;
+                cplx<T>* Tp = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off;
+#pragma unroll
+                for (int j = 0; j < RPT; ++j)
+                    if (valid[j]) Tp[(long long)slot[j] * n + (k - 1)] = v[q][j];
+                continue;
+            }
+            if (!in_X[q]) continue;
+            const long long off = (k - 1) + (long long)n * (line[q] - 1);
+            const bool set_u = (a.out_mode == OUT_GRID_ADD_U) ||
+                               (a.out_mode == OUT_GRID_ACC && d.kind == ASP_SUB_L && d.p == 1);
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                if (!valid[j]) continue;
+                const long long o = (long long)rid[j] * N + off;
+                zd val = ccast<double>(v[q][j]);
+                if (set_u) val = val + a.Ugrid[o];
+                else if (a.out_mode == OUT_GRID_ACC) val = val + a.out[o];
+                a.out[o] = val;
+            }
         }
-        emit(k, vk);
+    };
+    emit(n, yk);
+    cplx<T> (&vk)[RG][RPT] = yk;
+    for (int k = n - 1; k >= 1; --k) {
+        const int buf = k & 1;
+        if (k > 1) fetch(k - 2);
+        const cplx<T> shp = ccast<T>(a.ax.sh[k]);
+        cplx<T> ykk[RG][RPT];
 #pragma unroll
-        for (int u = 0; u < UMAX; ++u) A[u] = An[u];
+        for (int q = 0; q < RG; ++q) {
+            const cplx<T> e = shp * sinv2[q];                       // E_k, row i
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                ykk[q][j] = rowv[q] ? Y[((long long)(k - 1) * SRB + cgi * RPT + j) * LR + i0 + q]
+                                    : mk<T>(0, 0);
+                if (rowv[q]) tb[buf][cgi * RPT + j][i0 + q] = e * vk[q][j];
+            }
+        }
+        __syncthreads();
+        cplx<T> acc[RG][RPT];
+        product(buf, buf, acc);
+#pragma unroll
+        for (int q = 0; q < RG; ++q)
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) vk[q][j] = ykk[q][j] - acc[q][j];
+        emit(k, vk);
+        if (k > 1) stash((k - 1) & 1);
     }
 }
 
@@ -349,88 +375,102 @@ __global__ __launch_bounds__(WAVE) void solve2d_kernel(SolveArgs a) {
 // unit data at i1 = c + 1):
 //   right-going: W^R_{p+1} = T^R_p W^R_p + u~_{p,p} on the last line of X_p
 //   left-going:  W^L_{p-1} = T^L_p W^L_p + u~_{p,p} on the first line of X_p
-// blockIdx.z selects the sweep; a block computes 64 outputs i1 for a group of
-// right-hand sides, reading W in chunks of 64 columns through LDS.
 // ----------------------------------------------------------------------------
 struct SweepArgs {
     const void* T;
     long long t_off[2];      // map of the problem stepped from (R, L)
-    const zd* W;
-    long long w_in[2];       // offsets (in n-vectors * w_rhs) of the input rows
-    zd* Wout;
+    const void* Wt_in[2];    // W transposed: [i1][slot], row stride ws, type of the maps
+    void* Wt_out[2];
+    zd* W;                   // W rows [rhs][i1] (complex128) of the problems stepped into
     long long w_out[2];
     int line[2];             // line of u~_{p,p} added (last of X_p / first of X_p)
     const zd* Ugrid;
     const int* act;
     int nact;
-    int w_rhs;
+    int ws;                  // padded slot count (multiple of SW_RT)
     int n;
     long long N;
 };
 
-constexpr int SW_ROWS = 64;
-constexpr int SW_RG = 4;       // right-hand-side lanes per block
-constexpr int SW_RPT = 2;      // right-hand sides per thread
-constexpr int SW_KC = 64;      // columns per LDS chunk
+constexpr int SW_ROWS = 64;    // output rows (i1) per block: one per lane
+constexpr int SW_RT = 8;       // right-hand sides per block
 
+template <typename T> struct SweepWaves { static constexpr int value = sizeof(T) == 4 ? 16 : 8; };
+
+// A block computes 64 consecutive outputs i1 for 8 right-hand sides.  Its
+// wavefronts split the reduction over the columns c of T; per column a
+// wavefront makes one coalesced load of T(i1, c) and one wave-uniform load of
+// the 8 inputs.  The partial sums meet in LDS and are added in wavefront order
+// (fixed, so the result does not depend on scheduling).  Blocks that share a
+// row tile are 16 block ids apart and so run on the same XCD, sharing its L2
+// copy of T.
 template <typename T>
-__global__ __launch_bounds__(256) void sweep_step_kernel(SweepArgs a) {
-    __shared__ cplx<T> Ws[SW_KC][SW_RG * SW_RPT];
+__global__ __launch_bounds__(1024) void sweep_step_kernel(SweepArgs a) {
+    constexpr int NW = SweepWaves<T>::value;
+    __shared__ cplx<T> red[NW][SW_RT][SW_ROWS];
     const int side = blockIdx.z;
     const int n = a.n;
-    const int tid = threadIdx.x;
-    const int k = blockIdx.x * SW_ROWS + (tid % SW_ROWS);
-    const int rg = tid / SW_ROWS;
-    const int r0 = blockIdx.y * SW_RG * SW_RPT;
-    const cplx<T>* Tm = reinterpret_cast<const cplx<T>*>(a.T) + a.t_off[side];
-    const zd* Win = a.W + a.w_in[side];
-    cplx<T> acc[SW_RPT];
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    const int k0 = blockIdx.x * SW_ROWS;
+    const int k = k0 + lane;
+    const int s0 = blockIdx.y * SW_RT;
+    const cplx<T>* __restrict__ Tm = reinterpret_cast<const cplx<T>*>(a.T) + a.t_off[side];
+    const cplx<T>* __restrict__ Wi = reinterpret_cast<const cplx<T>*>(a.Wt_in[side]) + s0;
+    const int ws = a.ws;
+    const int kk = k < n ? k : n - 1;   // rows past n repeat the last one (not stored)
+    const int per = (n + NW - 1) / NW;
+    const int cb = wv * per, ce = min(n, cb + per);
+    cplx<T> acc[SW_RT];
 #pragma unroll
-    for (int j = 0; j < SW_RPT; ++j) acc[j] = mk<T>(0, 0);
-    for (int c0 = 0; c0 < n; c0 += SW_KC) {
-        __syncthreads();
-        for (int e = tid; e < SW_KC * SW_RG * SW_RPT; e += 256) {
-            const int cc = e % SW_KC, rr = e / SW_KC;
-            const int slot = r0 + rr;
-            cplx<T> v = mk<T>(0, 0);
-            if (c0 + cc < n && slot < a.nact) {
-                const int id = a.act ? a.act[slot] : slot;
-                v = ccast<T>(Win[(long long)id * n + c0 + cc]);
-            }
-            Ws[cc][rr] = v;
-        }
-        __syncthreads();
-        if (k < n) {
-            const int cmax = (n - c0 < SW_KC) ? n - c0 : SW_KC;
-            for (int cc = 0; cc < cmax; ++cc) {
-                const cplx<T> t = Tm[(long long)(c0 + cc) * n + k];
+    for (int j = 0; j < SW_RT; ++j) acc[j] = mk<T>(0, 0);
+#pragma unroll 4
+    for (int c = cb; c < ce; ++c) {
+        const cplx<T> t = Tm[(long long)c * n + kk];
+        const cplx<T>* wc = Wi + (long long)c * ws;
 #pragma unroll
-                for (int j = 0; j < SW_RPT; ++j) acc[j] = cfma(t, Ws[cc][rg * SW_RPT + j], acc[j]);
-            }
-        }
+        for (int j = 0; j < SW_RT; ++j) acc[j] = cfma(t, wc[j], acc[j]);
     }
-    if (k >= n) return;
 #pragma unroll
-    for (int j = 0; j < SW_RPT; ++j) {
-        const int slot = r0 + rg * SW_RPT + j;
-        if (slot >= a.nact) continue;
-        const int id = a.act ? a.act[slot] : slot;
-        const zd u = a.Ugrid[(long long)id * a.N + (long long)n * (a.line[side] - 1) + k];
-        a.Wout[a.w_out[side] + (long long)id * n + k] = ccast<double>(acc[j]) + u;
-    }
+    for (int j = 0; j < SW_RT; ++j) red[wv][j][lane] = acc[j];
+    __syncthreads();
+    if (threadIdx.x >= SW_RT * SW_ROWS) return;
+    const int j = threadIdx.x / SW_ROWS, row = threadIdx.x % SW_ROWS;
+    const int ko = k0 + row, slot = s0 + j;
+    if (ko >= n || slot >= a.nact) return;
+    cplx<T> sum = red[0][j][row];
+    for (int q = 1; q < NW; ++q) sum = sum + red[q][j][row];
+    const int id = a.act ? a.act[slot] : slot;
+    const zd v = ccast<double>(sum) +
+                 a.Ugrid[(long long)id * a.N + (long long)n * (a.line[side] - 1) + ko];
+    a.W[a.w_out[side] + (long long)id * n + ko] = v;
+    reinterpret_cast<cplx<T>*>(a.Wt_out[side])[(long long)ko * ws + slot] = ccast<T>(v);
 }
 
 // W rows of the first sweep step: u~_{1,1} on the last line of X_1 (right-going)
-// and u~_{m,m} on the first line of X_m (left-going)
+// and u~_{m,m} on the first line of X_m (left-going), plus their transposed copies
+// (padding slots zero)
+template <typename T>
 __global__ void sweep_seed_kernel(const zd* __restrict__ Ugrid, zd* __restrict__ W,
                                   long long outR, long long outL, int lineR, int lineL,
-                                  const int* __restrict__ act, int n, long long N) {
+                                  cplx<T>* __restrict__ WtR, cplx<T>* __restrict__ WtL,
+                                  const int* __restrict__ act, int nact, int ws, int n,
+                                  long long N) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const int id = act ? act[blockIdx.y] : (int)blockIdx.y;
+    const int slot = blockIdx.y;
+    if (slot >= nact) {
+        WtR[(long long)k * ws + slot] = mk<T>(0, 0);
+        WtL[(long long)k * ws + slot] = mk<T>(0, 0);
+        return;
+    }
+    const int id = act ? act[slot] : slot;
     const long long u = (long long)id * N + k;
-    W[outR + (long long)id * n + k] = Ugrid[u + (long long)n * (lineR - 1)];
-    W[outL + (long long)id * n + k] = Ugrid[u + (long long)n * (lineL - 1)];
+    const zd vR = Ugrid[u + (long long)n * (lineR - 1)];
+    const zd vL = Ugrid[u + (long long)n * (lineL - 1)];
+    W[outR + (long long)id * n + k] = vR;
+    W[outL + (long long)id * n + k] = vL;
+    WtR[(long long)k * ws + slot] = ccast<T>(vR);
+    WtL[(long long)k * ws + slot] = ccast<T>(vL);
 }
 
 }  // namespace
@@ -449,14 +489,16 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int Q, int RW>
-static hipError_t launch_solve_q(const asp_plan* P, const SolveArgs& a, int blocks, hipStream_t st) {
+template <int LR>
+static hipError_t launch_solve_lr(const asp_plan* P, const SolveArgs& a, int blocks, hipStream_t st) {
     if (P->prec == ASP_PREC_FP32)
-        hipLaunchKernelGGL((solve2d_kernel<float, Q, RW>), dim3(blocks), dim3(WAVE), 0, st, a);
+        hipLaunchKernelGGL((solve2d_kernel<float, LR>), dim3(blocks), dim3(SB), 0, st, a);
     else
-        hipLaunchKernelGGL((solve2d_kernel<double, Q, RW>), dim3(blocks), dim3(WAVE), 0, st, a);
+        hipLaunchKernelGGL((solve2d_kernel<double, LR>), dim3(blocks), dim3(SB), 0, st, a);
     return hipGetLastError();
 }
+
+int solve_rhs_per_block() { return SRB; }
 
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st) {
     if (L.njobs <= 0 || L.nact <= 0) return hipSuccess;
@@ -481,13 +523,23 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     a.y_per_wave = P->y_per_wave;
     a.n = P->n;
     a.N = P->N;
-    const int ngroups = (L.nact + SOLVE_RW - 1) / SOLVE_RW;
-    const long long B = (long long)L.njobs * ngroups;
-    if (B * a.y_per_wave > P->y_waves * P->y_per_wave) return hipErrorInvalidValue;   // scratch too small
+    const int LR = L.rl ? P->LR_RL : P->LR_M;   // every job of one launch shares its row count
+    const long long B = (long long)L.njobs * ((L.nact + SRB - 1) / SRB);
+    if (B > P->y_waves || (long long)P->n * SRB * LR > P->y_per_wave)
+        return hipErrorInvalidValue;   // scratch too small
     const int blocks = (int)(((B + 7) / 8) * 8);
-    const int Q = L.rl ? P->Q_RL : P->Q_M;   // every job of one launch shares its Q
-    if (Q == 4) return launch_solve_q<4, SOLVE_RW>(P, a, blocks, st);
-    return launch_solve_q<2, SOLVE_RW>(P, a, blocks, st);
+    if (LR == 16) return launch_solve_lr<16>(P, a, blocks, st);
+    return launch_solve_lr<32>(P, a, blocks, st);
+}
+
+static int sweep_slots(int nact) { return (nact + SW_RT - 1) / SW_RT * SW_RT; }
+
+int sweep_wt_len(const asp_plan* P, int nrhs) { return 4 * P->n * sweep_slots(nrhs); }
+
+// transposed sweep buffers: [side][ping-pong][n][ws]
+static void* wt_buf(const asp_plan* P, int side, int pp, int ws) {
+    const size_t esz = P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd);
+    return static_cast<char*>(P->d_wt) + ((size_t)(side * 2 + pp) * P->n * ws) * esz;
 }
 
 hipError_t launch_sweep_seed(const asp_plan* P, zd* W, long long outR, long long outL,
@@ -495,26 +547,38 @@ hipError_t launch_sweep_seed(const asp_plan* P, zd* W, long long outR, long long
     if (nact <= 0) return hipSuccess;
     const int lineR = P->X[0][1];
     const int lineL = P->X[P->m - 1][0];
-    dim3 grid((P->n + 255) / 256, nact);
-    hipLaunchKernelGGL(sweep_seed_kernel, grid, dim3(256), 0, st, P->d_U, W, outR, outL, lineR,
-                       lineL, act, P->n, P->N);
+    const int ws = sweep_slots(nact);
+    if ((long long)4 * P->n * ws > P->wt_elems) return hipErrorInvalidValue;
+    dim3 grid((P->n + 255) / 256, ws);
+    if (P->prec == ASP_PREC_FP32)
+        hipLaunchKernelGGL(sweep_seed_kernel<float>, grid, dim3(256), 0, st, P->d_U, W, outR, outL,
+                           lineR, lineL, (zf*)wt_buf(P, 0, 0, ws), (zf*)wt_buf(P, 1, 0, ws), act,
+                           nact, ws, P->n, P->N);
+    else
+        hipLaunchKernelGGL(sweep_seed_kernel<double>, grid, dim3(256), 0, st, P->d_U, W, outR, outL,
+                           lineR, lineL, (zd*)wt_buf(P, 0, 0, ws), (zd*)wt_buf(P, 1, 0, ws), act,
+                           nact, ws, P->n, P->N);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const int* act, int nact,
                              hipStream_t st) {
     // step t moves the right-going sweep from layer p = t+1 to p+1 and the
-    // left-going sweep from layer p' = m-t to p'-1
+    // left-going sweep from layer p' = m-t to p'-1; the transposed inputs of
+    // step t are ping-pong buffer (t-1) & 1
     const int m = P->m;
     const int pR = t + 1, pL = m - t;
+    const int ws = sweep_slots(nact);
+    if ((long long)4 * P->n * ws > P->wt_elems) return hipErrorInvalidValue;
     SweepArgs a;
     a.T = P->d_T;
     a.t_off[0] = P->subs[P->idx_R(pR)].tr_off;
     a.t_off[1] = P->subs[P->idx_L(pL)].tr_off;
+    for (int side = 0; side < 2; ++side) {
+        a.Wt_in[side] = wt_buf(P, side, (t - 1) & 1, ws);
+        a.Wt_out[side] = wt_buf(P, side, t & 1, ws);
+    }
     a.W = W;
-    a.Wout = W;
-    a.w_in[0] = (long long)P->wrow(P->idx_R(pR)) * w_rhs * P->n;
-    a.w_in[1] = (long long)P->wrow(P->idx_L(pL)) * w_rhs * P->n;
     a.w_out[0] = (long long)P->wrow(P->idx_R(pR + 1)) * w_rhs * P->n;
     a.w_out[1] = (long long)P->wrow(P->idx_L(pL - 1)) * w_rhs * P->n;
     a.line[0] = P->X[pR - 1][1];
@@ -522,13 +586,15 @@ hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const i
     a.Ugrid = P->d_U;
     a.act = act;
     a.nact = nact;
-    a.w_rhs = w_rhs;
+    a.ws = ws;
     a.n = P->n;
     a.N = P->N;
-    dim3 grid((P->n + SW_ROWS - 1) / SW_ROWS, (nact + SW_RG * SW_RPT - 1) / (SW_RG * SW_RPT), 2);
+    dim3 grid((P->n + SW_ROWS - 1) / SW_ROWS, ws / SW_RT, 2);
     if (P->prec == ASP_PREC_FP32)
-        hipLaunchKernelGGL(sweep_step_kernel<float>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(sweep_step_kernel<float>, grid, dim3(64 * SweepWaves<float>::value), 0,
+                           st, a);
     else
-        hipLaunchKernelGGL(sweep_step_kernel<double>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(sweep_step_kernel<double>, grid, dim3(64 * SweepWaves<double>::value), 0,
+                           st, a);
     return hipGetLastError();
 }

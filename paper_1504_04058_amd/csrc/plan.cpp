@@ -118,7 +118,7 @@ static void build_subproblems(asp_plan* P) {
     }
 }
 
-static int lanes_q(int L) { return L <= 16 ? 4 : 2; }
+static int rows_per_wave(int L) { return L <= 16 ? 16 : 32; }
 
 extern "C" void asp_default_opts(asp_opts* o) {
     if (!o) return;
@@ -192,16 +192,15 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (dim == 2 && P->max_L > 32) {
         return fail(ASP_ERR_ARG, "2D auxiliary problems are limited to 32 sweep lines (b + 2(pml_eta-1) <= 32)");
     }
-    P->Q_M = lanes_q(maxL_M);
-    P->Q_RL = lanes_q(maxL_RL > 0 ? maxL_RL : 1);
+    P->LR_M = rows_per_wave(maxL_M);
+    P->LR_RL = rows_per_wave(maxL_RL > 0 ? maxL_RL : 1);
     long long fac_off = 0, tab_off = 0, tr_off = 0;
     for (size_t s = 0; s < P->subs.size(); ++s) {
         SubDesc& d = P->subs[s];
-        d.Q = (d.kind == ASP_SUB_M) ? P->Q_M : P->Q_RL;
-        d.U = (d.L + d.Q - 1) / d.Q;
+        d.LR = (d.kind == ASP_SUB_M) ? P->LR_M : P->LR_RL;
         d.fac_off = fac_off;
         d.tab_off = tab_off;
-        fac_off += (long long)n * 64 * d.U;
+        fac_off += (long long)n * d.L * d.LR;
         tab_off += sub_table_len(d.L);
         d.wrow = (d.kind == ASP_SUB_M) ? -1 : (int)s - P->m;
         // the sweeps step through R_p and L_p for 1 < p < m with their dense maps
@@ -265,7 +264,7 @@ extern "C" void asp_destroy(asp_plan* P) {
         return;
     }
     void* bufs[] = {P->d_ksq, P->d_axis, P->d_subtab, P->d_desc, P->d_jobs, P->d_fac, P->d_flag,
-                    P->d_T, P->d_U, P->d_W, P->d_stage, P->d_y, P->d_V, P->d_Z, P->d_b,
+                    P->d_T, P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_y, P->d_V, P->d_Z, P->d_b,
                     P->d_red, P->d_small, P->d_act};
     (void)hipStreamSynchronize(P->stream);
     for (void* b : bufs)
