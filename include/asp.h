@@ -72,8 +72,10 @@ typedef struct {
     int dim, n, m;            /* dimension, points per side, number of layers (Section 2) */
     int n_sub;                /* 3m - 2 auxiliary problems (Algorithms 1 and 3) */
     int max_lines;            /* largest number of sweep lines of one auxiliary problem */
-    size_t factor_bytes;      /* device bytes held by the layer factors */
+    size_t factor_bytes;      /* device bytes the factors (and sweep maps) occupy once
+                                 asp_factor has run; known right after asp_setup */
     size_t workspace_bytes;   /* device bytes of the apply/GMRES workspaces now allocated */
+    int factored;             /* nonzero once asp_factor has succeeded */
 } asp_plan_info;
 
 /* Fill *opts with the defaults (C = 25, FP64, null stream, device plan). */
@@ -186,6 +188,15 @@ typedef enum {
 asp_status asp_timing_enable(asp_plan* plan, int enable);
 asp_status asp_timing_read(asp_plan* plan, int cls, int* launches, double* ms, double* bytes,
                            double* flops);
+
+/* asp_workspace_estimate -- device bytes of the workspaces asp_gmres allocates
+ * for nrhs right-hand sides and the given restart length (apply scratch,
+ * sweep data, Krylov basis); host only.
+ * asp_release_workspace -- free those workspaces now, keeping the factors
+ * (a factor cache keeps idle plans this way); the next call allocates again.
+ * Synchronizes the plan's stream. */
+asp_status asp_workspace_estimate(const asp_plan* plan, int nrhs, int restart, size_t* bytes);
+asp_status asp_release_workspace(asp_plan* plan);
 
 /* asp_info -- sizes and memory of the plan.  asp_set_stream -- change the stream
  * used by later calls.  asp_destroy -- free everything (NULL is ignored).

@@ -38,7 +38,8 @@ class asp_opts(ctypes.Structure):
 class asp_plan_info(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("m", ctypes.c_int),
                 ("n_sub", ctypes.c_int), ("max_lines", ctypes.c_int),
-                ("factor_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
+                ("factor_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+                ("factored", ctypes.c_int)]
 
 
 _lib = None
@@ -74,6 +75,12 @@ def lib():
             "asp_set_stream": (I, [P, P]),
             "asp_destroy": (V, [P]),
             "asp_last_error": (ctypes.c_char_p, [P]),
+            "asp_timing_enable": (I, [P, I]),
+            "asp_timing_read": (I, [P, I, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
+            "asp_workspace_estimate": (I, [P, I, I, ctypes.POINTER(ctypes.c_size_t)]),
+            "asp_release_workspace": (I, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -178,6 +185,29 @@ def asp_info(plan):
     info = asp_plan_info()
     _check(plan, lib().asp_info(plan, ctypes.byref(info)))
     return {k: getattr(info, k) for k, _ in asp_plan_info._fields_}
+
+
+def asp_workspace_estimate(plan, nrhs, restart):
+    b = ctypes.c_size_t()
+    _check(plan, lib().asp_workspace_estimate(plan, nrhs, restart, ctypes.byref(b)))
+    return b.value
+
+
+def asp_release_workspace(plan):
+    _check(plan, lib().asp_release_workspace(plan))
+
+
+def asp_timing_enable(plan, enable):
+    _check(plan, lib().asp_timing_enable(plan, int(enable)))
+
+
+def asp_timing_read(plan, cls):
+    """(launches, ms, bytes, flops) of one kernel class."""
+    nl, ms = ctypes.c_int(), ctypes.c_double()
+    by, fl = ctypes.c_double(), ctypes.c_double()
+    _check(plan, lib().asp_timing_read(plan, cls, ctypes.byref(nl), ctypes.byref(ms),
+                                       ctypes.byref(by), ctypes.byref(fl)))
+    return nl.value, ms.value, by.value, fl.value
 
 
 def asp_set_stream(plan, stream):

@@ -355,3 +355,47 @@ extern "C" asp_status asp_subsolve(asp_plan* P, int kind, int p, const void* in,
                                 P->N * row, Np * row, nrhs, hipMemcpyDeviceToDevice, st));
     return ASP_OK;
 }
+
+// ---------------------------------------------------------------------------
+// workspace accounting
+// ---------------------------------------------------------------------------
+extern "C" asp_status asp_workspace_estimate(const asp_plan* P, int nrhs, int restart,
+                                             size_t* bytes) {
+    if (!P || !bytes || nrhs < 1 || restart < 1) return ASP_ERR_ARG;
+    const double esz = elem_bytes(P);
+    const double vec = (double)nrhs * P->N * sizeof(zd);
+    const double wrows = (double)std::max(2 * P->m - 2, 1) * nrhs * P->n * sizeof(zd);
+    const double wt = (double)sweep_wt_len(P, nrhs) * esz;
+    const double y = (double)std::max(P->m, 2) * groups_of(std::max(nrhs, 64)) * P->n * 32.0 *
+                     solve_rhs_per_block() * esz;
+    const double krylov = vec * (2.0 * restart + 2.0) +
+                          (double)nrhs * krylov_blocks(P->N) * 8 * sizeof(zd) +
+                          (double)nrhs * 257 * sizeof(zd);
+    *bytes = (size_t)(2.0 * vec + wrows + wt + y + krylov);
+    return ASP_OK;
+}
+
+extern "C" asp_status asp_release_workspace(asp_plan* P) {
+    if (!P) return ASP_ERR_ARG;
+    if (P->host_only) return ASP_OK;
+    ASP_HIP(P, hipStreamSynchronize(P->stream));
+    void* bufs[] = {P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_V, P->d_Z, P->d_b, P->d_red,
+                    P->d_small, P->d_act};
+    for (void* b : bufs) dev_free(b);
+    P->d_U = P->d_W = P->d_stage = nullptr;
+    P->d_wt = nullptr;
+    P->d_V = P->d_Z = P->d_b = P->d_red = P->d_small = nullptr;
+    P->d_act = nullptr;
+    P->ws_rhs = 0;
+    P->ws_bytes = 0;
+    P->wt_elems = 0;
+    P->kr_rhs = P->kr_restart = 0;
+    P->kr_bytes = 0;
+    // the solve scratch is shared with asp_factor; keep it only if small
+    if ((double)P->y_waves * P->y_per_wave * elem_bytes(P) > 256.0 * (1 << 20)) {
+        dev_free(P->d_y);
+        P->d_y = nullptr;
+        P->y_waves = 0;
+    }
+    return ASP_OK;
+}

@@ -214,28 +214,33 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     bool rowv[RG];
     bool in_X[RG];
     int line[RG];
+    int lclamp[RG];   // line clamped to the grid, for unconditional loads
     cplx<T> sinv2[RG];
 #pragma unroll
     for (int q = 0; q < RG; ++q) {
         const int i = i0 + q;
         rowv[q] = i < L;
         line[q] = d.lo + i;
+        lclamp[q] = min(line[q], n);
         in_X[q] = rowv[q] && line[q] >= d.xs && line[q] <= d.xe;
         sinv2[q] = rowv[q] ? ccast<T>(tab[L + 1 + i]) : mk<T>(0, 0);
     }
     const int grow = (d.kind == ASP_SUB_R) ? 0 : L - 1;          // row carrying boundary data
     const zd coupl = (d.kind == ASP_SUB_R) ? tab[0] : tab[L];    // s at lo-1/2 or hi+1/2
 
-    // rows past L are read against zero factor entries but never written
+    // rows past L are read against zero factor entries but never written, and
+    // the factor columns past L are read against zero vectors: clear both once
     for (int e = tid; e < 2 * SRB * LR; e += SB) (&tb[0][0][0])[e] = mk<T>(0, 0);
+    for (int e = tid; e < 2 * FMAX; e += SB) (&Fs[0][0])[e] = mk<T>(0, 0);
+    const int LP = (L + 3) & ~3;
     cplx<T> pf[FPT];
+    // loads below are unconditional (from clamped, always valid addresses) and
+    // their values selected where used: a load under a divergent branch makes
+    // the compiler wait for every earlier load at the branch join
     auto fetch = [&](int blk) {
         const cplx<T>* Fk = F + (long long)blk * FS;
 #pragma unroll
-        for (int u = 0; u < FPT; ++u) {
-            const int e = tid + u * SB;
-            pf[u] = (e < FS) ? Fk[e] : mk<T>(0, 0);
-        }
+        for (int u = 0; u < FPT; ++u) pf[u] = Fk[min(tid + u * SB, FS - 1)];
     };
     auto stash = [&](int buf) {
 #pragma unroll
@@ -250,7 +255,10 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         for (int q = 0; q < RG; ++q)
 #pragma unroll
             for (int j = 0; j < RPT; ++j) acc[q][j] = mk<T>(0, 0);
-        for (int c = 0; c < L; ++c) {
+        // columns L..LP-1 of the ring and of tb are zero, so the loop runs to a
+        // multiple of 4 and unrolls
+#pragma unroll 4
+        for (int c = 0; c < LP; ++c) {
             cplx<T> f[RG], t[RPT];
 #pragma unroll
             for (int q = 0; q < RG; ++q) f[q] = Fs[fb][c * LR + i0 + q];
@@ -263,6 +271,31 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         }
     };
 
+    // raw data entering step k (complex128), for rows i0.. and the chunk's
+    // right-hand sides: read one step ahead, before the factor block, so that
+    // waiting for it never waits for the block
+    // one source pointer per (row, rhs): grid data (IN_GRID), boundary data
+    // (IN_BOUNDARY, the same for every row) or a dummy valid address (IN_UNIT);
+    // stride 1 along i1, 0 for the dummy
+    const zd* inp[RG][RPT];
+    const int ink = (a.in_mode == IN_UNIT) ? 0 : 1;
+#pragma unroll
+    for (int q = 0; q < RG; ++q)
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+            inp[q][j] = (a.in_mode == IN_GRID)       ? a.r + base[j] + (long long)n * (lclamp[q] - 1)
+                        : (a.in_mode == IN_BOUNDARY) ? a.W + base[j]
+                                                     : a.subtab;
+    auto load_in = [&](int k, zd (&gv)[RG][RPT]) {
+#pragma unroll
+        for (int q = 0; q < RG; ++q)
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) gv[q][j] = inp[q][j][(long long)(k - 1) * ink];
+    };
+
+    zd gin[RG][RPT];
+    load_in(1, gin);
+    zd shv = a.ax.sh[0], isv = a.ax.inv_sh2[0];
     fetch(0);
     stash(1);
     __syncthreads();
@@ -275,10 +308,16 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         for (int j = 0; j < RPT; ++j) yk[q][j] = mk<T>(0, 0);
     for (int k = 1; k <= n; ++k) {
         const int buf = k & 1;
-        if (k < n) fetch(k);
-        const cplx<T> shm = ccast<T>(a.ax.sh[k - 1]);
-        zd cin = mk(0.0, 0.0);
-        if (a.in_mode != IN_GRID) cin = -(coupl * a.ax.inv_sh2[k - 1]);
+        zd gnx[RG][RPT];
+        zd shn = shv, isn = isv;
+        if (k < n) {
+            load_in(k + 1, gnx);
+            shn = a.ax.sh[k];
+            isn = a.ax.inv_sh2[k];
+            fetch(k);
+        }
+        const cplx<T> shm = ccast<T>(shv);
+        const zd cin = -(coupl * isv);
 #pragma unroll
         for (int q = 0; q < RG; ++q) {
             if (!rowv[q]) continue;
@@ -287,14 +326,12 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
                 cplx<T> g = mk<T>(0, 0);
-                if (a.in_mode == IN_GRID) {
-                    if (in_X[q]) g = ccast<T>(a.r[base[j] + (k - 1) + (long long)n * (line[q] - 1)]);
-                } else if (i == grow) {
-                    if (a.in_mode == IN_BOUNDARY)
-                        g = ccast<T>(a.W[base[j] + (k - 1)] * cin);
-                    else if (slot[j] == k - 1)      // IN_UNIT: unit data at i1 = slot + 1
-                        g = ccast<T>(cin);
-                }
+                if (a.in_mode == IN_GRID)
+                    g = in_X[q] ? ccast<T>(gin[q][j]) : mk<T>(0, 0);
+                else if (i == grow && a.in_mode == IN_BOUNDARY)
+                    g = ccast<T>(gin[q][j] * cin);
+                else if (i == grow && slot[j] == k - 1)     // IN_UNIT: unit data at i1 = slot + 1
+                    g = ccast<T>(cin);
                 if (k > 1) g = g - e * yk[q][j];
                 tb[buf][cgi * RPT + j][i] = g;
             }
@@ -306,18 +343,54 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
             for (int j = 0; j < RPT; ++j)
                 if (rowv[q]) Y[((long long)(k - 1) * SRB + cgi * RPT + j) * LR + i0 + q] = yk[q][j];
-        if (k < n) stash((k + 1) & 1);
+        if (k < n) {
+            stash((k + 1) & 1);
+#pragma unroll
+            for (int q = 0; q < RG; ++q)
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) gin[q][j] = gnx[q][j];
+            shv = shn;
+            isv = isn;
+        }
     }
 
     // backward sweep: v_n = y_n, v_k = y_k - S_k^-1 E_k v_{k+1}.  Block n-1 is
-    // still in slot (n-1) & 1; block k-1 is loaded during step k.
+    // still in slot (n-1) & 1; block k-1 is loaded during step k.  The y_k and
+    // the values the outputs add to are read one step ahead as well.
     const int jout = (d.kind == ASP_SUB_R) ? (d.xe - d.lo) : (d.xs - d.lo);   // OUT_LINE row
-    auto emit = [&](int k, const cplx<T> (&v)[RG][RPT]) {
+    const bool set_u = (a.out_mode == OUT_GRID_ADD_U) ||
+                       (a.out_mode == OUT_GRID_ACC && d.kind == ASP_SUB_L && d.p == 1);
+    const bool add_out = !set_u && a.out_mode == OUT_GRID_ACC;
+    const bool grid_out = a.out_mode != OUT_LINE;
+    const bool use_add = set_u || add_out;
+    const zd* addp[RG][RPT];
+#pragma unroll
+    for (int q = 0; q < RG; ++q)
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+            addp[q][j] = use_add ? (set_u ? a.Ugrid : a.out) + (long long)rid[j] * N +
+                                       (long long)n * (lclamp[q] - 1)
+                                 : a.subtab;
+    const int addk = use_add ? 1 : 0;
+    auto load_add = [&](int k, zd (&av)[RG][RPT]) {
+#pragma unroll
+        for (int q = 0; q < RG; ++q)
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) av[q][j] = addp[q][j][(long long)(k - 1) * addk];
+    };
+    auto load_y = [&](int k, cplx<T> (&yv)[RG][RPT]) {
+#pragma unroll
+        for (int q = 0; q < RG; ++q)
+#pragma unroll
+            for (int j = 0; j < RPT; ++j)
+                yv[q][j] = Y[((long long)(k - 1) * SRB + cgi * RPT + j) * LR + i0 + q];
+    };
+    auto emit = [&](int k, const cplx<T> (&v)[RG][RPT], const zd (&av)[RG][RPT]) {
 #pragma unroll
         for (int q = 0; q < RG; ++q) {
             if (!rowv[q]) continue;
             const int i = i0 + q;
-            if (a.out_mode == OUT_LINE) {
+            if (!grid_out) {
                 if (i != jout) continue;
                 cplx<T>* Tp = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off;
 #pragma unroll
@@ -327,35 +400,42 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
             }
             if (!in_X[q]) continue;
             const long long off = (k - 1) + (long long)n * (line[q] - 1);
-            const bool set_u = (a.out_mode == OUT_GRID_ADD_U) ||
-                               (a.out_mode == OUT_GRID_ACC && d.kind == ASP_SUB_L && d.p == 1);
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
                 if (!valid[j]) continue;
-                const long long o = (long long)rid[j] * N + off;
-                zd val = ccast<double>(v[q][j]);
-                if (set_u) val = val + a.Ugrid[o];
-                else if (a.out_mode == OUT_GRID_ACC) val = val + a.out[o];
-                a.out[o] = val;
+                a.out[(long long)rid[j] * N + off] =
+                    use_add ? ccast<double>(v[q][j]) + av[q][j] : ccast<double>(v[q][j]);
             }
         }
     };
-    emit(n, yk);
+    zd acur[RG][RPT];
+    load_add(n, acur);
+    emit(n, yk, acur);
     cplx<T> (&vk)[RG][RPT] = yk;
+    cplx<T> ycur[RG][RPT];
+    if (n >= 2) {
+        load_y(n - 1, ycur);
+        load_add(n - 1, acur);
+    }
+    shv = a.ax.sh[n - 1];
     for (int k = n - 1; k >= 1; --k) {
         const int buf = k & 1;
-        if (k > 1) fetch(k - 2);
-        const cplx<T> shp = ccast<T>(a.ax.sh[k]);
-        cplx<T> ykk[RG][RPT];
+        cplx<T> ynx[RG][RPT];
+        zd anx[RG][RPT];
+        zd shn = shv;
+        if (k > 1) {
+            load_y(k - 1, ynx);
+            load_add(k - 1, anx);
+            shn = a.ax.sh[k - 1];
+            fetch(k - 2);
+        }
+        const cplx<T> shp = ccast<T>(shv);
 #pragma unroll
         for (int q = 0; q < RG; ++q) {
             const cplx<T> e = shp * sinv2[q];                       // E_k, row i
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                ykk[q][j] = rowv[q] ? Y[((long long)(k - 1) * SRB + cgi * RPT + j) * LR + i0 + q]
-                                    : mk<T>(0, 0);
+            for (int j = 0; j < RPT; ++j)
                 if (rowv[q]) tb[buf][cgi * RPT + j][i0 + q] = e * vk[q][j];
-            }
         }
         __syncthreads();
         cplx<T> acc[RG][RPT];
@@ -363,9 +443,19 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
         for (int q = 0; q < RG; ++q)
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) vk[q][j] = ykk[q][j] - acc[q][j];
-        emit(k, vk);
-        if (k > 1) stash((k - 1) & 1);
+            for (int j = 0; j < RPT; ++j) vk[q][j] = ycur[q][j] - acc[q][j];
+        emit(k, vk, acur);
+        if (k > 1) {
+            stash((k - 1) & 1);
+#pragma unroll
+            for (int q = 0; q < RG; ++q)
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    ycur[q][j] = ynx[q][j];
+                    acur[q][j] = anx[q][j];
+                }
+            shv = shn;
+        }
     }
 }
 

@@ -291,8 +291,9 @@ extern "C" asp_status asp_info(const asp_plan* P, asp_plan_info* info) {
     info->m = P->m;
     info->n_sub = (int)P->subs.size();
     info->max_lines = P->max_L;
-    info->factor_bytes = P->factored ? P->fac_bytes : 0;
+    info->factor_bytes = P->fac_bytes + P->t_bytes;
     info->workspace_bytes = P->ws_bytes + P->kr_bytes;
+    info->factored = P->factored ? 1 : 0;
     return ASP_OK;
 }
 

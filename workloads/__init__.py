@@ -21,3 +21,4 @@ from .fields import (  # noqa: F401
     workload,
     WORKLOADS,
 )
+from .serving import request_stream, materialize, velocity_of, sources_of  # noqa: F401
