@@ -22,7 +22,7 @@ unknowns are reordered with the sweep axis fastest, which makes H banded with
 bandwidth L (lines of the subproblem), and factored by banded LU (LAPACK
 zgbtrf, partial pivoting).  In 3D (Algorithm 3) the paper applies nested
 dissection to the reordered quasi-2D problem; here a sparse LU with a
-fill-reducing ordering (SuperLU) stands in for it: the factorization differs,
+fill-reducing column ordering (SuperLU, COLAMD) stands in for it: the factorization differs,
 the operator it inverts does not.
 """
 import numpy as np
@@ -57,7 +57,7 @@ class BandLU:
 
 class SparseLU:
     def __init__(self, A):
-        self.lu = spla.splu(sp.csc_matrix(A), permc_spec="MMD_AT_PLUS_A")
+        self.lu = spla.splu(sp.csc_matrix(A), permc_spec="COLAMD")
 
     def solve(self, rhs):
         return self.lu.solve(rhs)

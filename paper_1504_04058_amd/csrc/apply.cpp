@@ -62,7 +62,8 @@ void solve_cost(const asp_plan* P, int sub0, int nsub, int nact, double io_vecto
 }  // namespace
 
 double factor_bytes_of(const asp_plan* P, const SubDesc& d) {
-    return (double)P->n * d.L * d.L * elem_bytes(P);
+    const double B = (P->dim == 2) ? d.L : (double)P->n * d.L;
+    return (double)P->n * B * B * elem_bytes(P);
 }
 
 // ---------------------------------------------------------------------------
@@ -127,6 +128,7 @@ extern "C" asp_status asp_timing_read(asp_plan* P, int cls, int* launches, doubl
 // workspaces
 // ---------------------------------------------------------------------------
 asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
+    if (P->dim == 3) return ensure_apply_ws3(P, nrhs);
     if (nrhs <= P->ws_rhs) return ASP_OK;
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     dev_free(P->d_U);
@@ -163,6 +165,7 @@ asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
 // z = M^-1 r for the right-hand-side ids act[0..nact) (device list, NULL for
 // 0..nact-1) of batches laid out with stride N.
 asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact) {
+    if (P->dim == 3) return apply3d_internal(P, r, z, act, nact);
     hipStream_t st = P->stream;
     const int m = P->m;
     const int w_rhs = P->ws_rhs;
@@ -256,12 +259,23 @@ static asp_status compute_transfer(asp_plan* P) {
 extern "C" asp_status asp_factor(asp_plan* P) {
     if (!P) return ASP_ERR_ARG;
     if (P->host_only) return plan_fail(P, ASP_ERR_STATE, "host-only plan");
-    if (P->dim != 2) return plan_fail(P, ASP_ERR_ARG, "3D factorization is not available in this build");
     P->factored = false;
     if (!P->d_fac) {
         char* f = nullptr;
         if (dev_alloc(P, &f, P->fac_bytes) != ASP_OK) return ASP_ERR_OOM;
         P->d_fac = f;
+    }
+    if (P->dim == 3) {
+        ASP_HIP(P, hipMemsetAsync(P->d_flag, 0, sizeof(int), P->stream));
+        asp_status s3 = factor3d(P);
+        if (s3 != ASP_OK) return s3;
+        int flag3 = 0;
+        ASP_HIP(P, hipMemcpyAsync(&flag3, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, P->stream));
+        ASP_HIP(P, hipStreamSynchronize(P->stream));
+        if (flag3)
+            return plan_fail(P, ASP_ERR_BREAKDOWN, "zero or non-finite pivot in a layer factorization");
+        P->factored = true;
+        return ASP_OK;
     }
     if (!P->d_T && P->t_bytes > 0) {
         char* t = nullptr;
@@ -325,6 +339,7 @@ extern "C" asp_status asp_subsolve(asp_plan* P, int kind, int p, const void* in,
     if (!P->factored) return plan_fail(P, ASP_ERR_STATE, "asp_subsolve before asp_factor");
     asp_status s = ensure_apply_ws(P, nrhs);
     if (s != ASP_OK) return s;
+    if (P->dim == 3) return subsolve3d(P, idx, in, out, nrhs);
     const SubDesc& d = P->subs[idx];
     hipStream_t st = P->stream;
     const size_t row = sizeof(zd);
@@ -363,6 +378,14 @@ extern "C" asp_status asp_workspace_estimate(const asp_plan* P, int nrhs, int re
                                              size_t* bytes) {
     if (!P || !bytes || nrhs < 1 || restart < 1) return ASP_ERR_ARG;
     const double esz = elem_bytes(P);
+    if (P->dim == 3) {
+        const double vec3 = (double)nrhs * P->N * sizeof(zd);
+        const double kr3 = vec3 * (2.0 * restart + 2.0) +
+                           (double)nrhs * krylov_blocks(P->N) * 8 * sizeof(zd) +
+                           (double)nrhs * 257 * sizeof(zd);
+        *bytes = workspace_estimate3(P, nrhs) + (size_t)kr3;
+        return ASP_OK;
+    }
     const double vec = (double)nrhs * P->N * sizeof(zd);
     const double wrows = (double)std::max(2 * P->m - 2, 1) * nrhs * P->n * sizeof(zd);
     const double wt = (double)sweep_wt_len(P, nrhs) * esz;
@@ -380,8 +403,11 @@ extern "C" asp_status asp_release_workspace(asp_plan* P) {
     if (P->host_only) return ASP_OK;
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     void* bufs[] = {P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_V, P->d_Z, P->d_b, P->d_red,
-                    P->d_small, P->d_act};
+                    P->d_small, P->d_act, P->d_y3, P->d_g3, P->d_w3};
     for (void* b : bufs) dev_free(b);
+    P->d_y3 = P->d_g3 = nullptr;
+    P->d_w3 = nullptr;
+    P->y3_elems = P->w3_elems = 0;
     P->d_U = P->d_W = P->d_stage = nullptr;
     P->d_wt = nullptr;
     P->d_V = P->d_Z = P->d_b = P->d_red = P->d_small = nullptr;

@@ -73,12 +73,17 @@ __host__ __device__ __forceinline__ cplx<To> ccast(cplx<Ti> a) { return {(To)a.x
 // block recurrence) column-major with leading dimension LR >= L (rows past L
 // zero): entry (i, j) of block k at [(k-1) L LR + j LR + i], so that the LR
 // lanes holding the rows of one solve load each column coalesced.
+//
+// 3D: block k (k = i1 = 1..n) holds the n L unknowns (i1 = k, i2, i3 = lo..hi)
+// at in-block index j = (i3 - lo) + L (i2 - 1); blocks are padded to B (a
+// multiple of 64) with identity rows.  The factor stores S_k^-1 for every k as
+// a dense B x B column-major matrix at fac_off + (k-1) B^2.
 struct SubDesc {
     int kind;            // ASP_SUB_M / R / L
     int p;               // layer index (1-based)
     int lo, hi, L;       // sweep lines of the extended grid
-    int LR;              // rows per solve wavefront (16 or 32, >= L)
-    int pad_;
+    int LR;              // 2D: rows per solve wavefront (16 or 32, >= L)
+    int B;               // 3D: padded block size (multiple of 64); 2D: 0
     int xs, xe;          // lines of X_p (output lines)
     int src_line;        // R: last line of X_{p-1};  L: first line of X_{p+1};  M: 0
     int phi, psi;        // zero region of the sweep-axis PML profile
@@ -86,6 +91,7 @@ struct SubDesc {
     long long tab_off;   // offset of this problem's tables in the table buffer
     long long tr_off;    // offset of its boundary-to-boundary map (R_p, L_p with 1 < p < m), else -1
     int wrow;            // R/L problems: row of its boundary data in the sweep buffer, else -1
+    long long vec_off;   // 3D: offset of this problem's per-entry vectors (B entries each)
 };
 
 // solve launch modes
@@ -171,6 +177,25 @@ struct asp_plan {
     double tbytes[ASP_K_COUNT] = {0};
     double tflops[ASP_K_COUNT] = {0};
 
+    // 3D: per-entry vectors of every auxiliary problem (B entries at vec_off):
+    //   e3[j]  = 1 / (s2(i2) s3(i3) h^2), the coupling between blocks k and k+1
+    //            divided by s1 at the half line between them
+    //   gv3[j] = R/L problems, on the line next to the Dirichlet data:
+    //            -s3(half line to the data) / (s2(i2) h^2); else 0
+    //   gi3[j] = i2 - 1 where gv3 is nonzero, else -1
+    int Bmax = 0;                 // largest padded block size
+    long long vec_elems = 0;
+    zd* d_e3 = nullptr;
+    zd* d_gv3 = nullptr;
+    int* d_gi3 = nullptr;
+    // 3D solve workspaces
+    void* d_y3 = nullptr;         // forward results / solution blocks [chunk][job][k][B][16]
+    void* d_g3 = nullptr;         // gathered M data, same layout
+    long long y3_elems = 0;
+    zd* d_w3 = nullptr;           // sweep planes [pingpong][side][n^2][ws]
+    long long w3_elems = 0;
+    int ws3 = 0;                  // right-hand-side stride of the planes (multiple of 16)
+
     // GMRES workspaces
     int kr_rhs = 0, kr_restart = 0;
     zd* d_V = nullptr;      // (restart+1) * nrhs * N
@@ -238,6 +263,41 @@ int sweep_wt_len(const asp_plan* P, int nrhs);
 hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const int* act, int nact,
                              hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// 3D auxiliary problems
+// ---------------------------------------------------------------------------
+// S_k = D_k - diag(E_k) S_{k-1}^-1 diag(E_k) into block k (0-based) of every job
+hipError_t launch_form3d(const asp_plan* P, const int* jobs, int njobs, int k, hipStream_t st);
+// one panel jp of the in-place block Gauss-Jordan inversion of block k
+// (panel step, then trailing update); Rbuf: njobs x 64 x Bmax, Dbuf: njobs x 64 x 64
+hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int jp, void* Rbuf,
+                       void* Dbuf, hipStream_t st);
+// M data on X_q gathered into the block layout of the forward pass
+hipError_t launch_gather3d(const asp_plan* P, const int* jobs, int njobs, const zd* r,
+                           const int* act, int nact, hipStream_t st);
+// one block step of the forward (fwd = 1) or backward pass over jobs
+struct Solve3Launch {
+    const int* jobs = nullptr;   // device job list
+    int njobs = 0;
+    bool two_sided = false;      // job 0 is an R problem, job 1 an L problem
+    const int* act = nullptr;
+    int nact = 0;
+    int in_mode = IN_GRID;       // IN_GRID: gathered data; IN_BOUNDARY: planes in Win
+    const zd* Win = nullptr;     // [job][n^2][ws3]
+    zd* Wout = nullptr;          // outgoing boundary plane (+ U) of every job, or NULL
+    int out_mode[2] = {OUT_GRID_STORE, OUT_GRID_STORE};
+    zd* out[2] = {nullptr, nullptr};
+    const zd* Ugrid = nullptr;
+};
+hipError_t launch_solve3d_step(const asp_plan* P, const Solve3Launch& L, int k, int fwd,
+                               hipStream_t st);
+// W[job][i1 + n i2][slot] = U on sweep line `line0` (job 0) and `line1` (job 1)
+hipError_t launch_plane3d(const asp_plan* P, const zd* U, int line0, int line1, zd* W,
+                          const int* act, int nact, hipStream_t st);
+// z = U + C on lines 1..split, z += C on lines split+1..upto
+hipError_t launch_combine3d(const asp_plan* P, zd* z, const zd* U, const zd* C, int split,
+                            int upto, const int* act, int nact, hipStream_t st);
+
 // timing of one launch: constructed before the launch, end() after it
 struct KTimer {
     asp_plan* P;
@@ -267,8 +327,15 @@ hipError_t launch_scale_vec(const zd* w, zd* v, const zd* scal, long long N, con
 // host-side pieces shared by the entry points
 asp_status ensure_apply_ws(asp_plan* P, int nrhs);
 asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
-// algorithmic bytes of one auxiliary problem's factor (n dense L x L blocks)
+// algorithmic bytes of one auxiliary problem's factor (n dense L x L blocks in
+// 2D, n dense nL x nL blocks in 3D)
 double factor_bytes_of(const asp_plan* P, const SubDesc& d);
+// 3D counterparts (apply3d.cpp)
+asp_status ensure_apply_ws3(asp_plan* P, int nrhs);
+size_t workspace_estimate3(const asp_plan* P, int nrhs);
+asp_status factor3d(asp_plan* P);
+asp_status apply3d_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
+asp_status subsolve3d(asp_plan* P, int idx, const void* in, void* out, int nrhs);
 
 // a launch bracketed by a KTimer of class cls
 #define ASP_TIMED(plan, cls, bytes, flops, call)        \

@@ -1,0 +1,687 @@
+// 3D auxiliary problems (Section 4.1, Algorithms 3 and 4).
+//
+// Reordered with the sweep axis fastest inside x1-blocks, a 3D auxiliary
+// problem on sweep lines lo..hi is block tridiagonal in i1 with n dense
+// blocks of size n L (the quasi-2D cross-section of one x1 index).  The
+// factorization runs the block recurrence
+//     S_1 = D_1,   S_k = D_k - E_k S_{k-1}^-1 E_k     (E_k diagonal)
+// and stores every S_k^-1; each inverse is an in-place blocked Gauss-Jordan
+// elimination whose panel and trailing updates are complex products of 64 x 64
+// tiles on the matrix cores.  A solve is the forward pass y_k = S_k^-1 (g_k -
+// E_k y_{k-1}) and the backward pass x_k = y_k - S_k^-1 E_{k+1} x_{k+1}, one
+// launch per block step, each step a product of S_k^-1 with 16 right-hand sides.
+//
+// The Gauss-Jordan elimination does not pivot: at a few points per wavelength
+// the blocks are close to diagonally dominant (the shift omega^2 h^2 / c^2 is
+// small next to the 6 of the diagonal), and a zero or non-finite pivot is
+// reported as a breakdown.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "asp_internal.h"
+
+namespace {
+
+constexpr int TB = 64;        // panel width of the inversion, edge of a tile
+constexpr int LDT = TB + 1;   // LDS row stride of a tile (complex entries)
+constexpr int NT = 256;       // threads of a factor or solve workgroup (4 waves)
+constexpr int RW = 16;        // right-hand sides per solve chunk (one matrix-core tile)
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// 16x16x4 matrix-core product-accumulate: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element v (0..3) of the result in lane l is entry
+// (row(l, v), l % 16) of the 16 x 16 product.  The FP32 instruction stacks the
+// four elements of a lane (rows 4 (l / 16) + v), the FP64 one interleaves them
+// (rows l / 16 + 4 v).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    using V = f32x4;
+    __device__ static __forceinline__ V mac(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct Mfma<double> {
+    using V = f64x4;
+    __device__ static __forceinline__ V mac(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+// complex 16 x 16 accumulator (real and imaginary planes)
+template <typename T>
+struct CTile {
+    typename Mfma<T>::V re, im;
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            re[v] = T(0);
+            im[v] = T(0);
+        }
+    }
+};
+
+// c += a b with complex operands split into four real products
+template <typename T>
+__device__ __forceinline__ void cmac(CTile<T>& c, cplx<T> a, cplx<T> b) {
+    c.re = Mfma<T>::mac(a.x, b.x, c.re);
+    c.re = Mfma<T>::mac(-a.y, b.y, c.re);
+    c.im = Mfma<T>::mac(a.x, b.y, c.im);
+    c.im = Mfma<T>::mac(a.y, b.x, c.im);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+// ---------------------------------------------------------------------------
+// 64 x 64 tiles: LDS copies with row stride LDT, products on the matrix cores
+// ---------------------------------------------------------------------------
+// S[r][c] = A(r0 + r, c0 + c) of a column-major matrix with leading dimension ld
+template <typename T>
+__device__ __forceinline__ void load_tile(cplx<T>* S, const cplx<T>* A, long long ld, int r0,
+                                          int c0) {
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+#pragma unroll 4
+    for (int e = 0; e < 16; ++e) {
+        const int c = cg + 4 * e;
+        S[r * LDT + c] = A[(long long)(c0 + c) * ld + r0 + r];
+    }
+}
+
+// C = P Q for tiles in LDS (P[r][k], Q[k][c]).  Wave w computes rows
+// 32 (w / 2) .. + 32 and columns 32 (w % 2) .. + 32 as four transposed 16 x 16
+// blocks: acc[a][b], lane l, element v is C(R0 + 16 b + l % 16, C0 + 16 a +
+// row(l, v)), so that a column of C leaves the lanes contiguously.
+template <typename T>
+__device__ __forceinline__ void tile_product(const cplx<T>* P, const cplx<T>* Q,
+                                             CTile<T> acc[2][2]) {
+    const int l = lane_id(), w = wave_id();
+    const int R0 = 32 * (w >> 1), C0 = 32 * (w & 1);
+    const int li = l & 15, lk = l >> 4;
+#pragma unroll 2
+    for (int k0 = 0; k0 < TB; k0 += 4) {
+        const int kq = k0 + lk;
+        cplx<T> qa[2], pb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) qa[a] = Q[kq * LDT + C0 + 16 * a + li];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) pb[b] = P[(R0 + 16 * b + li) * LDT + kq];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) cmac(acc[a][b], qa[a], pb[b]);
+    }
+}
+
+// global tile (column-major, leading dimension ld, origin r0, c0) <-> accumulators
+template <typename T>
+__device__ __forceinline__ void load_acc(CTile<T> acc[2][2], const cplx<T>* A, long long ld,
+                                         int r0, int c0) {
+    const int l = lane_id(), w = wave_id();
+    const int R0 = 32 * (w >> 1), C0 = 32 * (w & 1);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = R0 + 16 * b + (l & 15), c = C0 + 16 * a + Mfma<T>::row(l, v);
+                const cplx<T> x = A[(long long)(c0 + c) * ld + r0 + r];
+                acc[a][b].re[v] = x.x;
+                acc[a][b].im[v] = x.y;
+            }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_acc(cplx<T>* A, long long ld, int r0, int c0,
+                                          const CTile<T> acc[2][2], T sign) {
+    const int l = lane_id(), w = wave_id();
+    const int R0 = 32 * (w >> 1), C0 = 32 * (w & 1);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = R0 + 16 * b + (l & 15), c = C0 + 16 * a + Mfma<T>::row(l, v);
+                A[(long long)(c0 + c) * ld + r0 + r] =
+                    mk<T>(sign * acc[a][b].re[v], sign * acc[a][b].im[v]);
+            }
+}
+
+// In-place inverse of a 64 x 64 tile by Gauss-Jordan elimination without
+// pivoting.  Thread t holds row t % 64, columns t / 64 + 4 e (e = 0..15) in v;
+// the pivot row and column pass through LDS (double-buffered, one barrier per
+// pivot).  *bad is set for a zero or non-finite pivot.
+template <typename T>
+__device__ __forceinline__ void invert_tile(cplx<T> v[16], cplx<T>* rowbuf, cplx<T>* colbuf,
+                                            int* bad) {
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    const T tiny = sizeof(T) == 4 ? T(1e-36) : T(1e-300);
+    for (int piv = 0; piv < TB; ++piv) {
+        cplx<T>* rb = rowbuf + (piv & 1) * TB;
+        cplx<T>* cb = colbuf + (piv & 1) * TB;
+        if (r == piv)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) rb[cg + 4 * e] = v[e];
+        if ((piv & 3) == cg) {
+            // select by value: a pointer into v would move it to scratch memory
+            cplx<T> pc = v[0];
+#pragma unroll
+            for (int e = 1; e < 16; ++e) {
+                const bool hit = e == (piv >> 2);
+                pc.x = hit ? v[e].x : pc.x;
+                pc.y = hit ? v[e].y : pc.y;
+            }
+            cb[r] = pc;
+        }
+        __syncthreads();
+        const cplx<T> p = rb[piv];
+        const T p2 = abs2(p);
+        if (!(p2 > tiny) || !(p2 < T(1) / tiny)) *bad = 1;
+        const cplx<T> pinv = mk<T>(p.x / p2, -p.y / p2);
+        const cplx<T> cr = cb[r];
+        const cplx<T> crp = cr * pinv;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int c = cg + 4 * e;
+            if (r == piv) {
+                v[e] = (c == piv) ? pinv : v[e] * pinv;
+            } else if (c == piv) {
+                v[e] = -crp;
+            } else {
+                v[e] = v[e] - crp * rb[c];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// factorization
+// ---------------------------------------------------------------------------
+struct Form3Args {
+    const SubDesc* desc;
+    const int* jobs;
+    void* fac;
+    AxisTables ax;
+    const zd* subtab;
+    const double* ksq;
+    const zd* e3;
+    int n, k;
+    long long S;
+};
+
+// Block k of the symmetric-form operator of the auxiliary problem reordered
+// (x1-blocks, sweep axis fastest), minus the Schur term of the previous block.
+// Entry (r, c): 7-point couplings inside the cross-section, the diagonal with
+// all six half-line terms, identity on the padding.
+template <typename T>
+__global__ __launch_bounds__(256) void form3d_kernel(Form3Args a) {
+    const SubDesc d = a.desc[a.jobs[blockIdx.z]];
+    const int Bp = d.B, L = d.L, B = a.n * d.L;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (r >= Bp || c >= Bp) return;
+    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    zd val = mk(0.0, 0.0);
+    if (r >= B || c >= B) {
+        if (r == c) val = mk(1.0, 0.0);
+    } else {
+        const int k = a.k;
+        const int i3r = r % L, i2r = r / L, i3c = c % L, i2c = c / L;
+        const zd* sh3 = a.subtab + d.tab_off;     // s3 at half lines lo - 1/2 ..
+        const zd* ish3 = sh3 + L + 1;             // 1 / (s3 h^2)
+        const zd* is3 = sh3 + 2 * L + 1;          // 1 / s3
+        if (r == c) {
+            const zd s23 = a.ax.inv_s[i2r] * ish3[i3r];     // 1 / (s2 s3 h^2)
+            const zd s13 = a.ax.inv_s[k] * ish3[i3r];       // 1 / (s1 s3 h^2)
+            const zd s12 = a.ax.inv_s[k] * a.ax.inv_sh2[i2r];
+            const zd c1 = (a.ax.sh[k + 1] + a.ax.sh[k]) * s23;
+            const zd c2 = (a.ax.sh[i2r + 1] + a.ax.sh[i2r]) * s13;
+            const zd c3 = (sh3[i3r + 1] + sh3[i3r]) * s12;
+            const long long g = (long long)k + (long long)a.n * i2r + a.S * (d.lo - 1 + i3r);
+            val = ((a.ksq[g] * a.ax.inv_s[k]) * a.ax.inv_s[i2r]) * is3[i3r] - (c1 + c2 + c3);
+        } else if (i2r == i2c && (i3r - i3c == 1 || i3c - i3r == 1)) {
+            val = sh3[max(i3r, i3c)] * (a.ax.inv_s[k] * a.ax.inv_sh2[i2r]);
+        } else if (i3r == i3c && (i2r - i2c == 1 || i2c - i2r == 1)) {
+            val = a.ax.sh[max(i2r, i2c)] * (a.ax.inv_s[k] * ish3[i3r]);
+        }
+        if (k > 0) {
+            const zd* e = a.e3 + d.vec_off;
+            const cplx<T>* prev = A - (long long)Bp * Bp;
+            const zd sk = a.ax.sh[k];
+            const zd er = sk * e[r], ec = sk * e[c];
+            const zd pv = ccast<double>(prev[(long long)c * Bp + r]);
+            val = val - (er * pv) * ec;
+        }
+    }
+    A[(long long)c * Bp + r] = ccast<T>(val);
+}
+
+struct GjArgs {
+    const SubDesc* desc;
+    const int* jobs;
+    void* fac;
+    void* Rbuf;     // [job][Bmax][64]: the panel rows before the step
+    void* Dbuf;     // [job][64][64]: the inverse of the pivot tile
+    int* flag;
+    long long rstride;
+    int k, jp, ntmax;
+};
+
+// Panel step of panel jp: every workgroup inverts the pivot tile D = A[J,J];
+// row-tile workgroups set A[I,J] = -A[I,J] D^-1, column-tile workgroups keep
+// A[J,C] in Rbuf and set A[J,C] = D^-1 A[J,C]; the workgroup of row tile jp
+// keeps D^-1 for the update step.
+template <typename T>
+__global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
+    __shared__ cplx<T> sD[TB * LDT];
+    __shared__ cplx<T> sA[TB * LDT];
+    __shared__ cplx<T> rowbuf[2 * TB], colbuf[2 * TB];
+    __shared__ int bad;
+    const int js = blockIdx.y;
+    const SubDesc d = a.desc[a.jobs[js]];
+    const int Bp = d.B, nt = Bp / TB;
+    if (a.jp >= nt) return;
+    const bool rowt = (int)blockIdx.x < a.ntmax;
+    const int t = rowt ? blockIdx.x : blockIdx.x - a.ntmax;
+    if (t >= nt || (!rowt && t == a.jp)) return;
+    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    const int J0 = a.jp * TB;
+    if (threadIdx.x == 0) bad = 0;
+    cplx<T> v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = A[(long long)(J0 + cg + 4 * e) * Bp + J0 + r];
+    invert_tile(v, rowbuf, colbuf, &bad);
+    if (rowt && t == a.jp) {
+        cplx<T>* D = static_cast<cplx<T>*>(a.Dbuf) + (long long)js * TB * TB;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) D[(cg + 4 * e) * TB + r] = v[e];
+        if (threadIdx.x == 0 && bad) *a.flag = 1;
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sD[r * LDT + cg + 4 * e] = v[e];
+    CTile<T> acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j].zero();
+    if (rowt) {
+        load_tile(sA, A, Bp, t * TB, J0);
+        __syncthreads();
+        tile_product(sA, sD, acc);
+        store_acc(A, Bp, t * TB, J0, acc, T(-1));
+    } else {
+        load_tile(sA, A, Bp, J0, t * TB);
+        __syncthreads();
+        cplx<T>* R = static_cast<cplx<T>*>(a.Rbuf) + js * a.rstride;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int c = cg + 4 * e;
+            R[(long long)(t * TB + c) * TB + r] = sA[r * LDT + c];
+        }
+        tile_product(sD, sA, acc);
+        store_acc(A, Bp, J0, t * TB, acc, T(1));
+    }
+}
+
+// Trailing update of panel jp: A[I,C] += A[I,J] R[J,C] for I, C outside the
+// panel; the pivot tile becomes D^-1.
+template <typename T>
+__global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
+    __shared__ cplx<T> sP[TB * LDT];
+    __shared__ cplx<T> sQ[TB * LDT];
+    const int js = blockIdx.y;
+    const SubDesc d = a.desc[a.jobs[js]];
+    const int Bp = d.B, nt = Bp / TB;
+    if (a.jp >= nt) return;
+    const int ti = blockIdx.x % a.ntmax, tj = blockIdx.x / a.ntmax;
+    if (ti >= nt || tj >= nt) return;
+    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    const int J0 = a.jp * TB;
+    if (tj == a.jp) {
+        if (ti == a.jp) {
+            const cplx<T>* D = static_cast<const cplx<T>*>(a.Dbuf) + (long long)js * TB * TB;
+            const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int c = cg + 4 * e;
+                A[(long long)(J0 + c) * Bp + J0 + r] = D[c * TB + r];
+            }
+        }
+        return;
+    }
+    if (ti == a.jp) return;
+    const cplx<T>* R = static_cast<const cplx<T>*>(a.Rbuf) + js * a.rstride;
+    load_tile(sP, A, Bp, ti * TB, J0);
+    load_tile(sQ, R, TB, 0, tj * TB);
+    CTile<T> acc[2][2];
+    load_acc(acc, A, Bp, ti * TB, tj * TB);
+    __syncthreads();
+    tile_product(sP, sQ, acc);
+    store_acc(A, Bp, ti * TB, tj * TB, acc, T(1));
+}
+
+// ---------------------------------------------------------------------------
+// solves
+// ---------------------------------------------------------------------------
+struct Solve3Args {
+    const SubDesc* desc;
+    const int* jobs;
+    int njobs;
+    const void* fac;
+    void* Y;               // [chunk][job][k][Bmax][RW]
+    const void* G;         // gathered M data, same layout
+    long long yj;          // entries per (chunk, job)
+    int Bmax;
+    int k, fwd;
+    int n;
+    long long N, S;
+    AxisTables ax;
+    const zd* e3;
+    const zd* gv3;
+    const int* gi3;
+    int in_mode;
+    const zd* Win;
+    zd* Wout;
+    int ws;
+    int two_sided;
+    int out_mode0, out_mode1;
+    zd* out0;
+    zd* out1;
+    const zd* U;
+    const int* act;
+    int nact;
+};
+
+// One block step for 16 rows of every job and one chunk of 16 right-hand
+// sides; the four waves split the inner dimension and reduce through LDS in a
+// fixed order.
+template <typename T>
+__global__ __launch_bounds__(NT) void solve3d_step_kernel(Solve3Args a) {
+    __shared__ cplx<T> red[4][64][4];
+    const int js = blockIdx.y, chunk = blockIdx.z;
+    const SubDesc d = a.desc[a.jobs[js]];
+    const int Bp = d.B, L = d.L;
+    const int r0 = blockIdx.x * 16;
+    if (r0 >= Bp) return;
+    const int k = a.k;
+    const int l = lane_id(), w = wave_id();
+    const int li = l & 15, lk = l >> 4;
+    const cplx<T>* Mk = static_cast<const cplx<T>*>(a.fac) + d.fac_off + (long long)k * Bp * Bp;
+    cplx<T>* Yc = static_cast<cplx<T>*>(a.Y) + ((long long)chunk * a.njobs + js) * a.yj;
+    const long long blk = (long long)a.Bmax * RW;
+    const zd* e = a.e3 + d.vec_off;
+    const int slot_l = chunk * RW + li;       // this lane's right-hand side in the B operand
+    const bool live_l = slot_l < a.nact;
+    CTile<T> acc;
+    acc.zero();
+    const int kq = Bp / 4;
+    const int cbeg = w * kq;
+    const bool skip = !a.fwd && k == a.n - 1;   // x_n = y_n
+    if (!skip) {
+        if (a.fwd) {
+            const cplx<T>* yp = Yc + (long long)(k - 1) * blk;
+            const zd sk = a.ax.sh[k];                      // coupling of blocks k-1, k
+            const bool has_prev = k > 0;
+            if (a.in_mode == IN_GRID) {
+                const cplx<T>* g = static_cast<const cplx<T>*>(a.G) +
+                                   ((long long)chunk * a.njobs + js) * a.yj + (long long)k * blk;
+                for (int c0 = cbeg; c0 < cbeg + kq; c0 += 4) {
+                    const int c = c0 + lk;
+                    const cplx<T> m = Mk[(long long)c * Bp + r0 + li];
+                    cplx<T> t = g[(long long)c * RW + li];
+                    if (has_prev) t = t - ccast<T>(sk * e[c]) * yp[(long long)c * RW + li];
+                    cmac(acc, m, t);
+                }
+            } else {
+                const zd* gv = a.gv3 + d.vec_off;
+                const int* gi = a.gi3 + d.vec_off;
+                const zd* win = a.Win + (long long)js * a.S * a.ws;
+                const zd is1 = a.ax.inv_s[k];
+                for (int c0 = cbeg; c0 < cbeg + kq; c0 += 4) {
+                    const int c = c0 + lk;
+                    const cplx<T> m = Mk[(long long)c * Bp + r0 + li];
+                    cplx<T> t = mk<T>(T(0), T(0));
+                    const int i2 = gi[c];
+                    if (i2 >= 0 && live_l)
+                        t = ccast<T>((is1 * gv[c]) *
+                                     win[((long long)k + (long long)a.n * i2) * a.ws + slot_l]);
+                    if (has_prev) t = t - ccast<T>(sk * e[c]) * yp[(long long)c * RW + li];
+                    cmac(acc, m, t);
+                }
+            }
+        } else {
+            const cplx<T>* xn = Yc + (long long)(k + 1) * blk;
+            const zd sk = a.ax.sh[k + 1];                  // coupling of blocks k, k+1
+            for (int c0 = cbeg; c0 < cbeg + kq; c0 += 4) {
+                const int c = c0 + lk;
+                const cplx<T> m = Mk[(long long)c * Bp + r0 + li];
+                const cplx<T> t = ccast<T>(sk * e[c]) * xn[(long long)c * RW + li];
+                cmac(acc, m, t);
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][l][v] = mk<T>(acc.re[v], acc.im[v]);
+    __syncthreads();
+    // wave w finishes element v = w of every lane: row r0 + row(l, w), rhs l % 16
+    cplx<T> s = red[0][l][w];
+    s = s + red[1][l][w];
+    s = s + red[2][l][w];
+    s = s + red[3][l][w];
+    const int row = r0 + Mfma<T>::row(l, w);
+    const int slot = chunk * RW + li;
+    cplx<T>* yk = Yc + (long long)k * blk + (long long)row * RW + li;
+    if (a.fwd) {
+        *yk = s;
+        return;
+    }
+    const cplx<T> x = skip ? *yk : *yk - s;
+    *yk = x;
+    const int B = a.n * L;
+    if (row >= B || slot >= a.nact) return;
+    const int i3l = row % L, i2 = row / L;
+    const int line = d.lo + i3l;
+    if (line < d.xs || line > d.xe) return;
+    const int rhs = a.act ? a.act[slot] : slot;
+    const long long gidx = (long long)rhs * a.N + k + (long long)a.n * i2 + a.S * (line - 1);
+    const zd xv = ccast<double>(x);
+    const int side = a.two_sided ? js : 0;
+    const int mode = side ? a.out_mode1 : a.out_mode0;
+    zd* out = side ? a.out1 : a.out0;
+    if (mode == OUT_GRID_STORE) out[gidx] = xv;
+    else if (mode == OUT_GRID_ADD_U) out[gidx] = a.U[gidx] + xv;
+    else out[gidx] = out[gidx] + xv;
+    if (a.Wout) {
+        // the data entering the next problem of this sweep: R_p hands over its
+        // last line, L_p its first line, each with u~_{p,p} added
+        const int hand = (d.kind == ASP_SUB_R) ? d.xe : d.xs;
+        if (line == hand)
+            a.Wout[((long long)js * a.S + k + (long long)a.n * i2) * a.ws + slot] = a.U[gidx] + xv;
+    }
+}
+
+// G[chunk][job][k][j][16] = r at block k, entry j if its line lies in X_q, else 0
+template <typename T>
+__global__ __launch_bounds__(256) void gather3d_kernel(const SubDesc* desc, const int* jobs,
+                                                       int njobs, const zd* r, const int* act,
+                                                       int nact, cplx<T>* G, long long yj,
+                                                       int Bmax, int n, long long N, long long S) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int c = idx >> 4, li = idx & 15;
+    const int k = blockIdx.y;
+    const int js = blockIdx.z % njobs, chunk = blockIdx.z / njobs;
+    if (c >= Bmax) return;
+    const SubDesc d = desc[jobs[js]];
+    zd v = mk(0.0, 0.0);
+    const int slot = chunk * RW + li;
+    if (c < n * d.L && slot < nact) {
+        const int line = d.lo + c % d.L;
+        if (line >= d.xs && line <= d.xe) {
+            const int rhs = act ? act[slot] : slot;
+            v = r[(long long)rhs * N + k + (long long)n * (c / d.L) + S * (line - 1)];
+        }
+    }
+    G[((long long)chunk * njobs + js) * yj + ((long long)k * Bmax + c) * RW + li] = ccast<T>(v);
+}
+
+// W[job][i1 + n i2][slot] = U(i1, i2, line_job)
+__global__ __launch_bounds__(256) void plane3d_kernel(const zd* U, int line0, int line1, zd* W,
+                                                      int ws, const int* act, int nact, int n,
+                                                      long long N, long long S) {
+    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= S) return;
+    const int slot = blockIdx.y, job = blockIdx.z;
+    const int rhs = act ? act[slot] : slot;
+    const int line = job ? line1 : line0;
+    W[((long long)job * S + p) * ws + slot] = U[(long long)rhs * N + S * (line - 1) + p];
+}
+
+// z = U + C on lines 1..split, z += C on lines split+1..upto
+__global__ __launch_bounds__(256) void combine3d_kernel(zd* z, const zd* U, const zd* C, int split,
+                                                        int upto, const int* act, long long N,
+                                                        long long S) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= S * upto) return;
+    const int rhs = act ? act[blockIdx.y] : blockIdx.y;
+    const long long g = (long long)rhs * N + i;
+    const int line = (int)(i / S) + 1;
+    z[g] = (line <= split) ? U[g] + C[g] : z[g] + C[g];
+}
+
+AxisTables axis_of(const asp_plan* P) {
+    AxisTables t;
+    t.sh = P->d_axis;
+    t.inv_sh2 = P->d_axis + P->n + 1;
+    t.inv_s = P->d_axis + 2 * P->n + 1;
+    return t;
+}
+
+}  // namespace
+
+hipError_t launch_form3d(const asp_plan* P, const int* jobs, int njobs, int k, hipStream_t st) {
+    Form3Args a;
+    a.desc = P->d_desc;
+    a.jobs = jobs;
+    a.fac = P->d_fac;
+    a.ax = axis_of(P);
+    a.subtab = P->d_subtab;
+    a.ksq = P->d_ksq;
+    a.e3 = P->d_e3;
+    a.n = P->n;
+    a.k = k;
+    a.S = P->S;
+    dim3 grid((P->Bmax + 255) / 256, P->Bmax, njobs);
+    if (P->prec == ASP_PREC_FP32)
+        hipLaunchKernelGGL(form3d_kernel<float>, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(form3d_kernel<double>, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int jp, void* Rbuf,
+                       void* Dbuf, hipStream_t st) {
+    GjArgs a;
+    a.desc = P->d_desc;
+    a.jobs = jobs;
+    a.fac = P->d_fac;
+    a.Rbuf = Rbuf;
+    a.Dbuf = Dbuf;
+    a.flag = P->d_flag;
+    a.rstride = (long long)P->Bmax * TB;
+    a.k = k;
+    a.jp = jp;
+    a.ntmax = P->Bmax / TB;
+    dim3 g1(2 * a.ntmax, njobs), g2(a.ntmax * a.ntmax, njobs);
+    if (P->prec == ASP_PREC_FP32) {
+        hipLaunchKernelGGL(gj_panel_kernel<float>, g1, dim3(NT), 0, st, a);
+        hipLaunchKernelGGL(gj_update_kernel<float>, g2, dim3(NT), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(gj_panel_kernel<double>, g1, dim3(NT), 0, st, a);
+        hipLaunchKernelGGL(gj_update_kernel<double>, g2, dim3(NT), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather3d(const asp_plan* P, const int* jobs, int njobs, const zd* r,
+                           const int* act, int nact, hipStream_t st) {
+    const int chunks = (nact + RW - 1) / RW;
+    const long long yj = (long long)P->n * P->Bmax * RW;
+    dim3 grid((P->Bmax * RW + 255) / 256, P->n, njobs * chunks);
+    if (P->prec == ASP_PREC_FP32)
+        hipLaunchKernelGGL(gather3d_kernel<float>, grid, dim3(256), 0, st, P->d_desc, jobs, njobs, r,
+                           act, nact, static_cast<zf*>(P->d_g3), yj, P->Bmax, P->n, P->N, P->S);
+    else
+        hipLaunchKernelGGL(gather3d_kernel<double>, grid, dim3(256), 0, st, P->d_desc, jobs, njobs,
+                           r, act, nact, static_cast<zd*>(P->d_g3), yj, P->Bmax, P->n, P->N, P->S);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve3d_step(const asp_plan* P, const Solve3Launch& L, int k, int fwd,
+                               hipStream_t st) {
+    Solve3Args a;
+    a.desc = P->d_desc;
+    a.jobs = L.jobs;
+    a.njobs = L.njobs;
+    a.fac = P->d_fac;
+    a.Y = P->d_y3;
+    a.G = P->d_g3;
+    a.yj = (long long)P->n * P->Bmax * RW;
+    a.Bmax = P->Bmax;
+    a.k = k;
+    a.fwd = fwd;
+    a.n = P->n;
+    a.N = P->N;
+    a.S = P->S;
+    a.ax = axis_of(P);
+    a.e3 = P->d_e3;
+    a.gv3 = P->d_gv3;
+    a.gi3 = P->d_gi3;
+    a.in_mode = L.in_mode;
+    a.Win = L.Win;
+    a.Wout = L.Wout;
+    a.ws = P->ws3;
+    a.two_sided = L.two_sided ? 1 : 0;
+    a.out_mode0 = L.out_mode[0];
+    a.out_mode1 = L.out_mode[1];
+    a.out0 = L.out[0];
+    a.out1 = L.out[1];
+    a.U = L.Ugrid;
+    a.act = L.act;
+    a.nact = L.nact;
+    const int chunks = (L.nact + RW - 1) / RW;
+    dim3 grid(P->Bmax / 16, L.njobs, chunks);
+    if (P->prec == ASP_PREC_FP32)
+        hipLaunchKernelGGL(solve3d_step_kernel<float>, grid, dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL(solve3d_step_kernel<double>, grid, dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane3d(const asp_plan* P, const zd* U, int line0, int line1, zd* W,
+                          const int* act, int nact, hipStream_t st) {
+    dim3 grid((unsigned)((P->S + 255) / 256), nact, 2);
+    hipLaunchKernelGGL(plane3d_kernel, grid, dim3(256), 0, st, U, line0, line1, W, P->ws3, act,
+                       nact, P->n, P->N, P->S);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine3d(const asp_plan* P, zd* z, const zd* U, const zd* C, int split,
+                            int upto, const int* act, int nact, hipStream_t st) {
+    const long long cnt = P->S * upto;
+    dim3 grid((unsigned)((cnt + 255) / 256), nact);
+    hipLaunchKernelGGL(combine3d_kernel, grid, dim3(256), 0, st, z, U, C, split, upto, act, P->N,
+                       P->S);
+    return hipGetLastError();
+}

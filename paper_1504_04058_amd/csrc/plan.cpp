@@ -194,23 +194,36 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     }
     P->LR_M = rows_per_wave(maxL_M);
     P->LR_RL = rows_per_wave(maxL_RL > 0 ? maxL_RL : 1);
-    long long fac_off = 0, tab_off = 0, tr_off = 0;
+    long long fac_off = 0, tab_off = 0, tr_off = 0, vec_off = 0;
+    P->Bmax = 0;
     for (size_t s = 0; s < P->subs.size(); ++s) {
         SubDesc& d = P->subs[s];
-        d.LR = (d.kind == ASP_SUB_M) ? P->LR_M : P->LR_RL;
         d.fac_off = fac_off;
         d.tab_off = tab_off;
-        fac_off += (long long)n * d.L * d.LR;
         tab_off += sub_table_len(d.L);
         d.wrow = (d.kind == ASP_SUB_M) ? -1 : (int)s - P->m;
-        // the sweeps step through R_p and L_p for 1 < p < m with their dense maps
-        if (d.kind != ASP_SUB_M && d.p > 1 && d.p < P->m) {
-            d.tr_off = tr_off;
-            tr_off += (long long)n * n;
+        d.tr_off = -1;
+        d.vec_off = -1;
+        if (dim == 2) {
+            d.LR = (d.kind == ASP_SUB_M) ? P->LR_M : P->LR_RL;
+            d.B = 0;
+            fac_off += (long long)n * d.L * d.LR;
+            // the sweeps step through R_p and L_p for 1 < p < m with their dense maps
+            if (d.kind != ASP_SUB_M && d.p > 1 && d.p < P->m) {
+                d.tr_off = tr_off;
+                tr_off += (long long)n * n;
+            }
         } else {
-            d.tr_off = -1;
+            // dense x1-blocks of n L unknowns, padded to a multiple of 64
+            d.LR = 0;
+            d.B = (n * d.L + 63) / 64 * 64;
+            d.vec_off = vec_off;
+            vec_off += d.B;
+            fac_off += (long long)n * d.B * d.B;
+            P->Bmax = std::max(P->Bmax, d.B);
         }
     }
+    P->vec_elems = vec_off;
     const size_t esz = (P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd));
     P->fac_elems = fac_off;
     P->fac_bytes = (size_t)fac_off * esz;
@@ -233,6 +246,33 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     }
     std::vector<double> ksq((size_t)P->N);
     for (long long i = 0; i < P->N; ++i) ksq[i] = (omega * omega) / (P->c[i] * P->c[i]);
+    // 3D per-entry vectors: the x1 coupling without its s1 factor, and the
+    // Dirichlet data weights of R/L problems (on their first / last line)
+    std::vector<zd> e3((size_t)vec_off), gv3((size_t)vec_off);
+    std::vector<int> gi3((size_t)vec_off, -1);
+    if (dim == 3) {
+        for (size_t s = 0; s < P->subs.size(); ++s) {
+            const SubDesc& d = P->subs[s];
+            const int data_line = d.kind == ASP_SUB_R ? 0 : (d.kind == ASP_SUB_L ? d.L - 1 : -1);
+            const cd s_data = d.kind == ASP_SUB_R ? P->sub_half[s][0] : P->sub_half[s][d.L];
+            for (int j = 0; j < d.B; ++j) {
+                zd ev = mk(0.0, 0.0), gv = mk(0.0, 0.0);
+                int gi = -1;
+                if (j < n * d.L) {
+                    const int i3 = j % d.L, i2 = j / d.L;
+                    const cd s2 = P->ax_int[i2], s3 = P->sub_int[s][i3];
+                    ev = to_zd(1.0 / (s2 * s3 * h2));
+                    if (i3 == data_line) {
+                        gv = to_zd(-s_data / (s2 * h2));
+                        gi = i2;
+                    }
+                }
+                e3[d.vec_off + j] = ev;
+                gv3[d.vec_off + j] = gv;
+                gi3[d.vec_off + j] = gi;
+            }
+        }
+    }
     P->host_only = (o.host_only != 0);
     if (P->host_only) {
         *out = P;
@@ -242,6 +282,12 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     // a launch takes a contiguous range of it
     std::vector<int> jobs(P->subs.size());
     for (size_t s = 0; s < P->subs.size(); ++s) jobs[s] = (int)s;
+    // 3D: sweep step t = 1..m-1 runs R_{t+1} and L_{m-t} together (two entries each)
+    if (dim == 3)
+        for (int t = 1; t <= P->m - 1; ++t) {
+            jobs.push_back(P->idx_R(t + 1));
+            jobs.push_back(P->idx_L(P->m - t));
+        }
 
     asp_status st;
     if ((st = upload(P, &P->d_axis, axis.data(), axis.size())) != ASP_OK) return fail(st, P->err.c_str());
@@ -249,6 +295,11 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if ((st = upload(P, &P->d_ksq, ksq.data(), ksq.size())) != ASP_OK) return fail(st, P->err.c_str());
     if ((st = upload(P, &P->d_desc, P->subs.data(), P->subs.size())) != ASP_OK) return fail(st, P->err.c_str());
     if ((st = upload(P, &P->d_jobs, jobs.data(), jobs.size())) != ASP_OK) return fail(st, P->err.c_str());
+    if (dim == 3) {
+        if ((st = upload(P, &P->d_e3, e3.data(), e3.size())) != ASP_OK) return fail(st, P->err.c_str());
+        if ((st = upload(P, &P->d_gv3, gv3.data(), gv3.size())) != ASP_OK) return fail(st, P->err.c_str());
+        if ((st = upload(P, &P->d_gi3, gi3.data(), gi3.size())) != ASP_OK) return fail(st, P->err.c_str());
+    }
     if (hipMalloc(reinterpret_cast<void**>(&P->d_flag), sizeof(int)) != hipSuccess)
         return fail(ASP_ERR_OOM, "hipMalloc failed");
     // the host vectors above are released on return: finish the copies first
@@ -265,7 +316,8 @@ extern "C" void asp_destroy(asp_plan* P) {
     }
     void* bufs[] = {P->d_ksq, P->d_axis, P->d_subtab, P->d_desc, P->d_jobs, P->d_fac, P->d_flag,
                     P->d_T, P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_y, P->d_V, P->d_Z, P->d_b,
-                    P->d_red, P->d_small, P->d_act};
+                    P->d_red, P->d_small, P->d_act, P->d_e3, P->d_gv3, P->d_gi3, P->d_y3,
+                    P->d_g3, P->d_w3};
     (void)hipStreamSynchronize(P->stream);
     for (void* b : bufs)
         if (b) (void)hipFree(b);

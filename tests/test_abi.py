@@ -113,3 +113,36 @@ def test_host_only_plan_refuses_device_calls(L):
         assert L.asp_apply(plan, None, None, 1) == asp.ASP_ERR_ARG
     finally:
         asp.asp_destroy(plan)
+
+
+@pytest.mark.parametrize("dim,n,b,gamma,prec", [(2, 1023, 4, 12, 1), (2, 63, 4, 12, 0),
+                                                (3, 63, 4, 8, 1), (3, 31, 4, 8, 0)])
+def test_planned_factor_bytes(dim, n, b, gamma, prec):
+    """The planned factor size: 2D, n blocks of L x LR per problem (LR = 16 or
+    32 rows) plus an n x n boundary map for R_p, L_p with 1 < p < m; 3D, n dense
+    blocks of B x B with B = n L rounded up to a multiple of 64."""
+    c = np.ones(n ** dim)
+    plan = asp.asp_setup(dim, c, 2 * np.pi * 4, n, b, gamma, prec=prec, host_only=True)
+    try:
+        info = asp.asp_info(plan)
+    finally:
+        asp.asp_destroy(plan)
+    esz = 8 if prec == 1 else 16
+    subs = partition.subproblems(n, b, gamma)
+    m = len(partition.layers(n, b, gamma))
+    want = 0
+    for kind in ("M", "R", "L"):
+        Ls = [s.hi - s.lo + 1 for s in subs[kind]]
+        for s, L in zip(subs[kind], Ls):
+            if dim == 2:
+                LR = 16 if max(Ls) <= 16 else 32
+                want += n * L * LR
+                if kind != "M" and 1 < s.p < m:
+                    want += n * n
+            else:
+                B = -(-n * L // 64) * 64
+                want += n * B * B
+    assert info["factor_bytes"] == want * esz
+    assert info["factored"] == 0
+    if dim == 3 and n == 63 and prec == 1:
+        assert 13.9e9 < info["factor_bytes"] < 15.0e9     # 13.9 GB unpadded, ~3% padding
