@@ -182,12 +182,10 @@ struct asp_plan {
     //            divided by s1 at the half line between them
     //   gv3[j] = R/L problems, on the line next to the Dirichlet data:
     //            -s3(half line to the data) / (s2(i2) h^2); else 0
-    //   gi3[j] = i2 - 1 where gv3 is nonzero, else -1
     int Bmax = 0;                 // largest padded block size
     long long vec_elems = 0;
     zd* d_e3 = nullptr;
     zd* d_gv3 = nullptr;
-    int* d_gi3 = nullptr;
     // 3D solve workspaces
     void* d_y3 = nullptr;         // forward results / solution blocks [chunk][job][k][B][16]
     void* d_g3 = nullptr;         // gathered M data, same layout

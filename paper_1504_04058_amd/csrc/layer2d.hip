@@ -14,6 +14,7 @@
 // y_k = S_k^-1 (g_k - E_{k-1} y_{k-1}) and the backward sweep
 // v_k = y_k - S_k^-1 E_k v_{k+1}.
 #include "asp_internal.h"
+#include "mfma.h"
 
 namespace {
 
@@ -162,12 +163,13 @@ struct SolveArgs {
     long long N;
 };
 
-constexpr int SB = 256;        // threads per solve workgroup
+constexpr int SB = 1024;       // threads per solve workgroup (16 wavefronts: one block
+                               // of a problem in LDS feeds 4 wavefronts per SIMD)
 constexpr int SRB = 64;        // right-hand sides per solve workgroup
 
 template <int LR> struct SolveShape;
-template <> struct SolveShape<32> { static constexpr int RG = 4, RPT = 2; };
-template <> struct SolveShape<16> { static constexpr int RG = 2, RPT = 2; };
+template <> struct SolveShape<32> { static constexpr int RG = 2, RPT = 1; };
+template <> struct SolveShape<16> { static constexpr int RG = 1, RPT = 1; };
 
 template <typename T, int LR>
 __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
@@ -232,6 +234,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // the factor columns past L are read against zero vectors: clear both once
     for (int e = tid; e < 2 * SRB * LR; e += SB) (&tb[0][0][0])[e] = mk<T>(0, 0);
     for (int e = tid; e < 2 * FMAX; e += SB) (&Fs[0][0])[e] = mk<T>(0, 0);
+    __syncthreads();   // the first stash writes entries another thread cleared
     const int LP = (L + 3) & ~3;
     cplx<T> pf[FPT];
     // loads below are unconditional (from clamped, always valid addresses) and
@@ -293,11 +296,15 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
             for (int j = 0; j < RPT; ++j) gv[q][j] = inp[q][j][(long long)(k - 1) * ink];
     };
 
+    // unit data enters at i1 = slot + 1 >= ch SRB + 1: the forward results of
+    // the blocks before the chunk's first column are zero, so the forward pass
+    // starts there and the backward pass reads no results before it
+    const int kstart = (a.in_mode == IN_UNIT) ? min(ch * SRB + 1, n) : 1;
     zd gin[RG][RPT];
-    load_in(1, gin);
-    zd shv = a.ax.sh[0], isv = a.ax.inv_sh2[0];
-    fetch(0);
-    stash(1);
+    load_in(kstart, gin);
+    zd shv = a.ax.sh[kstart - 1], isv = a.ax.inv_sh2[kstart - 1];
+    fetch(kstart - 1);
+    stash(kstart & 1);
     __syncthreads();
 
     // forward sweep: y_k = S_k^-1 (g_k - E_{k-1} y_{k-1}); block k sits in ring slot k & 1
@@ -306,7 +313,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     for (int q = 0; q < RG; ++q)
 #pragma unroll
         for (int j = 0; j < RPT; ++j) yk[q][j] = mk<T>(0, 0);
-    for (int k = 1; k <= n; ++k) {
+    for (int k = kstart; k <= n; ++k) {
         const int buf = k & 1;
         zd gnx[RG][RPT];
         zd shn = shv, isn = isv;
@@ -379,11 +386,14 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
             for (int j = 0; j < RPT; ++j) av[q][j] = addp[q][j][(long long)(k - 1) * addk];
     };
     auto load_y = [&](int k, cplx<T> (&yv)[RG][RPT]) {
+        const long long kk = max(k, kstart);     // blocks before kstart: y = 0
 #pragma unroll
         for (int q = 0; q < RG; ++q)
 #pragma unroll
-            for (int j = 0; j < RPT; ++j)
-                yv[q][j] = Y[((long long)(k - 1) * SRB + cgi * RPT + j) * LR + i0 + q];
+            for (int j = 0; j < RPT; ++j) {
+                const cplx<T> yv0 = Y[((kk - 1) * SRB + cgi * RPT + j) * LR + i0 + q];
+                yv[q][j] = (k >= kstart) ? yv0 : mk<T>(0, 0);
+            }
     };
     auto emit = [&](int k, const cplx<T> (&v)[RG][RPT], const zd (&av)[RG][RPT]) {
 #pragma unroll
@@ -482,58 +492,70 @@ struct SweepArgs {
     long long N;
 };
 
-constexpr int SW_ROWS = 64;    // output rows (i1) per block: one per lane
-constexpr int SW_RT = 8;       // right-hand sides per block
+constexpr int SW_ROWS = 16;    // output rows (i1) per block: one matrix-core tile
+constexpr int SW_RT = 32;      // right-hand sides per block: two tiles
+constexpr int SW_W = 8;        // wavefronts per block, splitting the columns of T
 
-template <typename T> struct SweepWaves { static constexpr int value = sizeof(T) == 4 ? 16 : 8; };
-
-// A block computes 64 consecutive outputs i1 for 8 right-hand sides.  Its
-// wavefronts split the reduction over the columns c of T; per column a
-// wavefront makes one coalesced load of T(i1, c) and one wave-uniform load of
-// the 8 inputs.  The partial sums meet in LDS and are added in wavefront order
-// (fixed, so the result does not depend on scheduling).  Blocks that share a
-// row tile are 16 block ids apart and so run on the same XCD, sharing its L2
-// copy of T.
+// W_out = T W_in for 16 outputs i1 and 32 right-hand sides: a complex product
+// on the matrix cores.  Each wavefront takes a contiguous eighth of the
+// columns of T, four k-steps of operands in flight at a time; the partial
+// tiles meet in LDS and are added in wavefront order (fixed, so a result does
+// not depend on the other right-hand sides or on scheduling).  The two blocks
+// of a row tile are 64 block ids apart and so share an XCD and its L2 copy of T.
 template <typename T>
-__global__ __launch_bounds__(1024) void sweep_step_kernel(SweepArgs a) {
-    constexpr int NW = SweepWaves<T>::value;
-    __shared__ cplx<T> red[NW][SW_RT][SW_ROWS];
+__global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
+    __shared__ cplx<T> red[SW_W][2][64][4];
     const int side = blockIdx.z;
     const int n = a.n;
-    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = l & 15, lk = l >> 4;
     const int k0 = blockIdx.x * SW_ROWS;
-    const int k = k0 + lane;
     const int s0 = blockIdx.y * SW_RT;
+    if (s0 >= a.nact) return;
     const cplx<T>* __restrict__ Tm = reinterpret_cast<const cplx<T>*>(a.T) + a.t_off[side];
-    const cplx<T>* __restrict__ Wi = reinterpret_cast<const cplx<T>*>(a.Wt_in[side]) + s0;
+    const cplx<T>* __restrict__ Wi = reinterpret_cast<const cplx<T>*>(a.Wt_in[side]);
     const int ws = a.ws;
-    const int kk = k < n ? k : n - 1;   // rows past n repeat the last one (not stored)
-    const int per = (n + NW - 1) / NW;
-    const int cb = wv * per, ce = min(n, cb + per);
-    cplx<T> acc[SW_RT];
+    const int kr = min(k0 + li, n - 1);               // rows past n repeat the last (not stored)
+    const int per = (n + 16 * SW_W - 1) / (16 * SW_W) * 16;
+    const int cb = wv * per;
+    CTile<T> acc[2];
+    acc[0].zero();
+    acc[1].zero();
+    for (int c0 = cb; c0 < cb + per; c0 += 16) {
+        cplx<T> av[4], bv[4][2];
 #pragma unroll
-    for (int j = 0; j < SW_RT; ++j) acc[j] = mk<T>(0, 0);
-#pragma unroll 4
-    for (int c = cb; c < ce; ++c) {
-        const cplx<T> t = Tm[(long long)c * n + kk];
-        const cplx<T>* wc = Wi + (long long)c * ws;
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + 4 * u + lk;
+            const int cc = min(c, n - 1);
+            av[u] = Tm[(long long)cc * n + kr];
 #pragma unroll
-        for (int j = 0; j < SW_RT; ++j) acc[j] = cfma(t, wc[j], acc[j]);
+            for (int t2 = 0; t2 < 2; ++t2) bv[u][t2] = Wi[(long long)cc * ws + s0 + 16 * t2 + li];
+            if (c >= n) av[u] = mk<T>(T(0), T(0));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t2 = 0; t2 < 2; ++t2) cmac(acc[t2], av[u], bv[u][t2]);
     }
 #pragma unroll
-    for (int j = 0; j < SW_RT; ++j) red[wv][j][lane] = acc[j];
+    for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wv][t2][l][v] = mk<T>(acc[t2].re[v], acc[t2].im[v]);
     __syncthreads();
-    if (threadIdx.x >= SW_RT * SW_ROWS) return;
-    const int j = threadIdx.x / SW_ROWS, row = threadIdx.x % SW_ROWS;
-    const int ko = k0 + row, slot = s0 + j;
+    // one output per thread: tile t2, lane l2, element v
+    const int tid = threadIdx.x;
+    const int v = tid & 3, l2 = (tid >> 2) & 63, t2 = tid >> 8;
+    const int ko = k0 + Mfma<T>::row(l2, v);
+    const int slot = s0 + 16 * t2 + (l2 & 15);
     if (ko >= n || slot >= a.nact) return;
-    cplx<T> sum = red[0][j][row];
-    for (int q = 1; q < NW; ++q) sum = sum + red[q][j][row];
+    cplx<T> sum = red[0][t2][l2][v];
+#pragma unroll
+    for (int q = 1; q < SW_W; ++q) sum = sum + red[q][t2][l2][v];
     const int id = a.act ? a.act[slot] : slot;
-    const zd v = ccast<double>(sum) +
-                 a.Ugrid[(long long)id * a.N + (long long)n * (a.line[side] - 1) + ko];
-    a.W[a.w_out[side] + (long long)id * n + ko] = v;
-    reinterpret_cast<cplx<T>*>(a.Wt_out[side])[(long long)ko * ws + slot] = ccast<T>(v);
+    const zd val = ccast<double>(sum) +
+                   a.Ugrid[(long long)id * a.N + (long long)n * (a.line[side] - 1) + ko];
+    a.W[a.w_out[side] + (long long)id * n + ko] = val;
+    reinterpret_cast<cplx<T>*>(a.Wt_out[side])[(long long)ko * ws + slot] = ccast<T>(val);
 }
 
 // W rows of the first sweep step: u~_{1,1} on the last line of X_1 (right-going)
@@ -681,10 +703,8 @@ hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const i
     a.N = P->N;
     dim3 grid((P->n + SW_ROWS - 1) / SW_ROWS, ws / SW_RT, 2);
     if (P->prec == ASP_PREC_FP32)
-        hipLaunchKernelGGL(sweep_step_kernel<float>, grid, dim3(64 * SweepWaves<float>::value), 0,
-                           st, a);
+        hipLaunchKernelGGL(sweep_step_kernel<float>, grid, dim3(64 * SW_W), 0, st, a);
     else
-        hipLaunchKernelGGL(sweep_step_kernel<double>, grid, dim3(64 * SweepWaves<double>::value), 0,
-                           st, a);
+        hipLaunchKernelGGL(sweep_step_kernel<double>, grid, dim3(64 * SW_W), 0, st, a);
     return hipGetLastError();
 }

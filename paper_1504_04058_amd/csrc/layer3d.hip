@@ -20,6 +20,7 @@
 #include <algorithm>
 
 #include "asp_internal.h"
+#include "mfma.h"
 
 namespace {
 
@@ -27,55 +28,6 @@ constexpr int TB = 64;        // panel width of the inversion, edge of a tile
 constexpr int LDT = TB + 1;   // LDS row stride of a tile (complex entries)
 constexpr int NT = 256;       // threads of a factor or solve workgroup (4 waves)
 constexpr int RW = 16;        // right-hand sides per solve chunk (one matrix-core tile)
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// 16x16x4 matrix-core product-accumulate: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; element v (0..3) of the result in lane l is entry
-// (row(l, v), l % 16) of the 16 x 16 product.  The FP32 instruction stacks the
-// four elements of a lane (rows 4 (l / 16) + v), the FP64 one interleaves them
-// (rows l / 16 + 4 v).
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<float> {
-    using V = f32x4;
-    __device__ static __forceinline__ V mac(float a, float b, V c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
-template <>
-struct Mfma<double> {
-    using V = f64x4;
-    __device__ static __forceinline__ V mac(double a, double b, V c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    __device__ static __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
-};
-
-// complex 16 x 16 accumulator (real and imaginary planes)
-template <typename T>
-struct CTile {
-    typename Mfma<T>::V re, im;
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            re[v] = T(0);
-            im[v] = T(0);
-        }
-    }
-};
-
-// c += a b with complex operands split into four real products
-template <typename T>
-__device__ __forceinline__ void cmac(CTile<T>& c, cplx<T> a, cplx<T> b) {
-    c.re = Mfma<T>::mac(a.x, b.x, c.re);
-    c.re = Mfma<T>::mac(-a.y, b.y, c.re);
-    c.im = Mfma<T>::mac(a.x, b.y, c.im);
-    c.im = Mfma<T>::mac(a.y, b.x, c.im);
-}
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
@@ -187,18 +139,21 @@ __device__ __forceinline__ void invert_tile(cplx<T> v[16], cplx<T>* rowbuf, cplx
         const T p2 = abs2(p);
         if (!(p2 > tiny) || !(p2 < T(1) / tiny)) *bad = 1;
         const cplx<T> pinv = mk<T>(p.x / p2, -p.y / p2);
-        const cplx<T> cr = cb[r];
-        const cplx<T> crp = cr * pinv;
+        // every entry: v -= (A[r][piv] / p) A[piv][c]; then the pivot row is
+        // A[piv][c] / p and the pivot column -A[r][piv] / p (1 / p at the pivot)
+        const bool prow = r == piv;
+        const cplx<T> crp = cb[r] * pinv;
+        const cplx<T> colv = prow ? pinv : -crp;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int c = cg + 4 * e;
-            if (r == piv) {
-                v[e] = (c == piv) ? pinv : v[e] * pinv;
-            } else if (c == piv) {
-                v[e] = -crp;
-            } else {
-                v[e] = v[e] - crp * rb[c];
-            }
+            const cplx<T> rc = rb[cg + 4 * e];
+            const cplx<T> gen = v[e] - crp * rc;
+            const cplx<T> rowv = rc * pinv;
+            cplx<T> x = prow ? rowv : gen;
+            const bool pcol = (cg + 4 * e) == piv;
+            x.x = pcol ? colv.x : x.x;
+            x.y = pcol ? colv.y : x.y;
+            v[e] = x;
         }
     }
     __syncthreads();
@@ -277,24 +232,16 @@ struct GjArgs {
     int k, jp, ntmax;
 };
 
-// Panel step of panel jp: every workgroup inverts the pivot tile D = A[J,J];
-// row-tile workgroups set A[I,J] = -A[I,J] D^-1, column-tile workgroups keep
-// A[J,C] in Rbuf and set A[J,C] = D^-1 A[J,C]; the workgroup of row tile jp
-// keeps D^-1 for the update step.
+// Pivot tile of panel jp: Dbuf = D^-1 for D = A[J,J], one workgroup per job.
 template <typename T>
-__global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
-    __shared__ cplx<T> sD[TB * LDT];
-    __shared__ cplx<T> sA[TB * LDT];
+__global__ __launch_bounds__(NT) void gj_pivot_kernel(GjArgs a) {
     __shared__ cplx<T> rowbuf[2 * TB], colbuf[2 * TB];
     __shared__ int bad;
-    const int js = blockIdx.y;
+    const int js = blockIdx.x;
     const SubDesc d = a.desc[a.jobs[js]];
-    const int Bp = d.B, nt = Bp / TB;
-    if (a.jp >= nt) return;
-    const bool rowt = (int)blockIdx.x < a.ntmax;
-    const int t = rowt ? blockIdx.x : blockIdx.x - a.ntmax;
-    if (t >= nt || (!rowt && t == a.jp)) return;
-    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    const int Bp = d.B;
+    if (a.jp >= Bp / TB) return;
+    const cplx<T>* A = static_cast<const cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
     const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
     const int J0 = a.jp * TB;
     if (threadIdx.x == 0) bad = 0;
@@ -302,15 +249,29 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = A[(long long)(J0 + cg + 4 * e) * Bp + J0 + r];
     invert_tile(v, rowbuf, colbuf, &bad);
-    if (rowt && t == a.jp) {
-        cplx<T>* D = static_cast<cplx<T>*>(a.Dbuf) + (long long)js * TB * TB;
+    cplx<T>* D = static_cast<cplx<T>*>(a.Dbuf) + (long long)js * TB * TB;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) D[(cg + 4 * e) * TB + r] = v[e];
-        if (threadIdx.x == 0 && bad) *a.flag = 1;
-        return;
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) sD[r * LDT + cg + 4 * e] = v[e];
+    for (int e = 0; e < 16; ++e) D[(cg + 4 * e) * TB + r] = v[e];
+    if (threadIdx.x == 0 && bad) *a.flag = 1;
+}
+
+// Panel step of panel jp: row-tile workgroups set A[I,J] = -A[I,J] D^-1,
+// column-tile workgroups keep A[J,C] in Rbuf and set A[J,C] = D^-1 A[J,C].
+template <typename T>
+__global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
+    __shared__ cplx<T> sD[TB * LDT];
+    __shared__ cplx<T> sA[TB * LDT];
+    const int js = blockIdx.y;
+    const SubDesc d = a.desc[a.jobs[js]];
+    const int Bp = d.B, nt = Bp / TB;
+    if (a.jp >= nt) return;
+    const bool rowt = (int)blockIdx.x < a.ntmax;
+    const int t = rowt ? blockIdx.x : blockIdx.x - a.ntmax;
+    if (t >= nt || t == a.jp) return;
+    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    const int J0 = a.jp * TB;
+    load_tile(sD, static_cast<const cplx<T>*>(a.Dbuf) + (long long)js * TB * TB, TB, 0, 0);
     CTile<T> acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -390,7 +351,6 @@ struct Solve3Args {
     AxisTables ax;
     const zd* e3;
     const zd* gv3;
-    const int* gi3;
     int in_mode;
     const zd* Win;
     zd* Wout;
@@ -404,16 +364,82 @@ struct Solve3Args {
     int nact;
 };
 
-// One block step for 16 rows of every job and one chunk of 16 right-hand
-// sides; the four waves split the inner dimension and reduce through LDS in a
-// fixed order.
-template <typename T>
-__global__ __launch_bounds__(NT) void solve3d_step_kernel(Solve3Args a) {
-    __shared__ cplx<T> red[4][64][4];
+// Operands of one batch (4 k-steps, 16 columns) of a block step: RT row tiles
+// of S_k^-1 and the raw terms of t(c) = g(c) - cf e(c) v(c).
+template <typename T, int RT>
+struct StepBatch {
+    cplx<T> m[RT][4], g[4], v[4];
+    zd e[4];
+};
+
+template <typename T, int RT, bool with_g>
+__device__ __forceinline__ void load_batch(StepBatch<T, RT>& B, const cplx<T>* __restrict__ Mk,
+                                           int Bp, int r0, int c0, const cplx<T>* __restrict__ g,
+                                           const cplx<T>* __restrict__ v,
+                                           const zd* __restrict__ e, bool with_v) {
+    const int l = lane_id();
+    const int li = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = c0 + 4 * u + lk;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) B.m[rt][u] = Mk[(long long)c * Bp + r0 + 16 * rt + li];
+        if (with_g) B.g[u] = g[(long long)c * RW + li];
+        if (with_v) {
+            B.v[u] = v[(long long)c * RW + li];
+            B.e[u] = e[c];
+        }
+    }
+}
+
+template <typename T, int RT, bool with_g>
+__device__ __forceinline__ void mac_batch(CTile<T> (&acc)[RT], const StepBatch<T, RT>& B, zd cf,
+                                          bool with_v) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        cplx<T> t = with_g ? B.g[u] : mk<T>(T(0), T(0));
+        if (with_v) t = t - ccast<T>(cf * B.e[u]) * B.v[u];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) cmac(acc[rt], B.m[rt][u], t);
+    }
+}
+
+// acc += S_k^-1 (RT row tiles from r0) t over the batches b = w, w + NW, ...
+// of 16 columns, where t(c) = g(c) - cf e(c) v(c) (with_g) or -cf e(c) v(c):
+// g the gathered data, v the previous / next block's vector, cf the x1
+// coupling without its cross-section factor e.  The next batch's operands are
+// loaded before the current batch's products.
+template <typename T, int NW, int RT, bool with_g>
+__device__ __forceinline__ void step_product(CTile<T> (&acc)[RT], const cplx<T>* __restrict__ Mk,
+                                             int Bp, int r0, const cplx<T>* __restrict__ g,
+                                             const cplx<T>* __restrict__ v,
+                                             const zd* __restrict__ e, zd cf, bool with_v) {
+    const int nb = Bp / 16;
+    int b = wave_id();
+    if (b >= nb) return;
+    StepBatch<T, RT> cur, nxt;
+    load_batch<T, RT, with_g>(cur, Mk, Bp, r0, 16 * b, g, v, e, with_v);
+    for (;;) {
+        const int bn = b + NW;
+        if (bn < nb) load_batch<T, RT, with_g>(nxt, Mk, Bp, r0, 16 * bn, g, v, e, with_v);
+        mac_batch<T, RT, with_g>(acc, cur, cf, with_v);
+        if (bn >= nb) break;
+        cur = nxt;
+        b = bn;
+    }
+}
+
+// One block step for RT x 16 rows of every job and one chunk of 16
+// right-hand sides; NW waves split the inner dimension and reduce through LDS
+// in a fixed order.  R/L data (nonzero on one line of the cross-section)
+// enters through a separate product over the columns of that line.
+template <typename T, int NW, int RT>
+__global__ __launch_bounds__(64 * NW) void solve3d_step_kernel(Solve3Args a) {
+    __shared__ cplx<T> red[NW][RT][64][4];
     const int js = blockIdx.y, chunk = blockIdx.z;
     const SubDesc d = a.desc[a.jobs[js]];
     const int Bp = d.B, L = d.L;
-    const int r0 = blockIdx.x * 16;
+    const int r0 = blockIdx.x * 16 * RT;
     if (r0 >= Bp) return;
     const int k = a.k;
     const int l = lane_id(), w = wave_id();
@@ -424,65 +450,62 @@ __global__ __launch_bounds__(NT) void solve3d_step_kernel(Solve3Args a) {
     const zd* e = a.e3 + d.vec_off;
     const int slot_l = chunk * RW + li;       // this lane's right-hand side in the B operand
     const bool live_l = slot_l < a.nact;
-    CTile<T> acc;
-    acc.zero();
-    const int kq = Bp / 4;
-    const int cbeg = w * kq;
+    CTile<T> acc[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc[rt].zero();
     const bool skip = !a.fwd && k == a.n - 1;   // x_n = y_n
+    // rows r0 + 16 RT may pass Bp when Bp is not a multiple of 16 RT: the
+    // last row tiles then read (and later drop) the next block's rows
     if (!skip) {
         if (a.fwd) {
             const cplx<T>* yp = Yc + (long long)(k - 1) * blk;
             const zd sk = a.ax.sh[k];                      // coupling of blocks k-1, k
-            const bool has_prev = k > 0;
             if (a.in_mode == IN_GRID) {
                 const cplx<T>* g = static_cast<const cplx<T>*>(a.G) +
                                    ((long long)chunk * a.njobs + js) * a.yj + (long long)k * blk;
-                for (int c0 = cbeg; c0 < cbeg + kq; c0 += 4) {
-                    const int c = c0 + lk;
-                    const cplx<T> m = Mk[(long long)c * Bp + r0 + li];
-                    cplx<T> t = g[(long long)c * RW + li];
-                    if (has_prev) t = t - ccast<T>(sk * e[c]) * yp[(long long)c * RW + li];
-                    cmac(acc, m, t);
-                }
+                step_product<T, NW, RT, true>(acc, Mk, Bp, r0, g, yp, e, sk, k > 0);
             } else {
+                if (k > 0) step_product<T, NW, RT, false>(acc, Mk, Bp, r0, nullptr, yp, e, sk, true);
+                // data on the line next to the Dirichlet data: columns c = L i2 + dl
+                const int dl = (d.kind == ASP_SUB_R) ? 0 : L - 1;
                 const zd* gv = a.gv3 + d.vec_off;
-                const int* gi = a.gi3 + d.vec_off;
                 const zd* win = a.Win + (long long)js * a.S * a.ws;
                 const zd is1 = a.ax.inv_s[k];
-                for (int c0 = cbeg; c0 < cbeg + kq; c0 += 4) {
-                    const int c = c0 + lk;
-                    const cplx<T> m = Mk[(long long)c * Bp + r0 + li];
-                    cplx<T> t = mk<T>(T(0), T(0));
-                    const int i2 = gi[c];
-                    if (i2 >= 0 && live_l)
-                        t = ccast<T>((is1 * gv[c]) *
-                                     win[((long long)k + (long long)a.n * i2) * a.ws + slot_l]);
-                    if (has_prev) t = t - ccast<T>(sk * e[c]) * yp[(long long)c * RW + li];
-                    cmac(acc, m, t);
+                const int nsteps = (a.n + 3) / 4;
+                for (int s4 = w; s4 < nsteps; s4 += NW) {
+                    const int i2 = 4 * s4 + lk;
+                    const int i2c = min(i2, a.n - 1);
+                    const int c = L * i2c + dl;
+                    const zd wv = win[((long long)k + (long long)a.n * i2c) * a.ws + slot_l];
+                    const bool on = i2 < a.n && live_l;
+                    const cplx<T> t = on ? ccast<T>((is1 * gv[c]) * wv) : mk<T>(T(0), T(0));
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+                        cmac(acc[rt], Mk[(long long)c * Bp + r0 + 16 * rt + li], t);
                 }
             }
         } else {
             const cplx<T>* xn = Yc + (long long)(k + 1) * blk;
             const zd sk = a.ax.sh[k + 1];                  // coupling of blocks k, k+1
-            for (int c0 = cbeg; c0 < cbeg + kq; c0 += 4) {
-                const int c = c0 + lk;
-                const cplx<T> m = Mk[(long long)c * Bp + r0 + li];
-                const cplx<T> t = ccast<T>(sk * e[c]) * xn[(long long)c * RW + li];
-                cmac(acc, m, t);
-            }
+            step_product<T, NW, RT, false>(acc, Mk, Bp, r0, nullptr, xn, e, -sk, true);
         }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[w][l][v] = mk<T>(acc.re[v], acc.im[v]);
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[w][rt][l][v] = mk<T>(acc[rt].re[v], acc[rt].im[v]);
     __syncthreads();
-    // wave w finishes element v = w of every lane: row r0 + row(l, w), rhs l % 16
-    cplx<T> s = red[0][l][w];
-    s = s + red[1][l][w];
-    s = s + red[2][l][w];
-    s = s + red[3][l][w];
-    const int row = r0 + Mfma<T>::row(l, w);
-    const int slot = chunk * RW + li;
-    cplx<T>* yk = Yc + (long long)k * blk + (long long)row * RW + li;
+    // one output per thread: row tile rt, lane l2, element v
+    const int tid = threadIdx.x;
+    if (tid >= RT * 256) return;
+    const int v = tid & 3, l2 = (tid >> 2) & 63, rt = tid >> 8;
+    cplx<T> s = red[0][rt][l2][v];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) s = s + red[q][rt][l2][v];
+    const int row = r0 + 16 * rt + Mfma<T>::row(l2, v);
+    if (row >= Bp) return;
+    const int slot = chunk * RW + (l2 & 15);
+    cplx<T>* yk = Yc + (long long)k * blk + (long long)row * RW + (l2 & 15);
     if (a.fwd) {
         *yk = s;
         return;
@@ -603,11 +626,13 @@ hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int
     a.k = k;
     a.jp = jp;
     a.ntmax = P->Bmax / TB;
-    dim3 g1(2 * a.ntmax, njobs), g2(a.ntmax * a.ntmax, njobs);
+    dim3 g0(njobs), g1(2 * a.ntmax, njobs), g2(a.ntmax * a.ntmax, njobs);
     if (P->prec == ASP_PREC_FP32) {
+        hipLaunchKernelGGL(gj_pivot_kernel<float>, g0, dim3(NT), 0, st, a);
         hipLaunchKernelGGL(gj_panel_kernel<float>, g1, dim3(NT), 0, st, a);
         hipLaunchKernelGGL(gj_update_kernel<float>, g2, dim3(NT), 0, st, a);
     } else {
+        hipLaunchKernelGGL(gj_pivot_kernel<double>, g0, dim3(NT), 0, st, a);
         hipLaunchKernelGGL(gj_panel_kernel<double>, g1, dim3(NT), 0, st, a);
         hipLaunchKernelGGL(gj_update_kernel<double>, g2, dim3(NT), 0, st, a);
     }
@@ -647,7 +672,6 @@ hipError_t launch_solve3d_step(const asp_plan* P, const Solve3Launch& L, int k, 
     a.ax = axis_of(P);
     a.e3 = P->d_e3;
     a.gv3 = P->d_gv3;
-    a.gi3 = P->d_gi3;
     a.in_mode = L.in_mode;
     a.Win = L.Win;
     a.Wout = L.Wout;
@@ -661,11 +685,23 @@ hipError_t launch_solve3d_step(const asp_plan* P, const Solve3Launch& L, int k, 
     a.act = L.act;
     a.nact = L.nact;
     const int chunks = (L.nact + RW - 1) / RW;
-    dim3 grid(P->Bmax / 16, L.njobs, chunks);
-    if (P->prec == ASP_PREC_FP32)
-        hipLaunchKernelGGL(solve3d_step_kernel<float>, grid, dim3(NT), 0, st, a);
-    else
-        hipLaunchKernelGGL(solve3d_step_kernel<double>, grid, dim3(NT), 0, st, a);
+    // the sweeps (two problems per step) are latency bound: 16 rows per block and
+    // 16 wavefronts over the inner dimension; the M-solves share each loaded
+    // vector between two row tiles
+    if (L.two_sided) {
+        // (FP64 operands take twice the registers: 8 wavefronts, 256 registers each)
+        dim3 grid(P->Bmax / 16, L.njobs, chunks);
+        if (P->prec == ASP_PREC_FP32)
+            hipLaunchKernelGGL((solve3d_step_kernel<float, 16, 1>), grid, dim3(1024), 0, st, a);
+        else
+            hipLaunchKernelGGL((solve3d_step_kernel<double, 8, 1>), grid, dim3(512), 0, st, a);
+    } else {
+        dim3 grid(P->Bmax / 32, L.njobs, chunks);
+        if (P->prec == ASP_PREC_FP32)
+            hipLaunchKernelGGL((solve3d_step_kernel<float, 8, 2>), grid, dim3(512), 0, st, a);
+        else
+            hipLaunchKernelGGL((solve3d_step_kernel<double, 8, 2>), grid, dim3(512), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -249,7 +249,6 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     // 3D per-entry vectors: the x1 coupling without its s1 factor, and the
     // Dirichlet data weights of R/L problems (on their first / last line)
     std::vector<zd> e3((size_t)vec_off), gv3((size_t)vec_off);
-    std::vector<int> gi3((size_t)vec_off, -1);
     if (dim == 3) {
         for (size_t s = 0; s < P->subs.size(); ++s) {
             const SubDesc& d = P->subs[s];
@@ -257,19 +256,14 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
             const cd s_data = d.kind == ASP_SUB_R ? P->sub_half[s][0] : P->sub_half[s][d.L];
             for (int j = 0; j < d.B; ++j) {
                 zd ev = mk(0.0, 0.0), gv = mk(0.0, 0.0);
-                int gi = -1;
                 if (j < n * d.L) {
                     const int i3 = j % d.L, i2 = j / d.L;
                     const cd s2 = P->ax_int[i2], s3 = P->sub_int[s][i3];
                     ev = to_zd(1.0 / (s2 * s3 * h2));
-                    if (i3 == data_line) {
-                        gv = to_zd(-s_data / (s2 * h2));
-                        gi = i2;
-                    }
+                    if (i3 == data_line) gv = to_zd(-s_data / (s2 * h2));
                 }
                 e3[d.vec_off + j] = ev;
                 gv3[d.vec_off + j] = gv;
-                gi3[d.vec_off + j] = gi;
             }
         }
     }
@@ -298,7 +292,6 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (dim == 3) {
         if ((st = upload(P, &P->d_e3, e3.data(), e3.size())) != ASP_OK) return fail(st, P->err.c_str());
         if ((st = upload(P, &P->d_gv3, gv3.data(), gv3.size())) != ASP_OK) return fail(st, P->err.c_str());
-        if ((st = upload(P, &P->d_gi3, gi3.data(), gi3.size())) != ASP_OK) return fail(st, P->err.c_str());
     }
     if (hipMalloc(reinterpret_cast<void**>(&P->d_flag), sizeof(int)) != hipSuccess)
         return fail(ASP_ERR_OOM, "hipMalloc failed");
@@ -316,7 +309,7 @@ extern "C" void asp_destroy(asp_plan* P) {
     }
     void* bufs[] = {P->d_ksq, P->d_axis, P->d_subtab, P->d_desc, P->d_jobs, P->d_fac, P->d_flag,
                     P->d_T, P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_y, P->d_V, P->d_Z, P->d_b,
-                    P->d_red, P->d_small, P->d_act, P->d_e3, P->d_gv3, P->d_gi3, P->d_y3,
+                    P->d_red, P->d_small, P->d_act, P->d_e3, P->d_gv3, P->d_y3,
                     P->d_g3, P->d_w3};
     (void)hipStreamSynchronize(P->stream);
     for (void* b : bufs)
