@@ -25,21 +25,33 @@ void dev_free(void* p) {
     if (p) (void)hipFree(p);
 }
 
-// workgroups of a solve launch per problem over `nact` right-hand sides
-int groups_of(int nact) {
-    return (nact + solve_rhs_per_block() - 1) / solve_rhs_per_block();
+// workgroups of a solve launch per problem of LR rows over `nact` right-hand sides
+int groups_of(int nact, int LR) {
+    const int srb = solve_rhs_per_block(LR);
+    return (nact + srb - 1) / srb;
 }
 
-// forward-substitution scratch for at least `waves` wavefronts
+// workgroups of the layer solves of one apply over nrhs right-hand sides: the
+// M-solves, then the R and L solves in one launch
+long long apply_groups(const asp_plan* P, int nrhs) {
+    return std::max((long long)P->m * groups_of(nrhs, P->LR_M),
+                    (long long)std::max(2 * P->m - 2, 1) * groups_of(nrhs, P->LR_RL));
+}
+
+// the boundary maps are computed in launches of at least this many workgroups
+// (two per CU), or all of them when fewer
+constexpr long long TRANSFER_GROUPS = 512;
+
+// forward-substitution scratch for at least `waves` workgroups
 asp_status ensure_y(asp_plan* P, long long waves) {
     if (waves <= P->y_waves) return ASP_OK;
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     dev_free(P->d_y);
     P->d_y = nullptr;
     P->y_waves = 0;
-    P->y_per_wave = (long long)P->n * 32 * solve_rhs_per_block();   // n blocks x LR rows x rhs
     char* y = nullptr;
-    if (dev_alloc(P, &y, (size_t)waves * P->y_per_wave * elem_bytes(P)) != ASP_OK) return ASP_ERR_OOM;
+    if (dev_alloc(P, &y, (size_t)waves * solve_scratch_per_block(P) * elem_bytes(P)) != ASP_OK)
+        return ASP_ERR_OOM;
     P->d_y = y;
     P->y_waves = waves;
     return ASP_OK;
@@ -152,10 +164,11 @@ asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
         P->d_wt = wt;
         P->wt_elems = we;
     }
-    asp_status s = ensure_y(P, (long long)std::max(P->m, 2) * groups_of(std::max(nrhs, 64)));
+    asp_status s = ensure_y(P, apply_groups(P, nrhs));
     if (s != ASP_OK) return s;
     P->ws_rhs = nrhs;
-    P->ws_bytes = (2 * vec + wlen) * sizeof(zd) + (size_t)P->y_waves * P->y_per_wave * elem_bytes(P);
+    P->ws_bytes = (2 * vec + wlen) * sizeof(zd) +
+                  (size_t)P->y_waves * solve_scratch_per_block(P) * elem_bytes(P);
     return ASP_OK;
 }
 
@@ -204,24 +217,33 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
         ASP_HIP(P, launch_sweep_step(P, s, P->d_W, w_rhs, act, nact, st));
         t.end();
     }
-    // u~_p = u~_{p,1:p-1} + u~_{p,p} + u~_{p,p+1:m}: all R_p solves write z = U + a,
-    // then all L_p solves add c
-    for (int side = 0; side < 2; ++side) {
+    // u~_p = u~_{p,1:p-1} + u~_{p,p} + u~_{p,p+1:m}: one launch of every R_p
+    // (z = U + a on X_p, p > 1) and L_p (c into the staging grid), then
+    // z = U + c on X_1 and z += c on X_p, 1 < p < m
+    {
         SolveLaunch L;
-        L.job0 = side == 0 ? P->idx_R(2) : P->idx_L(1);
-        L.njobs = m - 1;
+        L.job0 = P->idx_R(2);
+        L.njobs = 2 * m - 2;
         L.rl = true;
         L.act = act;
         L.nact = nact;
         L.in_mode = IN_BOUNDARY;
-        L.out_mode = side == 0 ? OUT_GRID_ADD_U : OUT_GRID_ACC;
+        L.out_mode = OUT_GRID_ADD_U;
+        L.out = z;
+        L.out_mode_L = OUT_GRID_STORE;
+        L.out_L = P->d_stage;
         L.W = P->d_W;
         L.w_rhs = w_rhs;
-        L.out = z;
         L.Ugrid = P->d_U;
-        solve_cost(P, L.job0, m - 1, nact, 2.0, &by, &fl);
+        solve_cost(P, L.job0, 2 * m - 2, nact, 2.0, &by, &fl);
         KTimer t(P, ASP_K_SOLVE_RL, by, fl);
         ASP_HIP(P, launch_solve2d(P, L, st));
+        t.end();
+    }
+    {
+        KTimer t(P, ASP_K_COMBINE, 4.0 * nact * (double)P->N * sizeof(zd), 0.0);
+        ASP_HIP(P, launch_combine3d(P, z, P->d_U, P->d_stage, P->X[0][1], P->X[m - 2][1], act,
+                                    nact, st));
         t.end();
     }
     return ASP_OK;
@@ -232,7 +254,7 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
 static asp_status compute_transfer(asp_plan* P) {
     const int m = P->m;
     if (m < 3) return ASP_OK;
-    const int per_job = groups_of(P->n);
+    const int per_job = groups_of(P->n, P->LR_RL);
     const long long chunk = std::max<long long>(1, P->y_waves / per_job);
     for (int side = 0; side < 2; ++side) {
         const int first = side == 0 ? P->idx_R(2) : P->idx_L(2);
@@ -282,7 +304,9 @@ extern "C" asp_status asp_factor(asp_plan* P) {
         if (dev_alloc(P, &t, P->t_bytes) != ASP_OK) return ASP_ERR_OOM;
         P->d_T = t;
     }
-    asp_status s = ensure_y(P, (long long)std::max(P->m, 2) * groups_of(64));
+    asp_status s = ensure_y(
+        P, std::min<long long>(TRANSFER_GROUPS, (long long)std::max(2 * P->m - 4, 1) *
+                                                    groups_of(P->n, P->LR_RL)));
     if (s != ASP_OK) return s;
     ASP_HIP(P, hipMemsetAsync(P->d_flag, 0, sizeof(int), P->stream));
     {
@@ -389,8 +413,7 @@ extern "C" asp_status asp_workspace_estimate(const asp_plan* P, int nrhs, int re
     const double vec = (double)nrhs * P->N * sizeof(zd);
     const double wrows = (double)std::max(2 * P->m - 2, 1) * nrhs * P->n * sizeof(zd);
     const double wt = (double)sweep_wt_len(P, nrhs) * esz;
-    const double y = (double)std::max(P->m, 2) * groups_of(std::max(nrhs, 64)) * P->n * 32.0 *
-                     solve_rhs_per_block() * esz;
+    const double y = (double)apply_groups(P, nrhs) * solve_scratch_per_block(P) * esz;
     const double krylov = vec * (2.0 * restart + 2.0) +
                           (double)nrhs * krylov_blocks(P->N) * 8 * sizeof(zd) +
                           (double)nrhs * 257 * sizeof(zd);
@@ -418,7 +441,7 @@ extern "C" asp_status asp_release_workspace(asp_plan* P) {
     P->kr_rhs = P->kr_restart = 0;
     P->kr_bytes = 0;
     // the solve scratch is shared with asp_factor; keep it only if small
-    if ((double)P->y_waves * P->y_per_wave * elem_bytes(P) > 256.0 * (1 << 20)) {
+    if ((double)P->y_waves * solve_scratch_per_block(P) * elem_bytes(P) > 256.0 * (1 << 20)) {
         dev_free(P->d_y);
         P->d_y = nullptr;
         P->y_waves = 0;

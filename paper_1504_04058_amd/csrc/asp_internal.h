@@ -164,8 +164,7 @@ struct asp_plan {
     zd* d_stage = nullptr;  // grid-shaped staging for asp_subsolve
     void* d_wt = nullptr;   // sweep data, transposed, in the factor precision
     long long wt_elems = 0;
-    void* d_y = nullptr;    // forward-substitution scratch
-    long long y_per_wave = 0;
+    void* d_y = nullptr;    // forward-substitution scratch, y_waves workgroups
     long long y_waves = 0;
     size_t ws_bytes = 0;
 
@@ -249,10 +248,15 @@ struct SolveLaunch {
     int w_rhs = 0;
     zd* out = nullptr;
     const zd* Ugrid = nullptr;
+    // a launch over R and L problems: the L problems write here instead (NULL: out)
+    int out_mode_L = OUT_GRID_STORE;
+    zd* out_L = nullptr;
 };
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st);
-// right-hand sides handled by one solve workgroup
-int solve_rhs_per_block();
+// right-hand sides handled by one solve workgroup for problems of LR rows, and
+// the scratch entries of one workgroup (the same for every LR)
+int solve_rhs_per_block(int LR);
+long long solve_scratch_per_block(const asp_plan* P);
 // the W rows that start the two sweeps (from u~_{1,1} and u~_{m,m} in U)
 hipError_t launch_sweep_seed(const asp_plan* P, zd* W, long long outR, long long outL,
                              const int* act, int nact, hipStream_t st);

@@ -22,10 +22,13 @@ constexpr int WAVE = 64;
 constexpr int MAXL = 32;
 
 // ----------------------------------------------------------------------------
-// factorization: one wavefront per auxiliary problem, the current L x L block
-// in LDS; S_k is inverted in place by Gauss-Jordan elimination with partial
-// pivoting inside the block.  Arithmetic in double; the stored factor is
-// rounded to TS.
+// factorization: one wavefront per auxiliary problem.  Lane (j, h) holds rows
+// 16h .. 16h+15 of column j of the current block in registers; S_k is formed
+// from S_{k-1}^-1 in place and inverted by Gauss-Jordan elimination without
+// pivoting (at a few points per wavelength the blocks are close to diagonally
+// dominant; a zero or non-finite pivot is reported as a breakdown).  The pivot
+// row and column pass through LDS, double-buffered: one wave barrier per
+// pivot.  Arithmetic in double; the stored factor is rounded to TS.
 // ----------------------------------------------------------------------------
 template <typename TS>
 __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restrict__ desc,
@@ -34,112 +37,107 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
                                                       const double* __restrict__ ksq, int n,
                                                       cplx<TS>* __restrict__ fac,
                                                       int* __restrict__ flag) {
-    __shared__ zd M[MAXL][MAXL + 1];
-    __shared__ zd col[MAXL];
-    __shared__ int piv[MAXL];
+    __shared__ zd rowbuf[2][MAXL];
+    __shared__ zd colbuf[2][MAXL];
 
     const SubDesc d = desc[blockIdx.x];
     const int L = d.L;
     const int lane = threadIdx.x;
+    const int j = lane & 31, h = lane >> 5;
+    const bool cj = j < L;
     const zd* tab = subtab + d.tab_off;
     const zd* ssh = tab;                // s at half lines lo-1/2 .. hi+1/2
     const zd* sinv2 = tab + L + 1;      // 1/(s h^2) on lines lo..hi
     const zd* sinv = tab + 2 * L + 1;   // 1/s on lines lo..hi
     const int LR = d.LR;
+    const zd sj = cj ? sinv2[j] : mk(0.0, 0.0);
     bool bad = false;
+    zd v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = mk(0.0, 0.0);
 
     for (int k = 1; k <= n; ++k) {
         const zd sh_m = ax.sh[k - 1];   // s1 at k - 1/2
         const zd sh_p = ax.sh[k];       // s1 at k + 1/2
         const zd is2k = ax.inv_sh2[k - 1];
         const zd isk = ax.inv_s[k - 1];
-        // S_k = D_k - E_{k-1} S_{k-1}^-1 E_{k-1}, in place over S_{k-1}^-1
-        for (int e = lane; e < L * L; e += WAVE) {
-            const int i = e / L, j = e % L;
-            zd v = mk(0.0, 0.0);
-            if (k > 1) {
-                const zd ei = sh_m * sinv2[i];
-                const zd ej = sh_m * sinv2[j];
-                v = -(ei * M[i][j] * ej);
+        // S_k = D_k - E_{k-1} S_{k-1}^-1 E_{k-1} over S_{k-1}^-1; identity padding
+        const zd ej = sh_m * sj;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = 16 * h + q;
+            zd val = mk(0.0, 0.0);
+            if (i < L && cj) {
+                if (k > 1) val = -((sh_m * sinv2[i]) * v[q] * ej);
+                if (i == j) {
+                    const zd lap1 = (sh_p + sh_m) * sinv2[i];
+                    const zd lap2 = (ssh[i + 1] + ssh[i]) * is2k;
+                    const zd mass =
+                        (ksq[(long long)(k - 1) + (long long)n * (d.lo + i - 1)] * isk) * sinv[i];
+                    val = val + mass - lap1 - lap2;
+                } else if (j == i + 1) {
+                    val = val + ssh[i + 1] * is2k;
+                } else if (j == i - 1) {
+                    val = val + ssh[i] * is2k;
+                }
+            } else if (i == j) {
+                val = mk(1.0, 0.0);
             }
-            if (i == j) {
-                const zd lap1 = (sh_p + sh_m) * sinv2[i];
-                const zd lap2 = (ssh[i + 1] + ssh[i]) * is2k;
-                const zd mass = (ksq[(long long)(k - 1) + (long long)n * (d.lo + i - 1)] * isk) * sinv[i];
-                v = v + mass - lap1 - lap2;
-            } else if (j == i + 1) {
-                v = v + ssh[i + 1] * is2k;
-            } else if (j == i - 1) {
-                v = v + ssh[i] * is2k;
-            }
-            M[i][j] = v;
+            v[q] = val;
         }
-        __syncthreads();
         // in-place inverse
         for (int kk = 0; kk < L; ++kk) {
-            double a = -1.0;
-            int ip = lane;
-            if (lane >= kk && lane < L) a = abs2(M[lane][kk]);
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ao = __shfl_xor(a, off);
-                const int io = __shfl_xor(ip, off);
-                if (ao > a || (ao == a && io < ip)) {
-                    a = ao;
-                    ip = io;
+            const int b = kk & 1;
+            if (h == (kk >> 4)) {
+                // select by value: a pointer into v would move it to scratch memory
+                zd pr = v[0];
+#pragma unroll
+                for (int q = 1; q < 16; ++q) {
+                    const bool hit = q == (kk & 15);
+                    pr.x = hit ? v[q].x : pr.x;
+                    pr.y = hit ? v[q].y : pr.y;
                 }
+                rowbuf[b][j] = pr;
             }
-            if (lane == 0) piv[kk] = ip;
-            if (ip != kk && lane < L) {
-                const zd t = M[kk][lane];
-                M[kk][lane] = M[ip][lane];
-                M[ip][lane] = t;
+            if (j == kk)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) colbuf[b][16 * h + q] = v[q];
+            __syncthreads();
+            const zd p = colbuf[b][kk];
+            const double pa = abs2(p);
+            if (!(pa > 1e-300) || !isfinite(pa)) bad = true;
+            const zd pinv = cinv(p);
+            const zd rp = rowbuf[b][j] * pinv;            // A[kk][j] / p
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = 16 * h + q;
+                const zd ci = colbuf[b][i];                // A[i][kk]
+                zd x = v[q] - ci * rp;
+                if (i == kk) x = rp;
+                if (j == kk) x = (i == kk) ? pinv : -(ci * pinv);
+                v[q] = x;
             }
-            __syncthreads();
-            const zd pv = M[kk][kk];
-            const double pa = abs2(pv);
-            if (!(pa > 0.0) || !isfinite(pa)) bad = true;
-            const zd inv = cinv(pv);
-            if (lane < L) col[lane] = M[lane][kk];
-            __syncthreads();
-            if (lane < L) M[kk][lane] = (lane == kk) ? inv : M[kk][lane] * inv;
-            __syncthreads();
-            for (int e = lane; e < L * L; e += WAVE) {
-                const int i = e / L, j = e % L;
-                if (i == kk) continue;
-                if (j == kk)
-                    M[i][j] = -(col[i] * inv);
-                else
-                    M[i][j] = M[i][j] - col[i] * M[kk][j];
-            }
-            __syncthreads();
-        }
-        for (int kk = L - 1; kk >= 0; --kk) {
-            const int p = piv[kk];
-            if (p != kk && lane < L) {
-                const zd t = M[lane][kk];
-                M[lane][kk] = M[lane][p];
-                M[lane][p] = t;
-            }
-            __syncthreads();
         }
         // store S_k^-1 column-major with leading dimension LR (rows past L zero)
-        cplx<TS>* out = fac + d.fac_off + (long long)(k - 1) * L * LR;
-        for (int e = lane; e < L * LR; e += WAVE) {
-            const int j = e / LR, i = e % LR;
-            out[e] = ccast<TS>(i < L ? M[i][j] : mk(0.0, 0.0));
+        if (cj) {
+            cplx<TS>* out = fac + d.fac_off + (long long)(k - 1) * L * LR + (long long)j * LR;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = 16 * h + q;
+                if (i < LR) out[i] = ccast<TS>(i < L ? v[q] : mk(0.0, 0.0));
+            }
         }
-        __syncthreads();
     }
-    if (bad && lane == 0) *flag = 1;
+    if (bad) *flag = 1;
 }
 
 // ----------------------------------------------------------------------------
-// batched solves: one 256-thread workgroup per (auxiliary problem, chunk of up
-// to 64 right-hand sides).  The L x L block S_k^-1 of each step is loaded once
-// into an LDS ring (the load of block k+1 overlaps step k) and shared by all
-// right-hand sides of the chunk.  Thread (row group, rhs group) owns RG rows x
-// RPT right-hand sides: it forms their step inputs, writes them to LDS, and
-// after the barrier computes their rows of the block product.
+// batched solves: one 1024-thread workgroup per (auxiliary problem, chunk of
+// 1024 / LR right-hand sides); thread (row, rhs) owns one row of one
+// right-hand side.  The L x L block S_k^-1 of each step is loaded once into an
+// LDS ring (the load of block k+1 overlaps step k) and shared by all
+// right-hand sides of the chunk; each thread forms its step input, writes it
+// to LDS and, after the barrier, computes its row of the block product.
 // ----------------------------------------------------------------------------
 struct SolveArgs {
     const SubDesc* desc;
@@ -148,6 +146,8 @@ struct SolveArgs {
     const int* act;      // right-hand-side ids (NULL: 0..nact-1)
     int nact;
     int in_mode, out_mode;
+    int out_mode_L;      // L problems of a launch with both kinds: their own output
+    zd* out_L;
     const void* fac;
     AxisTables ax;
     const zd* subtab;
@@ -163,20 +163,13 @@ struct SolveArgs {
     long long N;
 };
 
-constexpr int SB = 1024;       // threads per solve workgroup (16 wavefronts: one block
-                               // of a problem in LDS feeds 4 wavefronts per SIMD)
-constexpr int SRB = 64;        // right-hand sides per solve workgroup
-
-template <int LR> struct SolveShape;
-template <> struct SolveShape<32> { static constexpr int RG = 2, RPT = 1; };
-template <> struct SolveShape<16> { static constexpr int RG = 1, RPT = 1; };
+constexpr int SB = 1024;       // threads per solve workgroup (16 wavefronts)
 
 template <typename T, int LR>
 __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
-    constexpr int RG = SolveShape<LR>::RG, RPT = SolveShape<LR>::RPT;
+    constexpr int RG = 1, RPT = 1;          // one row of one right-hand side per thread
     constexpr int NRG = LR / RG;            // row groups
-    constexpr int NCG = SB / NRG;           // right-hand-side groups
-    static_assert(NCG * RPT == SRB, "shape covers the chunk");
+    constexpr int SRB = SB / NRG;           // right-hand sides per workgroup
     constexpr int FMAX = 32 * LR;           // largest block (L <= 32)
     constexpr int FPT = (FMAX + SB - 1) / SB;
     __shared__ cplx<T> Fs[2][FMAX];
@@ -365,17 +358,19 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // still in slot (n-1) & 1; block k-1 is loaded during step k.  The y_k and
     // the values the outputs add to are read one step ahead as well.
     const int jout = (d.kind == ASP_SUB_R) ? (d.xe - d.lo) : (d.xs - d.lo);   // OUT_LINE row
-    const bool set_u = (a.out_mode == OUT_GRID_ADD_U) ||
-                       (a.out_mode == OUT_GRID_ACC && d.kind == ASP_SUB_L && d.p == 1);
-    const bool add_out = !set_u && a.out_mode == OUT_GRID_ACC;
-    const bool grid_out = a.out_mode != OUT_LINE;
+    const int omode = (d.kind == ASP_SUB_L) ? a.out_mode_L : a.out_mode;
+    zd* const outp = (d.kind == ASP_SUB_L) ? a.out_L : a.out;
+    const bool set_u = (omode == OUT_GRID_ADD_U) ||
+                       (omode == OUT_GRID_ACC && d.kind == ASP_SUB_L && d.p == 1);
+    const bool add_out = !set_u && omode == OUT_GRID_ACC;
+    const bool grid_out = omode != OUT_LINE;
     const bool use_add = set_u || add_out;
     const zd* addp[RG][RPT];
 #pragma unroll
     for (int q = 0; q < RG; ++q)
 #pragma unroll
         for (int j = 0; j < RPT; ++j)
-            addp[q][j] = use_add ? (set_u ? a.Ugrid : a.out) + (long long)rid[j] * N +
+            addp[q][j] = use_add ? (set_u ? a.Ugrid : outp) + (long long)rid[j] * N +
                                        (long long)n * (lclamp[q] - 1)
                                  : a.subtab;
     const int addk = use_add ? 1 : 0;
@@ -413,7 +408,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
                 if (!valid[j]) continue;
-                a.out[(long long)rid[j] * N + off] =
+                outp[(long long)rid[j] * N + off] =
                     use_add ? ccast<double>(v[q][j]) + av[q][j] : ccast<double>(v[q][j]);
             }
         }
@@ -610,7 +605,9 @@ static hipError_t launch_solve_lr(const asp_plan* P, const SolveArgs& a, int blo
     return hipGetLastError();
 }
 
-int solve_rhs_per_block() { return SRB; }
+int solve_rhs_per_block(int LR) { return SB / LR; }
+
+long long solve_scratch_per_block(const asp_plan* P) { return (long long)P->n * SB; }
 
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st) {
     if (L.njobs <= 0 || L.nact <= 0) return hipSuccess;
@@ -622,6 +619,8 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     a.nact = L.nact;
     a.in_mode = L.in_mode;
     a.out_mode = L.out_mode;
+    a.out_mode_L = L.out_L ? L.out_mode_L : L.out_mode;
+    a.out_L = L.out_L ? L.out_L : L.out;
     a.fac = P->d_fac;
     a.ax = AxisTables{P->d_axis, P->d_axis + (P->n + 1), P->d_axis + (2 * P->n + 1)};
     a.subtab = P->d_subtab;
@@ -632,13 +631,13 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     a.Ugrid = L.Ugrid;
     a.Tout = P->d_T;
     a.y = P->d_y;
-    a.y_per_wave = P->y_per_wave;
+    a.y_per_wave = solve_scratch_per_block(P);
     a.n = P->n;
     a.N = P->N;
     const int LR = L.rl ? P->LR_RL : P->LR_M;   // every job of one launch shares its row count
-    const long long B = (long long)L.njobs * ((L.nact + SRB - 1) / SRB);
-    if (B > P->y_waves || (long long)P->n * SRB * LR > P->y_per_wave)
-        return hipErrorInvalidValue;   // scratch too small
+    const int srb = solve_rhs_per_block(LR);
+    const long long B = (long long)L.njobs * ((L.nact + srb - 1) / srb);
+    if (B > P->y_waves) return hipErrorInvalidValue;   // scratch too small
     const int blocks = (int)(((B + 7) / 8) * 8);
     if (LR == 16) return launch_solve_lr<16>(P, a, blocks, st);
     return launch_solve_lr<32>(P, a, blocks, st);
