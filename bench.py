@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--secondary", default="3d_n63_lens",
                     help="second workload timed after the first (one step), '' for none")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the seeded serving stream timed after the batch runs (0: none)")
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="auxiliary problems of each kind the oracle factors and solves")
     return ap.parse_args()
@@ -139,6 +141,42 @@ def cpu_baseline(w, iters_mean, sample):
     }
 
 
+def source_hash():
+    """sha256 over the library's kernel and host sources (paper_1504_04058_amd/csrc)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1504_04058_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload, prec_name, cls):
+    """HBM bytes per launch of a kernel class from the committed counter record
+    profiles/traffic_<workload>.md, or None when there is none for this
+    workload, precision and class or the sources changed since it was taken."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        m = re.search(r"<!-- traffic-json: (\{.*\}) -->", fh.read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("prec") != prec_name or rec.get("source_sha256") != source_hash():
+        return None
+    c = rec.get("classes", {}).get(cls)
+    if not c:
+        return None
+    return c["fetch_bytes"] + c["write_bytes"]
+
+
 def run_workload(name, prec_name, steps, warmup, restart=None, tol=None):
     """Time `steps` passes of the hot path (factor + GMRES of the whole batch)
     after `warmup` untimed passes; returns the measurements."""
@@ -199,7 +237,8 @@ def run_workload(name, prec_name, steps, warmup, restart=None, tol=None):
     else:
         achieved = ks["flops"] / (ks["ms"] / 1e3) / 1e12
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "kernel_class": dom,
+            "frac": achieved / peak, "traffic": recorded_traffic(name, prec_name, dom),
+            "traffic_unit": "bytes per launch", "kernel_class": dom,
             "avg_launch_ms": ks["ms"] / ks["launches"], "launches": ks["launches"],
             "per_launch_bytes": ks["bytes"] / ks["launches"],
             "per_launch_flops": ks["flops"] / ks["launches"]}
@@ -215,6 +254,33 @@ def run_workload(name, prec_name, steps, warmup, restart=None, tol=None):
         "pc_apply_gbps": pc_bytes / (pc_ms / 1e3) / 1e9 if pc_ms else None,
         "kernels": kstats, "roofline": roof, "factor_bytes": info["factor_bytes"],
     }
+
+
+def serving_run(count, prec_name):
+    """Served solves: a seeded Poisson stream of 2D (n = 127, 255, 511) and 3D
+    (n = 31) requests, 1-8 right-hand sides each, half of them repeating an
+    earlier problem, through the serving loop on a 64 GB device budget."""
+    import workloads
+    from paper_1504_04058_amd import asp, serve
+
+    sizes = ((2, 127), (2, 255), (2, 511), (3, 31))
+    descs = workloads.request_stream(count=count, rate=40.0, seed=5, sizes=sizes, max_rhs=8)
+    reqs = []
+    for d in descs:          # request payloads built before the stream starts
+        c, f = workloads.materialize(d)
+        reqs.append(serve.Request(d["rid"], d["key"], d["arrival"], d["d"], d["n"], d["omega"],
+                                  d["nrhs"], c, f, layer_b=d["b"], pml_eta=d["gamma"]))
+    prec = asp.ASP_PREC_FP32 if prec_name == "fp32" else asp.ASP_PREC_FP64
+    srv = serve.Server(serve.AspBackend(prec=prec, keep_u=False), budget_bytes=64 << 30,
+                       max_rhs=64, workers=4)
+    res, summ = srv.run(reqs)
+    summ["stream"] = {"requests": count, "rate_per_s": 40.0, "seed": 5,
+                      "sizes": [f"{d}d n={n}" for d, n in sizes], "rhs_per_request": "1-8",
+                      "repeat": 0.5}
+    summ["batches"] = len(srv.batches)
+    summ["mean_batch_rhs"] = (sum(sum(reqs[i].nrhs for i in ids) for _, ids in srv.batches) /
+                              max(len(srv.batches), 1))
+    return summ
 
 
 def config_of(name, r, prec_name):
@@ -268,6 +334,8 @@ def main():
             "max_relres": float(s2["relres"].max()), "status": s2["status"],
             "kernels": s2["kernels"], "roofline": s2["roofline"],
         }
+    if args.serve_requests > 0:
+        out["serving"] = serving_run(args.serve_requests, args.prec)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["w"], float(iters.mean()), args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -516,21 +516,31 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
     CTile<T> acc[2];
     acc[0].zero();
     acc[1].zero();
-    for (int c0 = cb; c0 < cb + per; c0 += 16) {
+    // operands of 4 k-steps (16 columns); the next batch is loaded before the
+    // current batch's products
+    struct Batch {
         cplx<T> av[4], bv[4][2];
+    };
+    auto load = [&](Batch& B, int c0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = c0 + 4 * u + lk;
             const int cc = min(c, n - 1);
-            av[u] = Tm[(long long)cc * n + kr];
+            B.av[u] = Tm[(long long)cc * n + kr];
 #pragma unroll
-            for (int t2 = 0; t2 < 2; ++t2) bv[u][t2] = Wi[(long long)cc * ws + s0 + 16 * t2 + li];
-            if (c >= n) av[u] = mk<T>(T(0), T(0));
+            for (int t2 = 0; t2 < 2; ++t2) B.bv[u][t2] = Wi[(long long)cc * ws + s0 + 16 * t2 + li];
+            if (c >= n) B.av[u] = mk<T>(T(0), T(0));
         }
+    };
+    Batch cur, nxt;
+    load(cur, cb);
+    for (int c0 = cb; c0 < cb + per; c0 += 16) {
+        if (c0 + 16 < cb + per) load(nxt, c0 + 16);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int t2 = 0; t2 < 2; ++t2) cmac(acc[t2], av[u], bv[u][t2]);
+            for (int t2 = 0; t2 < 2; ++t2) cmac(acc[t2], cur.av[u], cur.bv[u][t2]);
+        cur = nxt;
     }
 #pragma unroll
     for (int t2 = 0; t2 < 2; ++t2)

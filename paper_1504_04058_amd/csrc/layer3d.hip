@@ -108,57 +108,6 @@ __device__ __forceinline__ void store_acc(cplx<T>* A, long long ld, int r0, int 
             }
 }
 
-// In-place inverse of a 64 x 64 tile by Gauss-Jordan elimination without
-// pivoting.  Thread t holds row t % 64, columns t / 64 + 4 e (e = 0..15) in v;
-// the pivot row and column pass through LDS (double-buffered, one barrier per
-// pivot).  *bad is set for a zero or non-finite pivot.
-template <typename T>
-__device__ __forceinline__ void invert_tile(cplx<T> v[16], cplx<T>* rowbuf, cplx<T>* colbuf,
-                                            int* bad) {
-    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
-    const T tiny = sizeof(T) == 4 ? T(1e-36) : T(1e-300);
-    for (int piv = 0; piv < TB; ++piv) {
-        cplx<T>* rb = rowbuf + (piv & 1) * TB;
-        cplx<T>* cb = colbuf + (piv & 1) * TB;
-        if (r == piv)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) rb[cg + 4 * e] = v[e];
-        if ((piv & 3) == cg) {
-            // select by value: a pointer into v would move it to scratch memory
-            cplx<T> pc = v[0];
-#pragma unroll
-            for (int e = 1; e < 16; ++e) {
-                const bool hit = e == (piv >> 2);
-                pc.x = hit ? v[e].x : pc.x;
-                pc.y = hit ? v[e].y : pc.y;
-            }
-            cb[r] = pc;
-        }
-        __syncthreads();
-        const cplx<T> p = rb[piv];
-        const T p2 = abs2(p);
-        if (!(p2 > tiny) || !(p2 < T(1) / tiny)) *bad = 1;
-        const cplx<T> pinv = mk<T>(p.x / p2, -p.y / p2);
-        // every entry: v -= (A[r][piv] / p) A[piv][c]; then the pivot row is
-        // A[piv][c] / p and the pivot column -A[r][piv] / p (1 / p at the pivot)
-        const bool prow = r == piv;
-        const cplx<T> crp = cb[r] * pinv;
-        const cplx<T> colv = prow ? pinv : -crp;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const cplx<T> rc = rb[cg + 4 * e];
-            const cplx<T> gen = v[e] - crp * rc;
-            const cplx<T> rowv = rc * pinv;
-            cplx<T> x = prow ? rowv : gen;
-            const bool pcol = (cg + 4 * e) == piv;
-            x.x = pcol ? colv.x : x.x;
-            x.y = pcol ? colv.y : x.y;
-            v[e] = x;
-        }
-    }
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // factorization
 // ---------------------------------------------------------------------------
@@ -232,26 +181,68 @@ struct GjArgs {
     int k, jp, ntmax;
 };
 
-// Pivot tile of panel jp: Dbuf = D^-1 for D = A[J,J], one workgroup per job.
+// Pivot tile of panel jp: Dbuf = D^-1 for D = A[J,J], one 1024-thread
+// workgroup per job.  Gauss-Jordan elimination without pivoting: thread t holds
+// row t % 64, columns t / 64 + 16 e (e = 0..3); the pivot row and column pass
+// through LDS, double-buffered (one barrier per pivot).  A zero or non-finite
+// pivot sets the breakdown flag.
 template <typename T>
-__global__ __launch_bounds__(NT) void gj_pivot_kernel(GjArgs a) {
-    __shared__ cplx<T> rowbuf[2 * TB], colbuf[2 * TB];
+__global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
+    __shared__ cplx<T> rowbuf[2][TB], colbuf[2][TB];
     __shared__ int bad;
     const int js = blockIdx.x;
     const SubDesc d = a.desc[a.jobs[js]];
     const int Bp = d.B;
     if (a.jp >= Bp / TB) return;
     const cplx<T>* A = static_cast<const cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
-    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;     // cg = 0..15
     const int J0 = a.jp * TB;
     if (threadIdx.x == 0) bad = 0;
-    cplx<T> v[16];
+    cplx<T> v[4];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = A[(long long)(J0 + cg + 4 * e) * Bp + J0 + r];
-    invert_tile(v, rowbuf, colbuf, &bad);
+    for (int e = 0; e < 4; ++e) v[e] = A[(long long)(J0 + cg + 16 * e) * Bp + J0 + r];
+    const T tiny = sizeof(T) == 4 ? T(1e-36) : T(1e-300);
+    __syncthreads();
+    for (int piv = 0; piv < TB; ++piv) {
+        cplx<T>* rb = rowbuf[piv & 1];
+        cplx<T>* cb = colbuf[piv & 1];
+        if (r == piv)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rb[cg + 16 * e] = v[e];
+        if ((piv & 15) == cg) {
+            cplx<T> pc = v[0];
+#pragma unroll
+            for (int e = 1; e < 4; ++e) {
+                const bool hit = e == (piv >> 4);
+                pc.x = hit ? v[e].x : pc.x;
+                pc.y = hit ? v[e].y : pc.y;
+            }
+            cb[r] = pc;
+        }
+        __syncthreads();
+        const cplx<T> p = rb[piv];
+        const T p2 = abs2(p);
+        if (!(p2 > tiny) || !(p2 < T(1) / tiny)) bad = 1;
+        const cplx<T> pinv = mk<T>(p.x / p2, -p.y / p2);
+        // every entry: v -= (A[r][piv] / p) A[piv][c]; then the pivot row is
+        // A[piv][c] / p and the pivot column -A[r][piv] / p (1 / p at the pivot)
+        const bool prow = r == piv;
+        const cplx<T> crp = cb[r] * pinv;
+        const cplx<T> colv = prow ? pinv : -crp;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const cplx<T> rc = rb[cg + 16 * e];
+            cplx<T> x = prow ? rc * pinv : v[e] - crp * rc;
+            const bool pcol = (cg + 16 * e) == piv;
+            x.x = pcol ? colv.x : x.x;
+            x.y = pcol ? colv.y : x.y;
+            v[e] = x;
+        }
+    }
     cplx<T>* D = static_cast<cplx<T>*>(a.Dbuf) + (long long)js * TB * TB;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) D[(cg + 4 * e) * TB + r] = v[e];
+    for (int e = 0; e < 4; ++e) D[(cg + 16 * e) * TB + r] = v[e];
+    __syncthreads();
     if (threadIdx.x == 0 && bad) *a.flag = 1;
 }
 
@@ -628,11 +619,11 @@ hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int
     a.ntmax = P->Bmax / TB;
     dim3 g0(njobs), g1(2 * a.ntmax, njobs), g2(a.ntmax * a.ntmax, njobs);
     if (P->prec == ASP_PREC_FP32) {
-        hipLaunchKernelGGL(gj_pivot_kernel<float>, g0, dim3(NT), 0, st, a);
+        hipLaunchKernelGGL(gj_pivot_kernel<float>, g0, dim3(1024), 0, st, a);
         hipLaunchKernelGGL(gj_panel_kernel<float>, g1, dim3(NT), 0, st, a);
         hipLaunchKernelGGL(gj_update_kernel<float>, g2, dim3(NT), 0, st, a);
     } else {
-        hipLaunchKernelGGL(gj_pivot_kernel<double>, g0, dim3(NT), 0, st, a);
+        hipLaunchKernelGGL(gj_pivot_kernel<double>, g0, dim3(1024), 0, st, a);
         hipLaunchKernelGGL(gj_panel_kernel<double>, g1, dim3(NT), 0, st, a);
         hipLaunchKernelGGL(gj_update_kernel<double>, g2, dim3(NT), 0, st, a);
     }
