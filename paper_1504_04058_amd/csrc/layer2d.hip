@@ -132,12 +132,13 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
 }
 
 // ----------------------------------------------------------------------------
-// batched solves: one 1024-thread workgroup per (auxiliary problem, chunk of
-// 1024 / LR right-hand sides); thread (row, rhs) owns one row of one
-// right-hand side.  The L x L block S_k^-1 of each step is loaded once into an
-// LDS ring (the load of block k+1 overlaps step k) and shared by all
-// right-hand sides of the chunk; each thread forms its step input, writes it
-// to LDS and, after the barrier, computes its row of the block product.
+// batched solves on the matrix cores: one 256-thread workgroup per (auxiliary
+// problem, chunk of 1024 / LR right-hand sides).  A block step is the product
+// of S_k^-1 (L x L, staged in an LDS ring; the next block's load overlaps the
+// step) with the chunk's step vectors (LDS), as four 16 x 16 tiles, one per
+// wavefront.  Each lane owns the four (row, rhs) entries of its tile: it forms
+// their next step inputs in registers and writes them back to LDS, so a step
+// needs one barrier.  Forward results go to scratch for the backward pass.
 // ----------------------------------------------------------------------------
 struct SolveArgs {
     const SubDesc* desc;
@@ -163,17 +164,18 @@ struct SolveArgs {
     long long N;
 };
 
-constexpr int SB = 1024;       // threads per solve workgroup (16 wavefronts)
+constexpr int SB = 256;        // threads per solve workgroup: four wavefronts, one tile each
 
 template <typename T, int LR>
 __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
-    constexpr int RG = 1, RPT = 1;          // one row of one right-hand side per thread
-    constexpr int NRG = LR / RG;            // row groups
-    constexpr int SRB = SB / NRG;           // right-hand sides per workgroup
+    constexpr int SRB = 1024 / LR;          // right-hand sides per workgroup
+    constexpr int NCT = SRB / 16;           // right-hand-side tiles
+    static_assert((LR / 16) * NCT == 4, "four 16 x 16 tiles, one per wavefront");
     constexpr int FMAX = 32 * LR;           // largest block (L <= 32)
-    constexpr int FPT = (FMAX + SB - 1) / SB;
+    constexpr int FPT = FMAX / SB;
+    constexpr int TBS = SRB + 1;            // padded row stride of the step vectors
     __shared__ cplx<T> Fs[2][FMAX];
-    __shared__ cplx<T> tb[2][SRB][LR];
+    __shared__ cplx<T> tb[2][LR][TBS];      // step vectors [row][rhs]
 
     // XCD-aware order: the chunks of one problem are consecutive work items
     const int nchunk = (a.nact + SRB - 1) / SRB;
@@ -186,177 +188,159 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const int L = d.L, n = a.n;
     const long long N = a.N;
     const int tid = threadIdx.x;
-    const int rgi = tid % NRG, cgi = tid / NRG;
-    const int i0 = rgi * RG;
+    const int l = tid & 63, wv = tid >> 6;
+    const int li = l & 15, lk = l >> 4;
+    const int rt = wv / NCT, ct = wv % NCT;   // this wavefront's tile
+    const int rloc = 16 * ct + li;            // this lane's right-hand side in the chunk
     const cplx<T>* F = reinterpret_cast<const cplx<T>*>(a.fac) + d.fac_off;
     const int FS = L * LR;                  // entries of one block
     const zd* tab = a.subtab + d.tab_off;
     cplx<T>* Y = reinterpret_cast<cplx<T>*>(a.y) + (long long)w * a.y_per_wave;
 
-    int slot[RPT];
-    bool valid[RPT];
-    long long base[RPT];
-    int rid[RPT];
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = cgi * RPT + j;
-        slot[j] = ch * SRB + r;
-        valid[j] = slot[j] < a.nact;
-        rid[j] = valid[j] ? (a.act ? a.act[slot[j]] : slot[j]) : 0;
-        base[j] = (a.in_mode == IN_BOUNDARY) ? ((long long)d.wrow * a.w_rhs + rid[j]) * n
-                                             : (long long)rid[j] * N;
-    }
-    bool rowv[RG];
-    bool in_X[RG];
-    int line[RG];
-    int lclamp[RG];   // line clamped to the grid, for unconditional loads
-    cplx<T> sinv2[RG];
-#pragma unroll
-    for (int q = 0; q < RG; ++q) {
-        const int i = i0 + q;
-        rowv[q] = i < L;
-        line[q] = d.lo + i;
-        lclamp[q] = min(line[q], n);
-        in_X[q] = rowv[q] && line[q] >= d.xs && line[q] <= d.xe;
-        sinv2[q] = rowv[q] ? ccast<T>(tab[L + 1 + i]) : mk<T>(0, 0);
-    }
+    const int slot = ch * SRB + rloc;
+    const bool valid = slot < a.nact;
+    const int rid = valid ? (a.act ? a.act[slot] : slot) : 0;
     const int grow = (d.kind == ASP_SUB_R) ? 0 : L - 1;          // row carrying boundary data
     const zd coupl = (d.kind == ASP_SUB_R) ? tab[0] : tab[L];    // s at lo-1/2 or hi+1/2
+    int row[4], lcl[4];
+    bool rowv[4], inX[4];
+    cplx<T> sinv2[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        row[v] = 16 * rt + Mfma<T>::row(l, v);
+        rowv[v] = row[v] < L;
+        const int line = d.lo + row[v];
+        lcl[v] = min(line, n);
+        inX[v] = rowv[v] && line >= d.xs && line <= d.xe;
+        sinv2[v] = rowv[v] ? ccast<T>(tab[L + 1 + row[v]]) : mk<T>(0, 0);
+    }
 
-    // rows past L are read against zero factor entries but never written, and
-    // the factor columns past L are read against zero vectors: clear both once
-    for (int e = tid; e < 2 * SRB * LR; e += SB) (&tb[0][0][0])[e] = mk<T>(0, 0);
+    // rows and columns past L stay zero in both rings
+    for (int e = tid; e < 2 * LR * TBS; e += SB) (&tb[0][0][0])[e] = mk<T>(0, 0);
     for (int e = tid; e < 2 * FMAX; e += SB) (&Fs[0][0])[e] = mk<T>(0, 0);
-    __syncthreads();   // the first stash writes entries another thread cleared
+    __syncthreads();
     const int LP = (L + 3) & ~3;
-    cplx<T> pf[FPT];
     // loads below are unconditional (from clamped, always valid addresses) and
     // their values selected where used: a load under a divergent branch makes
     // the compiler wait for every earlier load at the branch join
-    auto fetch = [&](int blk) {
-        const cplx<T>* Fk = F + (long long)blk * FS;
-#pragma unroll
-        for (int u = 0; u < FPT; ++u) pf[u] = Fk[min(tid + u * SB, FS - 1)];
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < FPT; ++u) {
-            const int e = tid + u * SB;
-            if (e < FS) Fs[buf][e] = pf[u];
+    // this wavefront's tile of S^-1 (ring slot fb) times the step vectors tb[buf]
+    auto product = [&](int fb, int buf) {
+        CTile<T> acc;
+        acc.zero();
+        for (int c0 = 0; c0 < LP; c0 += 4) {
+            const int c = c0 + lk;
+            cmac(acc, Fs[fb][c * LR + 16 * rt + li], tb[buf][c][rloc]);
         }
-    };
-    // block product of rows i0.. for the chunk's vectors in tb[buf] with Fs[fb]
-    auto product = [&](int fb, int buf, cplx<T> (&acc)[RG][RPT]) {
-#pragma unroll
-        for (int q = 0; q < RG; ++q)
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) acc[q][j] = mk<T>(0, 0);
-        // columns L..LP-1 of the ring and of tb are zero, so the loop runs to a
-        // multiple of 4 and unrolls
-#pragma unroll 4
-        for (int c = 0; c < LP; ++c) {
-            cplx<T> f[RG], t[RPT];
-#pragma unroll
-            for (int q = 0; q < RG; ++q) f[q] = Fs[fb][c * LR + i0 + q];
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) t[j] = tb[buf][cgi * RPT + j][c];
-#pragma unroll
-            for (int q = 0; q < RG; ++q)
-#pragma unroll
-                for (int j = 0; j < RPT; ++j) acc[q][j] = cfma(f[q], t[j], acc[q][j]);
-        }
+        return acc;
     };
 
-    // raw data entering step k (complex128), for rows i0.. and the chunk's
-    // right-hand sides: read one step ahead, before the factor block, so that
-    // waiting for it never waits for the block
-    // one source pointer per (row, rhs): grid data (IN_GRID), boundary data
-    // (IN_BOUNDARY, the same for every row) or a dummy valid address (IN_UNIT);
-    // stride 1 along i1, 0 for the dummy
-    const zd* inp[RG][RPT];
+    // step data of this lane's rows (complex128): grid data (IN_GRID), the
+    // boundary data of its right-hand side (IN_BOUNDARY), or a dummy valid
+    // address (IN_UNIT, stride 0)
+    const zd* inp[4];
+    const long long bbase = ((long long)d.wrow * a.w_rhs + rid) * n;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        inp[v] = (a.in_mode == IN_GRID)       ? a.r + (long long)rid * N + (long long)n * (lcl[v] - 1)
+                 : (a.in_mode == IN_BOUNDARY) ? a.W + bbase
+                                              : a.subtab;
     const int ink = (a.in_mode == IN_UNIT) ? 0 : 1;
+    auto load_in = [&](int k, zd (&g)[4]) {
 #pragma unroll
-    for (int q = 0; q < RG; ++q)
+        for (int v = 0; v < 4; ++v) g[v] = inp[v][(long long)(k - 1) * ink];
+    };
+    // t_k = g_k - E_{k-1} y_{k-1} for this lane's entries into tb[k & 1]
+    auto put_input = [&](int k, const zd (&g)[4], const cplx<T> (&y)[4], zd shm, zd ism) {
+        const zd cin = -(coupl * ism);
+        const cplx<T> shc = ccast<T>(shm);
 #pragma unroll
-        for (int j = 0; j < RPT; ++j)
-            inp[q][j] = (a.in_mode == IN_GRID)       ? a.r + base[j] + (long long)n * (lclamp[q] - 1)
-                        : (a.in_mode == IN_BOUNDARY) ? a.W + base[j]
-                                                     : a.subtab;
-    auto load_in = [&](int k, zd (&gv)[RG][RPT]) {
-#pragma unroll
-        for (int q = 0; q < RG; ++q)
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) gv[q][j] = inp[q][j][(long long)(k - 1) * ink];
+        for (int v = 0; v < 4; ++v) {
+            if (!rowv[v]) continue;
+            cplx<T> t = mk<T>(0, 0);
+            if (a.in_mode == IN_GRID)
+                t = inX[v] ? ccast<T>(g[v]) : mk<T>(0, 0);
+            else if (row[v] == grow && a.in_mode == IN_BOUNDARY)
+                t = ccast<T>(g[v] * cin);
+            else if (row[v] == grow && a.in_mode == IN_UNIT && slot == k - 1)   // unit data at i1 = slot + 1
+                t = ccast<T>(cin);
+            if (k > 1) t = t - (shc * sinv2[v]) * y[v];
+            tb[k & 1][row[v]][rloc] = t;
+        }
     };
 
     // unit data enters at i1 = slot + 1 >= ch SRB + 1: the forward results of
     // the blocks before the chunk's first column are zero, so the forward pass
     // starts there and the backward pass reads no results before it
     const int kstart = (a.in_mode == IN_UNIT) ? min(ch * SRB + 1, n) : 1;
-    zd gin[RG][RPT];
-    load_in(kstart, gin);
-    zd shv = a.ax.sh[kstart - 1], isv = a.ax.inv_sh2[kstart - 1];
-    fetch(kstart - 1);
-    stash(kstart & 1);
-    __syncthreads();
+    // The loads of a step are issued two steps ahead into one of two register
+    // slots; the step loops are unrolled by two so that the slots stay in fixed
+    // registers (a register copy would wait for its load).
+    auto fetch_to = [&](cplx<T> (&p)[FPT], int blk) {
+        const cplx<T>* Fk = F + (long long)blk * FS;
+#pragma unroll
+        for (int u = 0; u < FPT; ++u) p[u] = Fk[min(tid + u * SB, FS - 1)];
+    };
+    auto stash_from = [&](const cplx<T> (&p)[FPT], int buf) {
+#pragma unroll
+        for (int u = 0; u < FPT; ++u) {
+            const int e = tid + u * SB;
+            if (e < FS) Fs[buf][e] = p[u];
+        }
+    };
+    cplx<T> yk[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) yk[v] = mk<T>(0, 0);
 
-    // forward sweep: y_k = S_k^-1 (g_k - E_{k-1} y_{k-1}); block k sits in ring slot k & 1
-    cplx<T> yk[RG][RPT];
+    // forward sweep: y_k = S_k^-1 t_k; block k-1 (S_k^-1) sits in ring slot
+    // k & 1.  Slot of step k: the input g_{k+1} and block k, both used at the
+    // end of step k.
+    struct FwdSlot {
+        cplx<T> pf[FPT];
+        zd g[4];
+    };
+    FwdSlot fsl[2];
+    {
+        zd g0[4];
+        load_in(kstart, g0);
+        fetch_to(fsl[0].pf, kstart - 1);
+        stash_from(fsl[0].pf, kstart & 1);
+        put_input(kstart, g0, yk, a.ax.sh[kstart - 1], a.ax.inv_sh2[kstart - 1]);
+    }
 #pragma unroll
-    for (int q = 0; q < RG; ++q)
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) yk[q][j] = mk<T>(0, 0);
-    for (int k = kstart; k <= n; ++k) {
-        const int buf = k & 1;
-        zd gnx[RG][RPT];
-        zd shn = shv, isn = isv;
+    for (int t = 0; t < 2; ++t) {
+        const int k = kstart + t;
         if (k < n) {
-            load_in(k + 1, gnx);
-            shn = a.ax.sh[k];
-            isn = a.ax.inv_sh2[k];
-            fetch(k);
-        }
-        const cplx<T> shm = ccast<T>(shv);
-        const zd cin = -(coupl * isv);
-#pragma unroll
-        for (int q = 0; q < RG; ++q) {
-            if (!rowv[q]) continue;
-            const int i = i0 + q;
-            const cplx<T> e = shm * sinv2[q];                       // E_{k-1}, row i
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                cplx<T> g = mk<T>(0, 0);
-                if (a.in_mode == IN_GRID)
-                    g = in_X[q] ? ccast<T>(gin[q][j]) : mk<T>(0, 0);
-                else if (i == grow && a.in_mode == IN_BOUNDARY)
-                    g = ccast<T>(gin[q][j] * cin);
-                else if (i == grow && slot[j] == k - 1)     // IN_UNIT: unit data at i1 = slot + 1
-                    g = ccast<T>(cin);
-                if (k > 1) g = g - e * yk[q][j];
-                tb[buf][cgi * RPT + j][i] = g;
-            }
-        }
-        __syncthreads();
-        product(buf, buf, yk);
-#pragma unroll
-        for (int q = 0; q < RG; ++q)
-#pragma unroll
-            for (int j = 0; j < RPT; ++j)
-                if (rowv[q]) Y[((long long)(k - 1) * SRB + cgi * RPT + j) * LR + i0 + q] = yk[q][j];
-        if (k < n) {
-            stash((k + 1) & 1);
-#pragma unroll
-            for (int q = 0; q < RG; ++q)
-#pragma unroll
-                for (int j = 0; j < RPT; ++j) gin[q][j] = gnx[q][j];
-            shv = shn;
-            isv = isn;
+            load_in(k + 1, fsl[t].g);
+            fetch_to(fsl[t].pf, k);
         }
     }
+    auto fwd_step = [&](int k, FwdSlot& S) {
+        const int buf = k & 1;
+        __syncthreads();
+        const CTile<T> acc = product(buf, buf);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            yk[v] = mk<T>(acc.re[v], acc.im[v]);
+            if (rowv[v]) Y[((long long)(k - 1) * LR + row[v]) * SRB + rloc] = yk[v];
+        }
+        if (k < n) {
+            stash_from(S.pf, (k + 1) & 1);                           // block k
+            put_input(k + 1, S.g, yk, a.ax.sh[k], a.ax.inv_sh2[k]);
+            if (k + 2 < n) {
+                load_in(k + 3, S.g);
+                fetch_to(S.pf, k + 2);
+            }
+        }
+    };
+    for (int k = kstart; k <= n; k += 2) {
+        fwd_step(k, fsl[0]);
+        if (k + 1 <= n) fwd_step(k + 1, fsl[1]);
+    }
 
-    // backward sweep: v_n = y_n, v_k = y_k - S_k^-1 E_k v_{k+1}.  Block n-1 is
-    // still in slot (n-1) & 1; block k-1 is loaded during step k.  The y_k and
-    // the values the outputs add to are read one step ahead as well.
+    // backward sweep: v_n = y_n, v_k = y_k - S_k^-1 E_k v_{k+1}; block k-1 in
+    // ring slot k & 1 (block n-2 is still in slot (n-1) & 1 unless the forward
+    // pass started at block n).  Slot of step k: y_k and the values its outputs
+    // add to (used in step k), and block k-2 (stashed at the end of step k).
     const int jout = (d.kind == ASP_SUB_R) ? (d.xe - d.lo) : (d.xs - d.lo);   // OUT_LINE row
     const int omode = (d.kind == ASP_SUB_L) ? a.out_mode_L : a.out_mode;
     zd* const outp = (d.kind == ASP_SUB_L) ? a.out_L : a.out;
@@ -365,102 +349,93 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const bool add_out = !set_u && omode == OUT_GRID_ACC;
     const bool grid_out = omode != OUT_LINE;
     const bool use_add = set_u || add_out;
-    const zd* addp[RG][RPT];
+    const zd* addp[4];
 #pragma unroll
-    for (int q = 0; q < RG; ++q)
-#pragma unroll
-        for (int j = 0; j < RPT; ++j)
-            addp[q][j] = use_add ? (set_u ? a.Ugrid : outp) + (long long)rid[j] * N +
-                                       (long long)n * (lclamp[q] - 1)
-                                 : a.subtab;
+    for (int v = 0; v < 4; ++v)
+        addp[v] = use_add ? (set_u ? a.Ugrid : outp) + (long long)rid * N + (long long)n * (lcl[v] - 1)
+                          : a.subtab;
     const int addk = use_add ? 1 : 0;
-    auto load_add = [&](int k, zd (&av)[RG][RPT]) {
+    auto load_add = [&](int k, zd (&av)[4]) {
 #pragma unroll
-        for (int q = 0; q < RG; ++q)
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) av[q][j] = addp[q][j][(long long)(k - 1) * addk];
+        for (int v = 0; v < 4; ++v) av[v] = addp[v][(long long)(k - 1) * addk];
     };
-    auto load_y = [&](int k, cplx<T> (&yv)[RG][RPT]) {
+    auto load_y = [&](int k, cplx<T> (&yv)[4]) {
         const long long kk = max(k, kstart);     // blocks before kstart: y = 0
 #pragma unroll
-        for (int q = 0; q < RG; ++q)
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                const cplx<T> yv0 = Y[((kk - 1) * SRB + cgi * RPT + j) * LR + i0 + q];
-                yv[q][j] = (k >= kstart) ? yv0 : mk<T>(0, 0);
-            }
+        for (int v = 0; v < 4; ++v) {
+            const cplx<T> y0 = Y[((kk - 1) * LR + min(row[v], L - 1)) * SRB + rloc];
+            yv[v] = (k >= kstart && rowv[v]) ? y0 : mk<T>(0, 0);
+        }
     };
-    auto emit = [&](int k, const cplx<T> (&v)[RG][RPT], const zd (&av)[RG][RPT]) {
+    cplx<T>* Tp = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off + (long long)slot * n;
+    auto emit = [&](int k, const cplx<T> (&v)[4], const zd (&av)[4]) {
+        if (!valid) return;
 #pragma unroll
-        for (int q = 0; q < RG; ++q) {
-            if (!rowv[q]) continue;
-            const int i = i0 + q;
+        for (int e = 0; e < 4; ++e) {
             if (!grid_out) {
-                if (i != jout) continue;
-                cplx<T>* Tp = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off;
-#pragma unroll
-                for (int j = 0; j < RPT; ++j)
-                    if (valid[j]) Tp[(long long)slot[j] * n + (k - 1)] = v[q][j];
+                if (rowv[e] && row[e] == jout) Tp[k - 1] = v[e];
                 continue;
             }
-            if (!in_X[q]) continue;
-            const long long off = (k - 1) + (long long)n * (line[q] - 1);
+            if (!inX[e]) continue;
+            outp[(long long)rid * N + (k - 1) + (long long)n * (lcl[e] - 1)] =
+                use_add ? ccast<double>(v[e]) + av[e] : ccast<double>(v[e]);
+        }
+    };
+    // E_k v_{k+1} for this lane's entries into tb[k & 1]
+    auto put_coupled = [&](int k, const cplx<T> (&v)[4]) {
+        const cplx<T> shc = ccast<T>(a.ax.sh[k]);                 // coupling of blocks k, k+1
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                if (!valid[j]) continue;
-                outp[(long long)rid[j] * N + off] =
-                    use_add ? ccast<double>(v[q][j]) + av[q][j] : ccast<double>(v[q][j]);
+        for (int e = 0; e < 4; ++e)
+            if (rowv[e]) tb[k & 1][row[e]][rloc] = (shc * sinv2[e]) * v[e];
+    };
+    struct BwdSlot {
+        cplx<T> pf[FPT];
+        cplx<T> y[4];
+        zd av[4];
+    };
+    BwdSlot bsl[2];
+    {
+        zd an[4];
+        load_add(n, an);
+        emit(n, yk, an);
+    }
+    cplx<T> (&vk)[4] = yk;
+    if (n >= 2) {
+        if (kstart > n - 1) {
+            fetch_to(bsl[0].pf, n - 2);
+            stash_from(bsl[0].pf, (n - 1) & 1);
+        }
+        put_coupled(n - 1, vk);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int k = n - 1 - t;
+        if (k >= 1) {
+            load_y(k, bsl[t].y);
+            load_add(k, bsl[t].av);
+            if (k > 1) fetch_to(bsl[t].pf, k - 2);
+        }
+    }
+    auto bwd_step = [&](int k, BwdSlot& S) {
+        const int buf = k & 1;
+        __syncthreads();
+        const CTile<T> acc = product(buf, buf);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vk[e] = S.y[e] - mk<T>(acc.re[e], acc.im[e]);
+        emit(k, vk, S.av);
+        if (k > 1) {
+            stash_from(S.pf, (k - 1) & 1);                           // block k-2
+            put_coupled(k - 1, vk);
+            if (k - 2 >= 1) {
+                load_y(k - 2, S.y);
+                load_add(k - 2, S.av);
+                if (k - 2 > 1) fetch_to(S.pf, k - 4);
             }
         }
     };
-    zd acur[RG][RPT];
-    load_add(n, acur);
-    emit(n, yk, acur);
-    cplx<T> (&vk)[RG][RPT] = yk;
-    cplx<T> ycur[RG][RPT];
-    if (n >= 2) {
-        load_y(n - 1, ycur);
-        load_add(n - 1, acur);
-    }
-    shv = a.ax.sh[n - 1];
-    for (int k = n - 1; k >= 1; --k) {
-        const int buf = k & 1;
-        cplx<T> ynx[RG][RPT];
-        zd anx[RG][RPT];
-        zd shn = shv;
-        if (k > 1) {
-            load_y(k - 1, ynx);
-            load_add(k - 1, anx);
-            shn = a.ax.sh[k - 1];
-            fetch(k - 2);
-        }
-        const cplx<T> shp = ccast<T>(shv);
-#pragma unroll
-        for (int q = 0; q < RG; ++q) {
-            const cplx<T> e = shp * sinv2[q];                       // E_k, row i
-#pragma unroll
-            for (int j = 0; j < RPT; ++j)
-                if (rowv[q]) tb[buf][cgi * RPT + j][i0 + q] = e * vk[q][j];
-        }
-        __syncthreads();
-        cplx<T> acc[RG][RPT];
-        product(buf, buf, acc);
-#pragma unroll
-        for (int q = 0; q < RG; ++q)
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) vk[q][j] = ycur[q][j] - acc[q][j];
-        emit(k, vk, acur);
-        if (k > 1) {
-            stash((k - 1) & 1);
-#pragma unroll
-            for (int q = 0; q < RG; ++q)
-#pragma unroll
-                for (int j = 0; j < RPT; ++j) {
-                    ycur[q][j] = ynx[q][j];
-                    acur[q][j] = anx[q][j];
-                }
-            shv = shn;
-        }
+    for (int k = n - 1; k >= 1; k -= 2) {
+        bwd_step(k, bsl[0]);
+        if (k - 1 >= 1) bwd_step(k - 1, bsl[1]);
     }
 }
 
@@ -615,9 +590,10 @@ static hipError_t launch_solve_lr(const asp_plan* P, const SolveArgs& a, int blo
     return hipGetLastError();
 }
 
-int solve_rhs_per_block(int LR) { return SB / LR; }
+int solve_rhs_per_block(int LR) { return 1024 / LR; }
 
-long long solve_scratch_per_block(const asp_plan* P) { return (long long)P->n * SB; }
+// forward results of one workgroup: n blocks x LR rows x 1024 / LR right-hand sides
+long long solve_scratch_per_block(const asp_plan* P) { return (long long)P->n * 1024; }
 
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st) {
     if (L.njobs <= 0 || L.nact <= 0) return hipSuccess;
