@@ -40,14 +40,14 @@ HBM_CLASSES = {"stencil", "krylov", "combine"}
 
 
 def class_bound(dim, cls, prec):
-    """(bound, peak, unit) of a kernel class: the 3D factor and solves and the
-    2D sweep steps run on the matrix cores; the other layer kernels on the
-    vector ALUs; stencil, Krylov and accumulation kernels stream HBM."""
+    """(bound, peak, unit) of a kernel class: the layer solves, the boundary
+    maps, the sweeps and the 3D factor run on the matrix cores; the 2D factor
+    on the vector ALUs; stencil, Krylov and accumulation kernels stream HBM."""
     if cls in HBM_CLASSES:
         return "hbm", PEAK_HBM_GBS, "GB/s"
-    if (dim == 3 and cls in ("factor", "solve_m", "solve_rl")) or (dim == 2 and cls == "sweep"):
-        return "mfma", PEAK_MFMA[prec], "TFLOP/s"
-    return "alu", PEAK_VALU[prec], "TFLOP/s"
+    if dim == 2 and cls == "factor":
+        return "alu", PEAK_VALU[prec], "TFLOP/s"
+    return "mfma", PEAK_MFMA[prec], "TFLOP/s"
 
 
 def parse():

@@ -114,34 +114,13 @@ asp_status factor3d(asp_plan* P) {
         fb += factor_bytes_of(P, d);
         fl += (double)P->n * B * B * B * 8.0;
     }
-    // The panels of block k stream every problem's current block once each.
-    // Problems are taken in groups of at most GROUP_BYTES of current blocks,
-    // each group running all its panels before the next, so that a group's
-    // blocks stay in the last-level cache (256 MB) across its panels.
-    constexpr double GROUP_BYTES = 112.0 * (1 << 20);
-    std::vector<int> cuts{0};
-    {
-        double acc = 0;
-        for (int j = 0; j < nsub; ++j) {
-            const double b = (double)P->subs[j].B * P->subs[j].B * esz(P);
-            if (acc > 0 && acc + b > GROUP_BYTES) {
-                cuts.push_back(j);
-                acc = 0;
-            }
-            acc += b;
-        }
-        cuts.push_back(nsub);
-    }
     {
         KTimer t(P, ASP_K_FACTOR, fb, fl);
         const int ntmax = P->Bmax / TB3;
         for (int k = 0; k < P->n && s == ASP_OK; ++k) {
             hipError_t e = launch_form3d(P, P->d_jobs, nsub, k, st);
-            for (size_t gi = 0; gi + 1 < cuts.size() && e == hipSuccess; ++gi) {
-                const int j0 = cuts[gi], nj = cuts[gi + 1] - cuts[gi];
-                for (int jp = 0; jp < ntmax && e == hipSuccess; ++jp)
-                    e = launch_gj3d(P, P->d_jobs + j0, nj, k, jp, Rbuf, Dbuf, st);
-            }
+            for (int jp = 0; jp < ntmax && e == hipSuccess; ++jp)
+                e = launch_gj3d(P, P->d_jobs, nsub, k, jp, Rbuf, Dbuf, st);
             if (e != hipSuccess)
                 s = plan_fail(P, ASP_ERR_DEVICE, std::string("3D factor launch: ") + hipGetErrorString(e));
         }
