@@ -32,8 +32,8 @@ METRIC = "Helmholtz solves/s to relres 1e-6 (2D n=1023, 3D n=63); PC-apply GB/s,
 # FP32 and FP64 alike; the 157.3 FP32 vector figure needs packed FP32
 # instructions, which this build leaves off.
 PEAK_HBM_GBS = 8000.0
-PEAK_MFMA = {"fp32": 157.3, "fp64": 78.6}
-PEAK_VALU = {"fp32": 78.6, "fp64": 78.6}
+PEAK_MFMA = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 157.3}
+PEAK_VALU = {"fp32": 78.6, "fp64": 78.6, "bf16x3": 78.6}
 
 KCLASS = ["factor", "transfer", "solve_m", "solve_rl", "sweep", "combine", "stencil", "krylov"]
 HBM_CLASSES = {"stencil", "krylov", "combine"}
@@ -190,7 +190,8 @@ def run_workload(name, prec_name, steps, warmup, restart=None, tol=None):
     w = workloads.workload(name)
     restart = restart or w["restart"]
     tol = tol or w["tol"]
-    prec = asp.ASP_PREC_FP32 if prec_name == "fp32" else asp.ASP_PREC_FP64
+    prec = {"fp32": asp.ASP_PREC_FP32, "fp64": asp.ASP_PREC_FP64,
+            "bf16x3": asp.ASP_PREC_BF16X3}[prec_name]
     nrhs = w["f"].shape[0]
     dev = torch.device("cuda:0")
     f = torch.from_numpy(w["f"]).to(dev)
@@ -283,6 +284,12 @@ def serving_run(count, prec_name):
     return summ
 
 
+def workloads_dim(name):
+    import workloads
+
+    return workloads.WORKLOADS[name]["d"]
+
+
 def config_of(name, r, prec_name):
     w = r["w"]
     return {"workload": name, "dim": w["d"], "n": w["n"], "nrhs": r["nrhs"],
@@ -325,15 +332,18 @@ def main():
         "cpu_baseline": None,
     }
     if args.secondary:
-        s2 = run_workload(args.secondary, args.prec, 1, 1)
-        out["secondary"] = {
-            "config": config_of(args.secondary, s2, args.prec),
-            "value": s2["value"], "unit": "solves/s", "ms_per_step": s2["ms_per_step"],
-            "warm_solves_per_s": s2["warm_solves_per_s"], "factor_ms": s2["factor_ms"],
-            "gmres_ms": s2["gmres_ms"], "iters_mean": float(s2["iters"].mean()),
-            "max_relres": float(s2["relres"].max()), "status": s2["status"],
-            "kernels": s2["kernels"], "roofline": s2["roofline"],
-        }
+        for key, prec in (("secondary", args.prec), ("secondary_bf16x3", "bf16x3")):
+            if prec == "bf16x3" and workloads_dim(args.secondary) != 3:
+                continue
+            s2 = run_workload(args.secondary, prec, 1, 1)
+            out[key] = {
+                "config": config_of(args.secondary, s2, prec),
+                "value": s2["value"], "unit": "solves/s", "ms_per_step": s2["ms_per_step"],
+                "warm_solves_per_s": s2["warm_solves_per_s"], "factor_ms": s2["factor_ms"],
+                "gmres_ms": s2["gmres_ms"], "iters_mean": float(s2["iters"].mean()),
+                "max_relres": float(s2["relres"].max()), "status": s2["status"],
+                "kernels": s2["kernels"], "roofline": s2["roofline"],
+            }
     if args.serve_requests > 0:
         out["serving"] = serving_run(args.serve_requests, args.prec)
     if not args.no_cpu_baseline:

@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "asp.h")
 
 ASP_OK, ASP_ERR_ARG, ASP_ERR_OOM, ASP_ERR_STATE = 0, 1, 2, 3
 ASP_ERR_BREAKDOWN, ASP_ERR_NOCONV, ASP_ERR_DEVICE = 4, 5, 6
-ASP_PREC_FP64, ASP_PREC_FP32 = 0, 1
+ASP_PREC_FP64, ASP_PREC_FP32, ASP_PREC_BF16X3 = 0, 1, 2
 ASP_SUB_M, ASP_SUB_R, ASP_SUB_L = 0, 1, 2
 STATUS_NAMES = {0: "ASP_OK", 1: "ASP_ERR_ARG", 2: "ASP_ERR_OOM", 3: "ASP_ERR_STATE",
                 4: "ASP_ERR_BREAKDOWN", 5: "ASP_ERR_NOCONV", 6: "ASP_ERR_DEVICE"}

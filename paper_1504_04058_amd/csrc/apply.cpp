@@ -9,7 +9,7 @@
 
 namespace {
 
-size_t elem_bytes(const asp_plan* P) { return P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd); }
+size_t elem_bytes(const asp_plan* P) { return P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd); }
 
 template <typename T>
 asp_status dev_alloc(asp_plan* P, T** p, size_t count) {

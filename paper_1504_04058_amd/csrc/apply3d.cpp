@@ -12,7 +12,7 @@ namespace {
 constexpr int RW3 = 16;   // right-hand sides per solve chunk
 constexpr int TB3 = 64;   // panel width of the block inversion
 
-size_t esz(const asp_plan* P) { return P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd); }
+size_t esz(const asp_plan* P) { return P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd); }
 
 template <typename T>
 asp_status alloc3(asp_plan* P, T** p, size_t bytes) {

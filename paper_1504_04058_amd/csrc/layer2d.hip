@@ -570,7 +570,7 @@ __global__ void sweep_seed_kernel(const zd* __restrict__ Ugrid, zd* __restrict__
 hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
     const int nsub = (int)P->subs.size();
     AxisTables ax{P->d_axis, P->d_axis + (P->n + 1), P->d_axis + (2 * P->n + 1)};
-    if (P->prec == ASP_PREC_FP32)
+    if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL(factor2d_kernel<float>, dim3(nsub), dim3(WAVE), 0, st, P->d_desc, ax,
                            P->d_subtab, P->d_ksq, P->n, reinterpret_cast<zf*>(P->d_fac),
                            P->d_flag);
@@ -583,7 +583,7 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
 
 template <int LR>
 static hipError_t launch_solve_lr(const asp_plan* P, const SolveArgs& a, int blocks, hipStream_t st) {
-    if (P->prec == ASP_PREC_FP32)
+    if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL((solve2d_kernel<float, LR>), dim3(blocks), dim3(SB), 0, st, a);
     else
         hipLaunchKernelGGL((solve2d_kernel<double, LR>), dim3(blocks), dim3(SB), 0, st, a);
@@ -635,7 +635,7 @@ int sweep_wt_len(const asp_plan* P, int nrhs) { return 4 * P->n * sweep_slots(nr
 
 // transposed sweep buffers: [side][ping-pong][n][ws]
 static void* wt_buf(const asp_plan* P, int side, int pp, int ws) {
-    const size_t esz = P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd);
+    const size_t esz = P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd);
     return static_cast<char*>(P->d_wt) + ((size_t)(side * 2 + pp) * P->n * ws) * esz;
 }
 
@@ -647,7 +647,7 @@ hipError_t launch_sweep_seed(const asp_plan* P, zd* W, long long outR, long long
     const int ws = sweep_slots(nact);
     if ((long long)4 * P->n * ws > P->wt_elems) return hipErrorInvalidValue;
     dim3 grid((P->n + 255) / 256, ws);
-    if (P->prec == ASP_PREC_FP32)
+    if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL(sweep_seed_kernel<float>, grid, dim3(256), 0, st, P->d_U, W, outR, outL,
                            lineR, lineL, (zf*)wt_buf(P, 0, 0, ws), (zf*)wt_buf(P, 1, 0, ws), act,
                            nact, ws, P->n, P->N);
@@ -687,7 +687,7 @@ hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const i
     a.n = P->n;
     a.N = P->N;
     dim3 grid((P->n + SW_ROWS - 1) / SW_ROWS, ws / SW_RT, 2);
-    if (P->prec == ASP_PREC_FP32)
+    if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL(sweep_step_kernel<float>, grid, dim3(64 * SW_W), 0, st, a);
     else
         hipLaunchKernelGGL(sweep_step_kernel<double>, grid, dim3(64 * SW_W), 0, st, a);

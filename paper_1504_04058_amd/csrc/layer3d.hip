@@ -324,6 +324,125 @@ __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
     store_acc(A, Bp, ti * TB, tj * TB, acc, T(1));
 }
 
+// Trailing update with real-split bf16 products (ASP_PREC_BF16X3): the same
+// tiles as gj_update_kernel<float>; P = A[I,J] and Q = R[J,C] are split into
+// bf16 hi/lo planes in LDS (k contiguous), and every real product is
+// hi*hi + hi*lo + lo*hi on the 16x16x32 bf16 matrix-core instruction with FP32
+// accumulation onto the FP32 tile of A.
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int LDB = TB + 8;   // padded k stride of a bf16 plane
+
+struct SplitPlanes {          // one 64 x 64 complex tile: [row][k] planes
+    __bf16 rh[TB * LDB], rl[TB * LDB], ih[TB * LDB], il[TB * LDB];
+};
+
+__device__ __forceinline__ void split_store(SplitPlanes& S, int i, int k, zf v) {
+    const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+    S.rh[i * LDB + k] = rh;
+    S.rl[i * LDB + k] = (__bf16)(v.x - (float)rh);
+    S.ih[i * LDB + k] = ih;
+    S.il[i * LDB + k] = (__bf16)(v.y - (float)ih);
+}
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+__device__ __forceinline__ bf16x8 neg8(bf16x8 x) {
+    s16x8 b = __builtin_bit_cast(s16x8, x);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[j] = (short)(b[j] ^ (short)0x8000);
+    return __builtin_bit_cast(bf16x8, b);
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// c += x*y with x = xh + xl, y = yh + yl, dropping xl*yl
+__device__ __forceinline__ f32x4 split_mac(bf16x8 xh, bf16x8 xl, bf16x8 yh, bf16x8 yl, f32x4 c) {
+    c = mfma_bf16(xl, yh, c);
+    c = mfma_bf16(xh, yl, c);
+    return mfma_bf16(xh, yh, c);
+}
+
+__global__ __launch_bounds__(NT) void gj_update_bf16x3_kernel(GjArgs a) {
+    __shared__ SplitPlanes sP, sQ;   // P[r][k], Q^T[c][k]
+    const int js = blockIdx.y;
+    const SubDesc d = a.desc[a.jobs[js]];
+    const int Bp = d.B, nt = Bp / TB;
+    if (a.jp >= nt) return;
+    const int ti = blockIdx.x % a.ntmax, tj = blockIdx.x / a.ntmax;
+    if (ti >= nt || tj >= nt) return;
+    zf* A = static_cast<zf*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    const int J0 = a.jp * TB;
+    if (tj == a.jp) {
+        if (ti == a.jp) {
+            const zf* D = static_cast<const zf*>(a.Dbuf) + (long long)js * TB * TB;
+            const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int c = cg + 4 * e;
+                A[(long long)(J0 + c) * Bp + J0 + r] = D[c * TB + r];
+            }
+        }
+        return;
+    }
+    if (ti == a.jp) return;
+    const zf* R = static_cast<const zf*>(a.Rbuf) + js * a.rstride;
+    {
+        // P(r, k) = A(ti*64 + r, J0 + k): reads coalesced over r
+        const int r = threadIdx.x & 63, kg = threadIdx.x >> 6;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int k = kg + 4 * e;
+            split_store(sP, r, k, A[(long long)(J0 + k) * Bp + ti * TB + r]);
+        }
+        // Q^T(c, k) = R(k, tj*64 + c) at [(tj*64 + c) * 64 + k]: reads coalesced over k
+        const int k2 = threadIdx.x & 63, cg = threadIdx.x >> 6;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int c = cg + 4 * e;
+            split_store(sQ, c, k2, R[(long long)(tj * TB + c) * TB + k2]);
+        }
+    }
+    CTile<float> acc[2][2];
+    load_acc(acc, A, Bp, ti * TB, tj * TB);
+    __syncthreads();
+    // C^T = Q^T P^T: MFMA rows are columns c of C, MFMA columns rows r
+    const int l = lane_id(), w = wave_id();
+    const int R0 = 32 * (w >> 1), C0 = 32 * (w & 1);
+    const int li = l & 15, kq = 8 * (l >> 4);
+#pragma unroll
+    for (int kc = 0; kc < TB; kc += 32) {
+        bf16x8 qrh[2], qrl[2], qih[2], qil[2], prh[2], prl[2], pih[2], pil[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int qo = (C0 + 16 * t + li) * LDB + kc + kq;
+            qrh[t] = ld8(sQ.rh + qo);
+            qrl[t] = ld8(sQ.rl + qo);
+            qih[t] = ld8(sQ.ih + qo);
+            qil[t] = ld8(sQ.il + qo);
+            const int po = (R0 + 16 * t + li) * LDB + kc + kq;
+            prh[t] = ld8(sP.rh + po);
+            prl[t] = ld8(sP.rl + po);
+            pih[t] = ld8(sP.ih + po);
+            pil[t] = ld8(sP.il + po);
+        }
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 2; ++tb) {
+                CTile<float>& c = acc[ta][tb];
+                // re += Qr Pr - Qi Pi ; im += Qr Pi + Qi Pr
+                c.re = split_mac(qrh[ta], qrl[ta], prh[tb], prl[tb], c.re);
+                c.re = split_mac(qih[ta], qil[ta], neg8(pih[tb]), neg8(pil[tb]), c.re);
+                c.im = split_mac(qrh[ta], qrl[ta], pih[tb], pil[tb], c.im);
+                c.im = split_mac(qih[ta], qil[ta], prh[tb], prl[tb], c.im);
+            }
+    }
+    store_acc(A, Bp, ti * TB, tj * TB, acc, 1.0f);
+}
+
 // ---------------------------------------------------------------------------
 // solves
 // ---------------------------------------------------------------------------
@@ -597,7 +716,7 @@ hipError_t launch_form3d(const asp_plan* P, const int* jobs, int njobs, int k, h
     a.k = k;
     a.S = P->S;
     dim3 grid((P->Bmax + 255) / 256, P->Bmax, njobs);
-    if (P->prec == ASP_PREC_FP32)
+    if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL(form3d_kernel<float>, grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(form3d_kernel<double>, grid, dim3(256), 0, st, a);
@@ -618,10 +737,13 @@ hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int
     a.jp = jp;
     a.ntmax = P->Bmax / TB;
     dim3 g0(njobs), g1(2 * a.ntmax, njobs), g2(a.ntmax * a.ntmax, njobs);
-    if (P->prec == ASP_PREC_FP32) {
+    if (P->prec != ASP_PREC_FP64) {
         hipLaunchKernelGGL(gj_pivot_kernel<float>, g0, dim3(1024), 0, st, a);
         hipLaunchKernelGGL(gj_panel_kernel<float>, g1, dim3(NT), 0, st, a);
-        hipLaunchKernelGGL(gj_update_kernel<float>, g2, dim3(NT), 0, st, a);
+        if (P->prec == ASP_PREC_BF16X3)
+            hipLaunchKernelGGL(gj_update_bf16x3_kernel, g2, dim3(NT), 0, st, a);
+        else
+            hipLaunchKernelGGL(gj_update_kernel<float>, g2, dim3(NT), 0, st, a);
     } else {
         hipLaunchKernelGGL(gj_pivot_kernel<double>, g0, dim3(1024), 0, st, a);
         hipLaunchKernelGGL(gj_panel_kernel<double>, g1, dim3(NT), 0, st, a);
@@ -635,7 +757,7 @@ hipError_t launch_gather3d(const asp_plan* P, const int* jobs, int njobs, const 
     const int chunks = (nact + RW - 1) / RW;
     const long long yj = (long long)P->n * P->Bmax * RW;
     dim3 grid((P->Bmax * RW + 255) / 256, P->n, njobs * chunks);
-    if (P->prec == ASP_PREC_FP32)
+    if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL(gather3d_kernel<float>, grid, dim3(256), 0, st, P->d_desc, jobs, njobs, r,
                            act, nact, static_cast<zf*>(P->d_g3), yj, P->Bmax, P->n, P->N, P->S);
     else
@@ -682,13 +804,13 @@ hipError_t launch_solve3d_step(const asp_plan* P, const Solve3Launch& L, int k, 
     if (L.two_sided) {
         // (FP64 operands take twice the registers: 8 wavefronts, 256 registers each)
         dim3 grid(P->Bmax / 16, L.njobs, chunks);
-        if (P->prec == ASP_PREC_FP32)
+        if (P->prec != ASP_PREC_FP64)
             hipLaunchKernelGGL((solve3d_step_kernel<float, 16, 1>), grid, dim3(1024), 0, st, a);
         else
             hipLaunchKernelGGL((solve3d_step_kernel<double, 8, 1>), grid, dim3(512), 0, st, a);
     } else {
         dim3 grid(P->Bmax / 32, L.njobs, chunks);
-        if (P->prec == ASP_PREC_FP32)
+        if (P->prec != ASP_PREC_FP64)
             hipLaunchKernelGGL((solve3d_step_kernel<float, 8, 2>), grid, dim3(512), 0, st, a);
         else
             hipLaunchKernelGGL((solve3d_step_kernel<double, 8, 2>), grid, dim3(512), 0, st, a);

@@ -150,7 +150,10 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (layer_b < 1) return fail(ASP_ERR_ARG, "layer_b must be >= 1");
     if (n < 1 || n - 2 * (pml_eta - 1) < 1) return fail(ASP_ERR_ARG, "n too small for the PML");
     if (!(o.C >= 0.0) || !std::isfinite(o.C)) return fail(ASP_ERR_ARG, "C must be finite and >= 0");
-    if (o.prec != ASP_PREC_FP64 && o.prec != ASP_PREC_FP32) return fail(ASP_ERR_ARG, "unknown precision");
+    if (o.prec != ASP_PREC_FP64 && o.prec != ASP_PREC_FP32 && o.prec != ASP_PREC_BF16X3)
+        return fail(ASP_ERR_ARG, "unknown precision");
+    if (o.prec == ASP_PREC_BF16X3 && dim != 3)
+        return fail(ASP_ERR_ARG, "the bf16 split precision applies to the 3D factorization only");
     if (dim == 3 && (long long)n * n * n > (1LL << 31)) return fail(ASP_ERR_ARG, "grid too large");
 
     P->dim = dim;
@@ -224,7 +227,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
         }
     }
     P->vec_elems = vec_off;
-    const size_t esz = (P->prec == ASP_PREC_FP32 ? sizeof(zf) : sizeof(zd));
+    const size_t esz = (P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd));
     P->fac_elems = fac_off;
     P->fac_bytes = (size_t)fac_off * esz;
     P->t_elems = tr_off;

@@ -146,3 +146,19 @@ def test_planned_factor_bytes(dim, n, b, gamma, prec):
     assert info["factored"] == 0
     if dim == 3 and n == 63 and prec == 1:
         assert 13.9e9 < info["factor_bytes"] < 15.0e9     # 13.9 GB unpadded, ~3% padding
+
+
+def test_bf16_split_precision_is_3d_only(L):
+    with pytest.raises(asp.AspError) as e:
+        asp.asp_setup(2, np.ones(63 * 63), 10.0, 63, 4, 12, prec=asp.ASP_PREC_BF16X3, host_only=True)
+    assert e.value.status == asp.ASP_ERR_ARG and "3D" in str(e.value)
+    plan = asp.asp_setup(3, np.ones(31 ** 3), 10.0, 31, 4, 8, prec=asp.ASP_PREC_BF16X3, host_only=True)
+    try:
+        fp32 = asp.asp_setup(3, np.ones(31 ** 3), 10.0, 31, 4, 8, prec=asp.ASP_PREC_FP32,
+                             host_only=True)
+        try:   # FP32 storage
+            assert asp.asp_info(plan)["factor_bytes"] == asp.asp_info(fp32)["factor_bytes"]
+        finally:
+            asp.asp_destroy(fp32)
+    finally:
+        asp.asp_destroy(plan)
