@@ -117,6 +117,8 @@ struct AxisTables {
 // ---------------------------------------------------------------------------
 // the plan
 // ---------------------------------------------------------------------------
+constexpr int SINK_ELEMS = 1024;   // complex128 entries of the discard buffer
+
 struct asp_plan {
     // problem
     int dim = 0, n = 0, b = 0, gamma = 0, g = 0, m = 0;
@@ -150,6 +152,7 @@ struct asp_plan {
     size_t fac_bytes = 0;
     long long fac_elems = 0;
     int* d_flag = nullptr;            // breakdown flag of the factorization
+    zd* d_sink = nullptr;             // SINK_ELEMS entries: target of stores a lane discards
     bool factored = false;
 
     // boundary-to-boundary maps T^R_p, T^L_p (1 < p < m), n x n each, column-major

@@ -160,6 +160,7 @@ struct SolveArgs {
     void* Tout;          // OUT_LINE: boundary-to-boundary maps
     void* y;
     long long y_per_wave;   // scratch entries per workgroup
+    zd* sink;               // discard buffer: four entries per thread
     int n;
     long long N;
 };
@@ -171,6 +172,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     constexpr int SRB = 1024 / LR;          // right-hand sides per workgroup
     constexpr int NCT = SRB / 16;           // right-hand-side tiles
     static_assert((LR / 16) * NCT == 4, "four 16 x 16 tiles, one per wavefront");
+    static_assert(SB * 4 <= SINK_ELEMS, "four discard entries per thread");
     constexpr int FMAX = 32 * LR;           // largest block (L <= 32)
     constexpr int FPT = FMAX / SB;
     constexpr int TBS = SRB + 1;            // padded row stride of the step vectors
@@ -234,6 +236,15 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         return acc;
     };
 
+    // Every memory operation of the step loops is issued by every lane, from a
+    // valid address (loads clamp their index; a store a lane does not keep
+    // goes to the discard buffer), and the loops have no branch inside: the
+    // wait for a load issued two steps ahead then counts exactly the
+    // operations issued after it.  (The vector memory counter also counts
+    // stores, and a branch makes the compiler assume the shorter path.)
+    zd* const sink = a.sink + tid * 4;
+    cplx<T>* const sinkT = reinterpret_cast<cplx<T>*>(sink);
+
     // step data of this lane's rows (complex128): grid data (IN_GRID), the
     // boundary data of its right-hand side (IN_BOUNDARY), or a dummy valid
     // address (IN_UNIT, stride 0)
@@ -250,21 +261,27 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         for (int v = 0; v < 4; ++v) g[v] = inp[v][(long long)(k - 1) * ink];
     };
     // t_k = g_k - E_{k-1} y_{k-1} for this lane's entries into tb[k & 1]
+    // (shm, ism: s at line k - 1/2 and 1 / s^2 at line k - 1 of axis 1).  The
+    // data term is g_k (grid rows of X), g_k times the Dirichlet coupling
+    // (boundary data on the carrying row) or the coupling alone (unit data on
+    // the carrying row at step slot + 1), selected by per-lane weights.
+    double wg[4], wb[4];
+    bool wu[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        wg[v] = (a.in_mode == IN_GRID && inX[v]) ? 1.0 : 0.0;
+        wb[v] = (a.in_mode == IN_BOUNDARY && rowv[v] && row[v] == grow) ? 1.0 : 0.0;
+        wu[v] = a.in_mode == IN_UNIT && rowv[v] && row[v] == grow;
+    }
     auto put_input = [&](int k, const zd (&g)[4], const cplx<T> (&y)[4], zd shm, zd ism) {
         const zd cin = -(coupl * ism);
         const cplx<T> shc = ccast<T>(shm);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            if (!rowv[v]) continue;
-            cplx<T> t = mk<T>(0, 0);
-            if (a.in_mode == IN_GRID)
-                t = inX[v] ? ccast<T>(g[v]) : mk<T>(0, 0);
-            else if (row[v] == grow && a.in_mode == IN_BOUNDARY)
-                t = ccast<T>(g[v] * cin);
-            else if (row[v] == grow && a.in_mode == IN_UNIT && slot == k - 1)   // unit data at i1 = slot + 1
-                t = ccast<T>(cin);
-            if (k > 1) t = t - (shc * sinv2[v]) * y[v];
-            tb[k & 1][row[v]][rloc] = t;
+            const zd dv = g[v] * (mk(wg[v], 0.0) + wb[v] * cin);
+            cplx<T> t = ccast<T>((wu[v] && slot == k - 1) ? cin : dv);
+            t = t - (shc * sinv2[v]) * y[v];              // y = 0 at the first step
+            tb[k & 1][row[v]][rloc] = rowv[v] ? t : mk<T>(0, 0);
         }
     };
 
@@ -273,7 +290,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // starts there and the backward pass reads no results before it
     const int kstart = (a.in_mode == IN_UNIT) ? min(ch * SRB + 1, n) : 1;
     // The loads of a step are issued two steps ahead into one of two register
-    // slots; the step loops are unrolled by two so that the slots stay in fixed
+    // slots; the step loops run in pairs so that the slots stay in fixed
     // registers (a register copy would wait for its load).
     auto fetch_to = [&](cplx<T> (&p)[FPT], int blk) {
         const cplx<T>* Fk = F + (long long)blk * FS;
@@ -284,7 +301,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
         for (int u = 0; u < FPT; ++u) {
             const int e = tid + u * SB;
-            if (e < FS) Fs[buf][e] = p[u];
+            Fs[buf][e] = (e < FS) ? p[u] : mk<T>(0, 0);
         }
     };
     cplx<T> yk[4];
@@ -292,55 +309,59 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     for (int v = 0; v < 4; ++v) yk[v] = mk<T>(0, 0);
 
     // forward sweep: y_k = S_k^-1 t_k; block k-1 (S_k^-1) sits in ring slot
-    // k & 1.  Slot of step k: the input g_{k+1} and block k, both used at the
-    // end of step k.
+    // k & 1.  Slot of step k: the input g_{k+1}, the couplings of lines k, k+1
+    // and block k, all used at the end of step k.  The last step stashes block
+    // n-2 (already in its ring slot) and forms an input nobody reads: the
+    // backward pass finds block n-2 where it expects it and overwrites tb.
     struct FwdSlot {
         cplx<T> pf[FPT];
         zd g[4];
+        zd sh, ism;
+    };
+    auto prefetch_f = [&](FwdSlot& S, int k) {
+        load_in(min(k + 1, n), S.g);
+        fetch_to(S.pf, k <= n - 1 ? k : max(n - 2, 0));
+        const int kc = min(k, n - 1);
+        S.sh = a.ax.sh[kc];
+        S.ism = a.ax.inv_sh2[kc];
     };
     FwdSlot fsl[2];
     {
         zd g0[4];
         load_in(kstart, g0);
         fetch_to(fsl[0].pf, kstart - 1);
+        const zd sh0 = a.ax.sh[kstart - 1], ism0 = a.ax.inv_sh2[kstart - 1];
         stash_from(fsl[0].pf, kstart & 1);
-        put_input(kstart, g0, yk, a.ax.sh[kstart - 1], a.ax.inv_sh2[kstart - 1]);
+        put_input(kstart, g0, yk, sh0, ism0);
     }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int k = kstart + t;
-        if (k < n) {
-            load_in(k + 1, fsl[t].g);
-            fetch_to(fsl[t].pf, k);
-        }
-    }
-    auto fwd_step = [&](int k, FwdSlot& S) {
+    prefetch_f(fsl[0], kstart);
+    prefetch_f(fsl[1], kstart + 1);
+    auto fwd_step = [&](int k, FwdSlot& S, auto pre) {
         const int buf = k & 1;
         __syncthreads();
         const CTile<T> acc = product(buf, buf);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             yk[v] = mk<T>(acc.re[v], acc.im[v]);
-            if (rowv[v]) Y[((long long)(k - 1) * LR + row[v]) * SRB + rloc] = yk[v];
+            Y[((long long)(k - 1) * LR + row[v]) * SRB + rloc] = yk[v];   // rows past L: zero
         }
-        if (k < n) {
-            stash_from(S.pf, (k + 1) & 1);                           // block k
-            put_input(k + 1, S.g, yk, a.ax.sh[k], a.ax.inv_sh2[k]);
-            if (k + 2 < n) {
-                load_in(k + 3, S.g);
-                fetch_to(S.pf, k + 2);
-            }
-        }
+        stash_from(S.pf, (k + 1) & 1);                               // block k
+        put_input(k + 1, S.g, yk, S.sh, S.ism);
+        // the slot's next loads after its last use, so that they reuse its registers
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (decltype(pre)::value) prefetch_f(S, k + 2);
     };
-    for (int k = kstart; k <= n; k += 2) {
-        fwd_step(k, fsl[0]);
-        if (k + 1 <= n) fwd_step(k + 1, fsl[1]);
+    int kf = kstart;
+    for (; kf + 1 <= n; kf += 2) {
+        fwd_step(kf, fsl[0], std::true_type{});
+        fwd_step(kf + 1, fsl[1], std::true_type{});
     }
+    if (kf <= n) fwd_step(kf, fsl[0], std::false_type{});   // the last step: nothing to fetch
 
     // backward sweep: v_n = y_n, v_k = y_k - S_k^-1 E_k v_{k+1}; block k-1 in
-    // ring slot k & 1 (block n-2 is still in slot (n-1) & 1 unless the forward
-    // pass started at block n).  Slot of step k: y_k and the values its outputs
-    // add to (used in step k), and block k-2 (stashed at the end of step k).
+    // ring slot k & 1.  Slot of step k: y_k, the values its outputs add to and
+    // the coupling of lines k-1, k (used in step k), and block k-2 (stashed at
+    // the end of step k).  Step 1 stashes and forms data nobody reads.
     const int jout = (d.kind == ASP_SUB_R) ? (d.xe - d.lo) : (d.xs - d.lo);   // OUT_LINE row
     const int omode = (d.kind == ASP_SUB_L) ? a.out_mode_L : a.out_mode;
     zd* const outp = (d.kind == ASP_SUB_L) ? a.out_L : a.out;
@@ -363,80 +384,86 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         const long long kk = max(k, kstart);     // blocks before kstart: y = 0
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const cplx<T> y0 = Y[((kk - 1) * LR + min(row[v], L - 1)) * SRB + rloc];
-            yv[v] = (k >= kstart && rowv[v]) ? y0 : mk<T>(0, 0);
+            const cplx<T> y0 = Y[((kk - 1) * LR + row[v]) * SRB + rloc];
+            yv[v] = (k >= kstart) ? y0 : mk<T>(0, 0);
         }
     };
-    cplx<T>* Tp = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off + (long long)slot * n;
+    // the one entry of this lane on the OUT_LINE row, if any
+    int jsel = -1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (rowv[e] && row[e] == jout) jsel = e;
+    cplx<T>* const Tp = (valid && jsel >= 0)
+                            ? reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off + (long long)slot * n
+                            : nullptr;
+    bool keep[4];
+    zd* gout[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        keep[e] = valid && inX[e];
+        gout[e] = outp + (long long)rid * N + (long long)n * (lcl[e] - 1);
+    }
     auto emit = [&](int k, const cplx<T> (&v)[4], const zd (&av)[4]) {
-        if (!valid) return;
+        if (!grid_out) {
+            cplx<T> x = v[0];
+#pragma unroll
+            for (int e = 1; e < 4; ++e) x = (jsel == e) ? v[e] : x;
+            *(Tp ? Tp + (k - 1) : sinkT) = x;
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            if (!grid_out) {
-                if (rowv[e] && row[e] == jout) Tp[k - 1] = v[e];
-                continue;
-            }
-            if (!inX[e]) continue;
-            outp[(long long)rid * N + (k - 1) + (long long)n * (lcl[e] - 1)] =
-                use_add ? ccast<double>(v[e]) + av[e] : ccast<double>(v[e]);
+            const zd x = use_add ? ccast<double>(v[e]) + av[e] : ccast<double>(v[e]);
+            *(keep[e] ? gout[e] + (k - 1) : sink + e) = x;
         }
     };
-    // E_k v_{k+1} for this lane's entries into tb[k & 1]
-    auto put_coupled = [&](int k, const cplx<T> (&v)[4]) {
-        const cplx<T> shc = ccast<T>(a.ax.sh[k]);                 // coupling of blocks k, k+1
+    // E_k v_{k+1} for this lane's entries into tb[k & 1] (shk: s at line k + 1/2)
+    auto put_coupled = [&](int k, const cplx<T> (&v)[4], zd shk) {
+        const cplx<T> shc = ccast<T>(shk);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (rowv[e]) tb[k & 1][row[e]][rloc] = (shc * sinv2[e]) * v[e];
+        for (int e = 0; e < 4; ++e) tb[k & 1][row[e]][rloc] = (shc * sinv2[e]) * v[e];
     };
     struct BwdSlot {
         cplx<T> pf[FPT];
         cplx<T> y[4];
         zd av[4];
+        zd sh;
+    };
+    auto prefetch_b = [&](BwdSlot& S, int k) {
+        load_y(k, S.y);
+        load_add(max(k, 1), S.av);
+        fetch_to(S.pf, max(k - 2, 0));
+        S.sh = a.ax.sh[max(k - 1, 0)];
     };
     BwdSlot bsl[2];
     {
         zd an[4];
         load_add(n, an);
+        const zd shn = a.ax.sh[max(n - 1, 0)];
         emit(n, yk, an);
+        put_coupled(n - 1, yk, shn);    // n = 1: data nobody reads
     }
     cplx<T> (&vk)[4] = yk;
-    if (n >= 2) {
-        if (kstart > n - 1) {
-            fetch_to(bsl[0].pf, n - 2);
-            stash_from(bsl[0].pf, (n - 1) & 1);
-        }
-        put_coupled(n - 1, vk);
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int k = n - 1 - t;
-        if (k >= 1) {
-            load_y(k, bsl[t].y);
-            load_add(k, bsl[t].av);
-            if (k > 1) fetch_to(bsl[t].pf, k - 2);
-        }
-    }
-    auto bwd_step = [&](int k, BwdSlot& S) {
+    prefetch_b(bsl[0], n - 1);
+    prefetch_b(bsl[1], n - 2);
+    auto bwd_step = [&](int k, BwdSlot& S, auto pre) {
         const int buf = k & 1;
         __syncthreads();
         const CTile<T> acc = product(buf, buf);
 #pragma unroll
         for (int e = 0; e < 4; ++e) vk[e] = S.y[e] - mk<T>(acc.re[e], acc.im[e]);
         emit(k, vk, S.av);
-        if (k > 1) {
-            stash_from(S.pf, (k - 1) & 1);                           // block k-2
-            put_coupled(k - 1, vk);
-            if (k - 2 >= 1) {
-                load_y(k - 2, S.y);
-                load_add(k - 2, S.av);
-                if (k - 2 > 1) fetch_to(S.pf, k - 4);
-            }
-        }
+        stash_from(S.pf, (k - 1) & 1);                               // block k-2
+        put_coupled(k - 1, vk, S.sh);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (decltype(pre)::value) prefetch_b(S, k - 2);
     };
-    for (int k = n - 1; k >= 1; k -= 2) {
-        bwd_step(k, bsl[0]);
-        if (k - 1 >= 1) bwd_step(k - 1, bsl[1]);
+    int kb = n - 1;
+    for (; kb - 1 >= 1; kb -= 2) {
+        bwd_step(kb, bsl[0], std::true_type{});
+        bwd_step(kb - 1, bsl[1], std::true_type{});
     }
+    if (kb >= 1) bwd_step(kb, bsl[0], std::false_type{});
 }
 
 // ----------------------------------------------------------------------------
@@ -618,6 +645,7 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     a.Tout = P->d_T;
     a.y = P->d_y;
     a.y_per_wave = solve_scratch_per_block(P);
+    a.sink = P->d_sink;
     a.n = P->n;
     a.N = P->N;
     const int LR = L.rl ? P->LR_RL : P->LR_M;   // every job of one launch shares its row count

@@ -298,6 +298,8 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     }
     if (hipMalloc(reinterpret_cast<void**>(&P->d_flag), sizeof(int)) != hipSuccess)
         return fail(ASP_ERR_OOM, "hipMalloc failed");
+    if (hipMalloc(reinterpret_cast<void**>(&P->d_sink), SINK_ELEMS * sizeof(zd)) != hipSuccess)
+        return fail(ASP_ERR_OOM, "hipMalloc failed");
     // the host vectors above are released on return: finish the copies first
     if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(ASP_ERR_DEVICE, "upload failed");
     *out = P;
@@ -310,7 +312,7 @@ extern "C" void asp_destroy(asp_plan* P) {
         delete P;
         return;
     }
-    void* bufs[] = {P->d_ksq, P->d_axis, P->d_subtab, P->d_desc, P->d_jobs, P->d_fac, P->d_flag,
+    void* bufs[] = {P->d_ksq, P->d_axis, P->d_subtab, P->d_desc, P->d_jobs, P->d_fac, P->d_flag, P->d_sink,
                     P->d_T, P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_y, P->d_V, P->d_Z, P->d_b,
                     P->d_red, P->d_small, P->d_act, P->d_e3, P->d_gv3, P->d_y3,
                     P->d_g3, P->d_w3};
