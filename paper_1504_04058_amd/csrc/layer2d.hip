@@ -248,17 +248,24 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // step data of this lane's rows (complex128): grid data (IN_GRID), the
     // boundary data of its right-hand side (IN_BOUNDARY), or a dummy valid
     // address (IN_UNIT, stride 0)
+    // Rows whose data the step ignores read a fixed table entry instead (stride
+    // 0), so that they cost no memory traffic.
     const zd* inp[4];
+    int ink[4];
     const long long bbase = ((long long)d.wrow * a.w_rhs + rid) * n;
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-        inp[v] = (a.in_mode == IN_GRID)       ? a.r + (long long)rid * N + (long long)n * (lcl[v] - 1)
-                 : (a.in_mode == IN_BOUNDARY) ? a.W + bbase
-                                              : a.subtab;
-    const int ink = (a.in_mode == IN_UNIT) ? 0 : 1;
+    for (int v = 0; v < 4; ++v) {
+        const bool used = (a.in_mode == IN_GRID) ? inX[v]
+                          : (a.in_mode == IN_BOUNDARY) ? (rowv[v] && row[v] == grow)
+                                                       : false;
+        inp[v] = !used                      ? a.subtab
+                 : (a.in_mode == IN_GRID) ? a.r + (long long)rid * N + (long long)n * (lcl[v] - 1)
+                                          : a.W + bbase;
+        ink[v] = used ? 1 : 0;
+    }
     auto load_in = [&](int k, zd (&g)[4]) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) g[v] = inp[v][(long long)(k - 1) * ink];
+        for (int v = 0; v < 4; ++v) g[v] = inp[v][(long long)(k - 1) * ink[v]];
     };
     // t_k = g_k - E_{k-1} y_{k-1} for this lane's entries into tb[k & 1]
     // (shm, ism: s at line k - 1/2 and 1 / s^2 at line k - 1 of axis 1).  The
@@ -336,6 +343,10 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     }
     prefetch_f(fsl[0], kstart);
     prefetch_f(fsl[1], kstart + 1);
+    // one full wait before the loop: with nothing outstanding on entry, the
+    // waits inside the loop count only the loop's own operations (otherwise the
+    // compiler merges in the prologue's shorter history and waits for all)
+    __builtin_amdgcn_s_waitcnt(0);
     auto fwd_step = [&](int k, FwdSlot& S, auto pre) {
         const int buf = k & 1;
         __syncthreads();
@@ -370,15 +381,20 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const bool add_out = !set_u && omode == OUT_GRID_ACC;
     const bool grid_out = omode != OUT_LINE;
     const bool use_add = set_u || add_out;
+    // values the outputs add to, on the rows this lane writes (others: a fixed
+    // table entry, stride 0)
     const zd* addp[4];
+    int addk[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-        addp[v] = use_add ? (set_u ? a.Ugrid : outp) + (long long)rid * N + (long long)n * (lcl[v] - 1)
-                          : a.subtab;
-    const int addk = use_add ? 1 : 0;
+    for (int v = 0; v < 4; ++v) {
+        const bool used = use_add && grid_out && valid && inX[v];
+        addp[v] = used ? (set_u ? a.Ugrid : outp) + (long long)rid * N + (long long)n * (lcl[v] - 1)
+                       : a.subtab;
+        addk[v] = used ? 1 : 0;
+    }
     auto load_add = [&](int k, zd (&av)[4]) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) av[v] = addp[v][(long long)(k - 1) * addk];
+        for (int v = 0; v < 4; ++v) av[v] = addp[v][(long long)(k - 1) * addk[v]];
     };
     auto load_y = [&](int k, cplx<T> (&yv)[4]) {
         const long long kk = max(k, kstart);     // blocks before kstart: y = 0
@@ -446,6 +462,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     cplx<T> (&vk)[4] = yk;
     prefetch_b(bsl[0], n - 1);
     prefetch_b(bsl[1], n - 2);
+    __builtin_amdgcn_s_waitcnt(0);
     auto bwd_step = [&](int k, BwdSlot& S, auto pre) {
         const int buf = k & 1;
         __syncthreads();
