@@ -58,8 +58,14 @@ template <typename T>
 __host__ __device__ __forceinline__ T abs2(cplx<T> a) { return a.x * a.x + a.y * a.y; }
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> cinv(cplx<T> a) {
-    T d = a.x * a.x + a.y * a.y;
-    return {a.x / d, -a.y / d};
+    const T r = T(1) / (a.x * a.x + a.y * a.y);
+    return {a.x * r, -a.y * r};
+}
+// c ? a : b per component (a select of whole structs can become a select of
+// their addresses, which puts them in scratch memory)
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> csel(bool c, cplx<T> a, cplx<T> b) {
+    return {c ? a.x : b.x, c ? a.y : b.y};
 }
 template <typename To, typename Ti>
 __host__ __device__ __forceinline__ cplx<To> ccast(cplx<Ti> a) { return {(To)a.x, (To)a.y}; }

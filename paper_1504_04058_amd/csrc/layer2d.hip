@@ -20,6 +20,7 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int MAXL = 32;
+static_assert(WAVE * 16 <= SINK_ELEMS, "sixteen discard entries per lane");
 
 // ----------------------------------------------------------------------------
 // factorization: one wavefront per auxiliary problem.  Lane (j, h) holds rows
@@ -36,7 +37,8 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
                                                       const zd* __restrict__ subtab,
                                                       const double* __restrict__ ksq, int n,
                                                       cplx<TS>* __restrict__ fac,
-                                                      int* __restrict__ flag) {
+                                                      int* __restrict__ flag,
+                                                      cplx<TS>* __restrict__ sink) {
     __shared__ zd rowbuf[2][MAXL];
     __shared__ zd colbuf[2][MAXL];
 
@@ -50,83 +52,95 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
     const zd* sinv2 = tab + L + 1;      // 1/(s h^2) on lines lo..hi
     const zd* sinv = tab + 2 * L + 1;   // 1/s on lines lo..hi
     const int LR = d.LR;
-    const zd sj = cj ? sinv2[j] : mk(0.0, 0.0);
+    const int jc = min(j, L - 1);
+    // tables that do not change along axis 1: 1/(s h^2) per row (LDS, zero
+    // past L) and, for this lane's column j, the couplings to rows j -+ 1
+    __shared__ zd srow[MAXL];
+    if (h == 0) srow[j] = csel(cj, sinv2[jc], mk(0.0, 0.0));
+    const zd sj = csel(cj, sinv2[jc], mk(0.0, 0.0));
+    const zd c_lo = ssh[jc], c_hi = ssh[jc + 1], sinvj = sinv[jc];
+    const double* ksq_j = ksq + (long long)n * (d.lo + jc - 1);
     bool bad = false;
     zd v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = mk(0.0, 0.0);
 
+    // the tables of block k (couplings s1 at k -+ 1/2, 1/(s1 h^2), 1/s1 and
+    // omega^2/c^2 on this lane's diagonal point), fetched one block ahead
+    struct Step {
+        zd sh_m, sh_p, is2, is;
+        double kq;
+    };
+    auto fetch = [&](Step& S, int k) {
+        S.sh_m = ax.sh[k - 1];
+        S.sh_p = ax.sh[k];
+        S.is2 = ax.inv_sh2[k - 1];
+        S.is = ax.inv_s[k - 1];
+        S.kq = ksq_j[k - 1];
+    };
+    Step cur, nxt;
+    fetch(cur, 1);
+    // nothing outstanding on entry: the waits in the loop count its own operations
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     for (int k = 1; k <= n; ++k) {
-        const zd sh_m = ax.sh[k - 1];   // s1 at k - 1/2
-        const zd sh_p = ax.sh[k];       // s1 at k + 1/2
-        const zd is2k = ax.inv_sh2[k - 1];
-        const zd isk = ax.inv_s[k - 1];
+        fetch(nxt, min(k + 1, n));
         // S_k = D_k - E_{k-1} S_{k-1}^-1 E_{k-1} over S_{k-1}^-1; identity padding
-        const zd ej = sh_m * sj;
+        const zd ej = cur.sh_m * sj;
+        const zd diag = (cur.kq * cur.is) * sinvj - (cur.sh_p + cur.sh_m) * sj -
+                        (c_hi + c_lo) * cur.is2;
+        const zd off_lo = c_lo * cur.is2;   // row j - 1
+        const zd off_hi = c_hi * cur.is2;   // row j + 1
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = 16 * h + q;
-            zd val = mk(0.0, 0.0);
-            if (i < L && cj) {
-                if (k > 1) val = -((sh_m * sinv2[i]) * v[q] * ej);
-                if (i == j) {
-                    const zd lap1 = (sh_p + sh_m) * sinv2[i];
-                    const zd lap2 = (ssh[i + 1] + ssh[i]) * is2k;
-                    const zd mass =
-                        (ksq[(long long)(k - 1) + (long long)n * (d.lo + i - 1)] * isk) * sinv[i];
-                    val = val + mass - lap1 - lap2;
-                } else if (j == i + 1) {
-                    val = val + ssh[i + 1] * is2k;
-                } else if (j == i - 1) {
-                    val = val + ssh[i] * is2k;
+            zd val = csel(k > 1, -((cur.sh_m * srow[i]) * v[q] * ej), mk(0.0, 0.0));
+            const zd add = csel(i == j, diag,
+                                csel(i == j - 1, off_lo, csel(i == j + 1, off_hi, mk(0.0, 0.0))));
+            val = val + add;
+            const bool inside = i < L && cj;
+            v[q] = csel(inside, val, mk(i == j ? 1.0 : 0.0, 0.0));
+        }
+        // in-place inverse; the pivots run in groups of 16 with the pivot's
+        // register index fixed at compile time
+        for (int kb = 0; kb < L; kb += 16) {
+            const int hb = kb >> 4;
+#pragma unroll
+            for (int pq = 0; pq < 16; ++pq) {
+                const int kk = kb + pq;
+                if (kk >= L) continue;
+                const int b = pq & 1;
+                if (h == hb) rowbuf[b][j] = v[pq];
+                if (j == kk)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) colbuf[b][16 * h + q] = v[q];
+                __syncthreads();
+                const zd p = colbuf[b][kk];
+                const double pa = abs2(p);
+                if (!(pa > 1e-300) || !isfinite(pa)) bad = true;
+                const zd pinv = cinv(p);
+                const zd rp = rowbuf[b][j] * pinv;            // A[kk][j] / p
+                const bool jp = j == kk, hp = h == hb;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const zd ci = colbuf[b][16 * h + q];       // A[i][kk]
+                    zd x = v[q] - ci * rp;
+                    if (q == pq) x = csel(hp, rp, x);
+                    const zd xc = csel(q == pq && hp, pinv, -(ci * pinv));
+                    v[q] = csel(jp, xc, x);
                 }
-            } else if (i == j) {
-                val = mk(1.0, 0.0);
-            }
-            v[q] = val;
-        }
-        // in-place inverse
-        for (int kk = 0; kk < L; ++kk) {
-            const int b = kk & 1;
-            if (h == (kk >> 4)) {
-                // select by value: a pointer into v would move it to scratch memory
-                zd pr = v[0];
-#pragma unroll
-                for (int q = 1; q < 16; ++q) {
-                    const bool hit = q == (kk & 15);
-                    pr.x = hit ? v[q].x : pr.x;
-                    pr.y = hit ? v[q].y : pr.y;
-                }
-                rowbuf[b][j] = pr;
-            }
-            if (j == kk)
-#pragma unroll
-                for (int q = 0; q < 16; ++q) colbuf[b][16 * h + q] = v[q];
-            __syncthreads();
-            const zd p = colbuf[b][kk];
-            const double pa = abs2(p);
-            if (!(pa > 1e-300) || !isfinite(pa)) bad = true;
-            const zd pinv = cinv(p);
-            const zd rp = rowbuf[b][j] * pinv;            // A[kk][j] / p
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = 16 * h + q;
-                const zd ci = colbuf[b][i];                // A[i][kk]
-                zd x = v[q] - ci * rp;
-                if (i == kk) x = rp;
-                if (j == kk) x = (i == kk) ? pinv : -(ci * pinv);
-                v[q] = x;
             }
         }
-        // store S_k^-1 column-major with leading dimension LR (rows past L zero)
-        if (cj) {
-            cplx<TS>* out = fac + d.fac_off + (long long)(k - 1) * L * LR + (long long)j * LR;
+        // store S_k^-1 column-major with leading dimension LR (rows past L zero);
+        // lanes outside the block write to the discard buffer
+        cplx<TS>* out = fac + d.fac_off + (long long)(k - 1) * L * LR + (long long)j * LR;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = 16 * h + q;
-                if (i < LR) out[i] = ccast<TS>(i < L ? v[q] : mk(0.0, 0.0));
-            }
+        for (int q = 0; q < 16; ++q) {
+            const int i = 16 * h + q;
+            const bool keep = cj && i < LR;
+            *(keep ? out + i : sink + lane * 16 + q) = ccast<TS>(csel(i < L, v[q], mk(0.0, 0.0)));
         }
+        cur = nxt;
     }
     if (bad) *flag = 1;
 }
@@ -423,7 +437,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         if (!grid_out) {
             cplx<T> x = v[0];
 #pragma unroll
-            for (int e = 1; e < 4; ++e) x = (jsel == e) ? v[e] : x;
+            for (int e = 1; e < 4; ++e) x = csel(jsel == e, v[e], x);
             *(Tp ? Tp + (k - 1) : sinkT) = x;
             return;
         }
@@ -617,11 +631,11 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
     if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL(factor2d_kernel<float>, dim3(nsub), dim3(WAVE), 0, st, P->d_desc, ax,
                            P->d_subtab, P->d_ksq, P->n, reinterpret_cast<zf*>(P->d_fac),
-                           P->d_flag);
+                           P->d_flag, reinterpret_cast<zf*>(P->d_sink));
     else
         hipLaunchKernelGGL(factor2d_kernel<double>, dim3(nsub), dim3(WAVE), 0, st, P->d_desc,
                            ax, P->d_subtab, P->d_ksq, P->n, reinterpret_cast<zd*>(P->d_fac),
-                           P->d_flag);
+                           P->d_flag, P->d_sink);
     return hipGetLastError();
 }
 

@@ -228,11 +228,11 @@ __global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
         // A[piv][c] / p and the pivot column -A[r][piv] / p (1 / p at the pivot)
         const bool prow = r == piv;
         const cplx<T> crp = cb[r] * pinv;
-        const cplx<T> colv = prow ? pinv : -crp;
+        const cplx<T> colv = csel(prow, pinv, -crp);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const cplx<T> rc = rb[cg + 16 * e];
-            cplx<T> x = prow ? rc * pinv : v[e] - crp * rc;
+            cplx<T> x = csel(prow, rc * pinv, v[e] - crp * rc);
             const bool pcol = (cg + 16 * e) == piv;
             x.x = pcol ? colv.x : x.x;
             x.y = pcol ? colv.y : x.y;
@@ -507,7 +507,7 @@ __device__ __forceinline__ void mac_batch(CTile<T> (&acc)[RT], const StepBatch<T
                                           bool with_v) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        cplx<T> t = with_g ? B.g[u] : mk<T>(T(0), T(0));
+        cplx<T> t = csel(with_g, B.g[u], mk<T>(T(0), T(0)));
         if (with_v) t = t - ccast<T>(cf * B.e[u]) * B.v[u];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) cmac(acc[rt], B.m[rt][u], t);
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(64 * NW) void solve3d_step_kernel(Solve3Args a) {
                     const int c = L * i2c + dl;
                     const zd wv = win[((long long)k + (long long)a.n * i2c) * a.ws + slot_l];
                     const bool on = i2 < a.n && live_l;
-                    const cplx<T> t = on ? ccast<T>((is1 * gv[c]) * wv) : mk<T>(T(0), T(0));
+                    const cplx<T> t = csel(on, ccast<T>((is1 * gv[c]) * wv), mk<T>(T(0), T(0)));
 #pragma unroll
                     for (int rt = 0; rt < RT; ++rt)
                         cmac(acc[rt], Mk[(long long)c * Bp + r0 + 16 * rt + li], t);
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(64 * NW) void solve3d_step_kernel(Solve3Args a) {
         *yk = s;
         return;
     }
-    const cplx<T> x = skip ? *yk : *yk - s;
+    const cplx<T> x = csel(skip, *yk, *yk - s);
     *yk = x;
     const int B = a.n * L;
     if (row >= B || slot >= a.nact) return;
