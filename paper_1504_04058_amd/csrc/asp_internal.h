@@ -322,6 +322,15 @@ struct KTimer {
 hipError_t launch_scale_by_s(const asp_plan* P, const zd* f, zd* b, int nrhs, hipStream_t st);
 // partial[r][blk][i] = sum conj(V_i[r]) w[r] for i in [i0, i1)
 int krylov_blocks(long long N);
+// fused Gram-Schmidt passes (modes: 0 dots, 1 update then dots, 2 update then
+// norm) over nv <= CGS_MAXV basis vectors; partial sums [rhs][block][CGS_MAXV]
+constexpr int CGS_MAXV = 24;
+int cgs_blocks(long long N);
+hipError_t launch_cgs(int mode, int nv, const zd* V, long long vstride, const zd* coef,
+                      int coef_stride, zd* w, long long N, const int* act, int nact, zd* partial,
+                      hipStream_t st);
+hipError_t launch_cgs_reduce(const zd* partial, int nblk, int nv, const int* act, int nact,
+                             zd* out, int out_stride, hipStream_t st);
 hipError_t launch_multidot(const zd* V, long long vstride, int i0, int i1, const zd* w,
                            long long N, const int* act, int nact, zd* partial, hipStream_t st);
 // out[r][i] = sum_blk partial[r][blk][i], i < ni, fixed order

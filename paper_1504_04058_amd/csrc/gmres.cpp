@@ -50,12 +50,13 @@ asp_status ensure_krylov_ws(asp_plan* P, int nrhs, int restart) {
     if (dev_alloc(P, &P->d_V, vec * (restart + 1)) != ASP_OK) return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_Z, vec * restart) != ASP_OK) return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_b, vec) != ASP_OK) return ASP_ERR_OOM;
-    if (dev_alloc(P, &P->d_red, (size_t)nrhs * nblk * CH) != ASP_OK) return ASP_ERR_OOM;
+    const size_t red = std::max((size_t)nblk * CH, (size_t)cgs_blocks(P->N) * CGS_MAXV);
+    if (dev_alloc(P, &P->d_red, (size_t)nrhs * red) != ASP_OK) return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_small, (size_t)nrhs * SMALL + nrhs) != ASP_OK) return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_act, (size_t)nrhs) != ASP_OK) return ASP_ERR_OOM;
     P->kr_rhs = nrhs;
     P->kr_restart = restart;
-    P->kr_bytes = vec * (2 * restart + 2) * sizeof(zd) + (size_t)nrhs * nblk * CH * sizeof(zd);
+    P->kr_bytes = vec * (2 * restart + 2) * sizeof(zd) + (size_t)nrhs * red * sizeof(zd);
     return ASP_OK;
 }
 
@@ -199,24 +200,41 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
             ASP_TIMED(P, ASP_K_STENCIL, 32.0 * ni * N + 8.0 * N, 40.0 * ni * N,
                       launch_stencil(P, zj, w, P->d_act, ni, st));
             // two passes of classical Gram-Schmidt against v_0..v_j
-            for (int pass = 0; pass < 2; ++pass) {
-                const int off = pass == 0 ? OFF_H1 : OFF_H2;
-                for (int c0 = 0; c0 <= j; c0 += CH) {
-                    const int c1 = std::min(j + 1, c0 + CH);
-                    ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * (c1 - c0 + 1) * ni * N, 8.0 * (c1 - c0) * ni * N,
-                              launch_multidot(V, vs, c0, c1, w, N, P->d_act, ni, P->d_red, st));
-                    ASP_HIP(P, launch_reduce(P->d_red, nblk, c1 - c0, P->d_act, ni, small + off + c0,
-                                             SMALL, st));
+            if (j + 1 <= CGS_MAXV) {
+                // fused: h1 = V^H w; w -= V h1 and h2 = V^H w; w -= V h2 and |w|^2
+                const int nv = j + 1, cb = cgs_blocks(N);
+                const double vb = 16.0 * ni * N;
+                ASP_TIMED(P, ASP_K_KRYLOV, vb * (nv + 1), 8.0 * nv * ni * N,
+                          launch_cgs(0, nv, V, vs, nullptr, 0, w, N, P->d_act, ni, P->d_red, st));
+                ASP_HIP(P, launch_cgs_reduce(P->d_red, cb, nv, P->d_act, ni, small + OFF_H1, SMALL, st));
+                ASP_TIMED(P, ASP_K_KRYLOV, vb * (nv + 2), 16.0 * nv * ni * N,
+                          launch_cgs(1, nv, V, vs, small + OFF_H1, SMALL, w, N, P->d_act, ni,
+                                     P->d_red, st));
+                ASP_HIP(P, launch_cgs_reduce(P->d_red, cb, nv, P->d_act, ni, small + OFF_H2, SMALL, st));
+                ASP_TIMED(P, ASP_K_KRYLOV, vb * (nv + 2), 8.0 * nv * ni * N + 4.0 * ni * N,
+                          launch_cgs(2, nv, V, vs, small + OFF_H2, SMALL, w, N, P->d_act, ni,
+                                     P->d_red, st));
+                ASP_HIP(P, launch_cgs_reduce(P->d_red, cb, 1, P->d_act, ni, small + OFF_NRM, SMALL, st));
+            } else {
+                for (int pass = 0; pass < 2; ++pass) {
+                    const int off = pass == 0 ? OFF_H1 : OFF_H2;
+                    for (int c0 = 0; c0 <= j; c0 += CH) {
+                        const int c1 = std::min(j + 1, c0 + CH);
+                        ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * (c1 - c0 + 1) * ni * N, 8.0 * (c1 - c0) * ni * N,
+                                  launch_multidot(V, vs, c0, c1, w, N, P->d_act, ni, P->d_red, st));
+                        ASP_HIP(P, launch_reduce(P->d_red, nblk, c1 - c0, P->d_act, ni, small + off + c0,
+                                                 SMALL, st));
+                    }
+                    for (int c0 = 0; c0 <= j; c0 += CH) {
+                        const int c1 = std::min(j + 1, c0 + CH);
+                        const bool last = (pass == 1) && (c1 == j + 1);
+                        ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * (c1 - c0 + 2) * ni * N, 8.0 * (c1 - c0) * ni * N,
+                                  launch_axpy_multi(V, vs, c0, c1, small + off, SMALL, w, N, P->d_act,
+                                                    ni, last ? P->d_red : nullptr, st));
+                    }
                 }
-                for (int c0 = 0; c0 <= j; c0 += CH) {
-                    const int c1 = std::min(j + 1, c0 + CH);
-                    const bool last = (pass == 1) && (c1 == j + 1);
-                    ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * (c1 - c0 + 2) * ni * N, 8.0 * (c1 - c0) * ni * N,
-                              launch_axpy_multi(V, vs, c0, c1, small + off, SMALL, w, N, P->d_act,
-                                                ni, last ? P->d_red : nullptr, st));
-                }
+                ASP_HIP(P, launch_reduce(P->d_red, nblk, 1, P->d_act, ni, small + OFF_NRM, SMALL, st));
             }
-            ASP_HIP(P, launch_reduce(P->d_red, nblk, 1, P->d_act, ni, small + OFF_NRM, SMALL, st));
             if ((s = download_small()) != ASP_OK) return s;
             std::vector<int> next;
             for (int r : inner) {

@@ -176,6 +176,96 @@ __global__ __launch_bounds__(BS) void axpy_multi_kernel(const zd* __restrict__ V
     }
 }
 
+// ----------------------------------------------------------------------------
+// Fused classical Gram-Schmidt passes over the basis v_0 .. v_{nv-1} (nv <=
+// CGS_MAXV), one right-hand side per grid row:
+//   CGS_DOT:     p_k = sum conj(v_k) w
+//   CGS_UPD_DOT: w -= sum_k c_k v_k, then p_k = sum conj(v_k) w   (one read of V)
+//   CGS_UPD_NRM: w -= sum_k c_k v_k, then |w|^2
+// Two passes of Gram-Schmidt then read the basis three times.  Each thread
+// walks its elements with a fixed stride; the per-block sums are reduced
+// through a fixed butterfly inside each wavefront and a fixed order across
+// the four wavefronts, so results do not depend on the other right-hand sides.
+// ----------------------------------------------------------------------------
+constexpr int CGS_DOT = 0, CGS_UPD_DOT = 1, CGS_UPD_NRM = 2;
+
+template <int NV, int MODE>
+__global__ __launch_bounds__(BS) void cgs_kernel(const zd* __restrict__ V, long long vstride,
+                                                const zd* __restrict__ coef, int coef_stride,
+                                                zd* __restrict__ w, long long N,
+                                                const int* __restrict__ act,
+                                                zd* __restrict__ partial) {
+    constexpr int NO = (MODE == CGS_UPD_NRM) ? 1 : NV;   // sums per block
+    __shared__ zd red[BS / 64][NO];
+    const int rhs = act ? act[blockIdx.y] : (int)blockIdx.y;
+    const int nblk = gridDim.x;
+    const zd* vr = V + (long long)rhs * N;
+    zd* wr = w + (long long)rhs * N;
+    zd cf[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        cf[k] = (MODE == CGS_DOT) ? mk(0.0, 0.0) : coef[(long long)rhs * coef_stride + k];
+    zd acc[NO];
+#pragma unroll
+    for (int k = 0; k < NO; ++k) acc[k] = mk(0.0, 0.0);
+    for (long long idx = (long long)blockIdx.x * BS + threadIdx.x; idx < N;
+         idx += (long long)nblk * BS) {
+        zd x = wr[idx];
+        zd vv[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vv[k] = vr[(long long)k * vstride + idx];
+        if (MODE != CGS_DOT) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) x = x - cf[k] * vv[k];
+            wr[idx] = x;
+        }
+        if (MODE == CGS_UPD_NRM) {
+            acc[0].x += abs2(x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) acc[k] = cfma_conj(vv[k], x, acc[k]);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            acc[k].x += __shfl_xor(acc[k].x, o);
+            acc[k].y += __shfl_xor(acc[k].y, o);
+        }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NO; ++k) red[wv][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < NO) {
+        zd t = red[0][threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < BS / 64; ++q) t = t + red[q][threadIdx.x];
+        partial[((long long)rhs * nblk + blockIdx.x) * CGS_MAXV + threadIdx.x] = t;
+    }
+}
+
+// out[rhs][k] = sum over blocks of partial[rhs][b][k], k < nv, in block order
+__global__ __launch_bounds__(64) void cgs_reduce_kernel(const zd* __restrict__ partial, int nblk,
+                                                      int nv, const int* __restrict__ act,
+                                                      zd* __restrict__ out, int out_stride) {
+    __shared__ zd sh[CGS_MAXV][65];
+    const int rhs = act ? act[blockIdx.x] : (int)blockIdx.x;
+    const int t = threadIdx.x;
+    for (int k = 0; k < nv; ++k) {
+        zd a = mk(0.0, 0.0);
+        for (int b = t; b < nblk; b += 64) a = a + partial[((long long)rhs * nblk + b) * CGS_MAXV + k];
+        sh[k][t] = a;
+    }
+    __syncthreads();
+    if (t < nv) {
+        zd a = sh[t][0];
+        for (int q = 1; q < 64; ++q) a = a + sh[t][q];
+        out[(long long)rhs * out_stride + t] = a;
+    }
+}
+
 __global__ void scale_vec_kernel(const zd* __restrict__ w, zd* __restrict__ v,
                                  const zd* __restrict__ scal, long long N,
                                  const int* __restrict__ act) {
@@ -275,6 +365,59 @@ hipError_t launch_axpy_multi(const zd* V, long long vstride, int i0, int i1, con
     const int nblk = krylov_blocks(N);
     hipLaunchKernelGGL(axpy_multi_kernel, dim3(nblk, nact), dim3(BS), 0, st, V, vstride, i0,
                        i1 - i0, coef, coef_stride, w, N, act, norm_partial);
+    return hipGetLastError();
+}
+
+int cgs_blocks(long long N) {
+    long long b = (N + BS * 16 - 1) / (BS * 16);
+    if (b < 1) b = 1;
+    if (b > 256) b = 256;
+    return (int)b;
+}
+
+template <int MODE>
+static hipError_t launch_cgs_mode(int nv, const zd* V, long long vstride, const zd* coef,
+                                  int coef_stride, zd* w, long long N, const int* act, int nact,
+                                  zd* partial, hipStream_t st) {
+    dim3 grid(cgs_blocks(N), nact);
+    switch (nv) {
+#define ASP_CGS_CASE(K)                                                                        \
+    case K:                                                                                    \
+        hipLaunchKernelGGL((cgs_kernel<K, MODE>), grid, dim3(BS), 0, st, V, vstride, coef,     \
+                           coef_stride, w, N, act, partial);                                   \
+        break;
+        ASP_CGS_CASE(1) ASP_CGS_CASE(2) ASP_CGS_CASE(3) ASP_CGS_CASE(4) ASP_CGS_CASE(5)
+        ASP_CGS_CASE(6) ASP_CGS_CASE(7) ASP_CGS_CASE(8) ASP_CGS_CASE(9) ASP_CGS_CASE(10)
+        ASP_CGS_CASE(11) ASP_CGS_CASE(12) ASP_CGS_CASE(13) ASP_CGS_CASE(14) ASP_CGS_CASE(15)
+        ASP_CGS_CASE(16) ASP_CGS_CASE(17) ASP_CGS_CASE(18) ASP_CGS_CASE(19) ASP_CGS_CASE(20)
+        ASP_CGS_CASE(21) ASP_CGS_CASE(22) ASP_CGS_CASE(23) ASP_CGS_CASE(24)
+#undef ASP_CGS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cgs(int mode, int nv, const zd* V, long long vstride, const zd* coef,
+                      int coef_stride, zd* w, long long N, const int* act, int nact, zd* partial,
+                      hipStream_t st) {
+    static_assert(CGS_MAXV == 24, "one kernel instance per basis size");
+    if (nv < 1 || nv > CGS_MAXV) return hipErrorInvalidValue;
+    if (mode == CGS_DOT)
+        return launch_cgs_mode<CGS_DOT>(nv, V, vstride, coef, coef_stride, w, N, act, nact,
+                                        partial, st);
+    if (mode == CGS_UPD_DOT)
+        return launch_cgs_mode<CGS_UPD_DOT>(nv, V, vstride, coef, coef_stride, w, N, act, nact,
+                                            partial, st);
+    return launch_cgs_mode<CGS_UPD_NRM>(nv, V, vstride, coef, coef_stride, w, N, act, nact,
+                                        partial, st);
+}
+
+hipError_t launch_cgs_reduce(const zd* partial, int nblk, int nv, const int* act, int nact,
+                             zd* out, int out_stride, hipStream_t st) {
+    if (nv < 1 || nv > CGS_MAXV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cgs_reduce_kernel, dim3(nact), dim3(64), 0, st, partial, nblk, nv, act,
+                       out, out_stride);
     return hipGetLastError();
 }
 
