@@ -13,6 +13,8 @@
 // form; the factor keeps S_k^-1 for every k.  A solve is the forward sweep
 // y_k = S_k^-1 (g_k - E_{k-1} y_{k-1}) and the backward sweep
 // v_k = y_k - S_k^-1 E_k v_{k+1}.
+#include <algorithm>
+
 #include "asp_internal.h"
 #include "mfma.h"
 
@@ -21,6 +23,23 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int MAXL = 32;
 static_assert(WAVE * 16 <= SINK_ELEMS, "sixteen discard entries per lane");
+
+// raw buffer stores: dword 3 of the resource (32-bit data format) and an
+// offset past any range, whose writes the hardware drops
+constexpr int BUF_DW3 = 0x00020000;
+constexpr unsigned BUF_OOB = 0x80000000u;
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, zd v) {
+    u32x4 d;
+    __builtin_memcpy(&d, &v, sizeof(d));
+    __builtin_amdgcn_raw_buffer_store_b128(d, r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, zf v) {
+    u32x2 d;
+    __builtin_memcpy(&d, &v, sizeof(d));
+    __builtin_amdgcn_raw_buffer_store_b64(d, r, off, 0, 0);
+}
 
 // ----------------------------------------------------------------------------
 // factorization: one wavefront per auxiliary problem.  Lane (j, h) holds rows
@@ -175,6 +194,7 @@ struct SolveArgs {
     void* y;
     long long y_per_wave;   // scratch entries per workgroup
     zd* sink;               // discard buffer: four entries per thread
+    int buf_ok;             // output byte offsets fit the 31-bit buffer range
     int n;
     long long N;
 };
@@ -423,9 +443,8 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
         if (rowv[e] && row[e] == jout) jsel = e;
-    cplx<T>* const Tp = (valid && jsel >= 0)
-                            ? reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off + (long long)slot * n
-                            : nullptr;
+    cplx<T>* const Tbase = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off;
+    cplx<T>* const Tp = (valid && jsel >= 0) ? Tbase + (long long)slot * n : nullptr;
     bool keep[4];
     zd* gout[4];
 #pragma unroll
@@ -433,18 +452,37 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         keep[e] = valid && inX[e];
         gout[e] = outp + (long long)rid * N + (long long)n * (lcl[e] - 1);
     }
+    // With a.buf_ok the outputs go through a buffer resource: a lane that keeps
+    // nothing gives an offset past the range and the hardware drops the write
+    // (no memory traffic, no branch).  Otherwise such writes go to the discard
+    // buffer.
+    const bool bufo = a.buf_ok != 0;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        grid_out ? static_cast<void*>(outp) : static_cast<void*>(Tbase), 0, 0x7fffffff, BUF_DW3);
+    unsigned boff[4];   // byte offsets at step 1
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        boff[e] = grid_out ? (keep[e] ? (unsigned)(((long long)rid * N + (long long)n * (lcl[e] - 1)) * 16)
+                                      : BUF_OOB)
+                           : (Tp ? (unsigned)((long long)slot * n * sizeof(cplx<T>)) : BUF_OOB);
     auto emit = [&](int k, const cplx<T> (&v)[4], const zd (&av)[4]) {
         if (!grid_out) {
             cplx<T> x = v[0];
 #pragma unroll
             for (int e = 1; e < 4; ++e) x = csel(jsel == e, v[e], x);
-            *(Tp ? Tp + (k - 1) : sinkT) = x;
+            if (bufo)
+                buf_store(rs, boff[0] + (unsigned)(k - 1) * (unsigned)sizeof(cplx<T>), x);
+            else
+                *(Tp ? Tp + (k - 1) : sinkT) = x;
             return;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const zd x = use_add ? ccast<double>(v[e]) + av[e] : ccast<double>(v[e]);
-            *(keep[e] ? gout[e] + (k - 1) : sink + e) = x;
+            if (bufo)
+                buf_store(rs, boff[e] + (unsigned)(k - 1) * 16u, x);
+            else
+                *(keep[e] ? gout[e] + (k - 1) : sink + e) = x;
         }
     };
     // E_k v_{k+1} for this lane's entries into tb[k & 1] (shk: s at line k + 1/2)
@@ -677,6 +715,13 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     a.y = P->d_y;
     a.y_per_wave = solve_scratch_per_block(P);
     a.sink = P->d_sink;
+    {
+        const size_t esz = P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd);
+        const long long lim = 1LL << 31;
+        const long long grid_bytes = (long long)std::max(P->ws_rhs, L.nact) * P->N * (long long)sizeof(zd);
+        const long long line_bytes = (long long)P->n * P->n * (long long)esz;
+        a.buf_ok = (grid_bytes < lim && line_bytes < lim) ? 1 : 0;
+    }
     a.n = P->n;
     a.N = P->N;
     const int LR = L.rl ? P->LR_RL : P->LR_M;   // every job of one launch shares its row count
