@@ -42,50 +42,54 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
 }
 
 // ----------------------------------------------------------------------------
-// factorization: one wavefront per auxiliary problem.  Lane (j, h) holds rows
-// 16h .. 16h+15 of column j of the current block in registers; S_k is formed
-// from S_{k-1}^-1 in place and inverted by Gauss-Jordan elimination without
-// pivoting (at a few points per wavelength the blocks are close to diagonally
-// dominant; a zero or non-finite pivot is reported as a breakdown).  The pivot
-// row and column pass through LDS, double-buffered: one wave barrier per
-// pivot.  Arithmetic in double; the stored factor is rounded to TS.
+// factorization: one 256-thread workgroup per auxiliary problem.  With LR
+// columns, thread (j, g) holds rows g RPL .. g RPL + RPL - 1 of column j of the
+// current block in registers (LR = 32: 8 row groups of 4; LR = 16: 16 of 1);
+// S_k is formed from S_{k-1}^-1 in place and inverted by Gauss-Jordan
+// elimination without pivoting (at a few points per wavelength the blocks are
+// close to diagonally dominant; a zero or non-finite pivot is reported as a
+// breakdown).  The pivot row and column pass through LDS, double-buffered by
+// pivot parity: one barrier per pivot.  Arithmetic in double; the stored
+// factor is rounded to TS.
 // ----------------------------------------------------------------------------
-template <typename TS>
-__global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restrict__ desc,
-                                                      AxisTables ax,
-                                                      const zd* __restrict__ subtab,
-                                                      const double* __restrict__ ksq, int n,
-                                                      cplx<TS>* __restrict__ fac,
-                                                      int* __restrict__ flag,
-                                                      cplx<TS>* __restrict__ sink) {
-    __shared__ zd rowbuf[2][MAXL];
-    __shared__ zd colbuf[2][MAXL];
+constexpr int FB = 256;   // threads per factor workgroup
 
-    const SubDesc d = desc[blockIdx.x];
+template <typename TS, int LR>
+__device__ __forceinline__ void factor2d_body(const SubDesc& d, AxisTables ax,
+                                              const zd* __restrict__ subtab,
+                                              const double* __restrict__ ksq, int n,
+                                              cplx<TS>* __restrict__ fac, int* __restrict__ flag,
+                                              zd (&rowbuf)[2][MAXL], zd (&colbuf)[2][MAXL],
+                                              zd (&srow)[MAXL]) {
+    constexpr int G = FB / LR, RPL = LR / G;
     const int L = d.L;
-    const int lane = threadIdx.x;
-    const int j = lane & 31, h = lane >> 5;
+    const int t = threadIdx.x;
+    const int j = t % LR, g = t / LR;
     const bool cj = j < L;
     const zd* tab = subtab + d.tab_off;
     const zd* ssh = tab;                // s at half lines lo-1/2 .. hi+1/2
     const zd* sinv2 = tab + L + 1;      // 1/(s h^2) on lines lo..hi
     const zd* sinv = tab + 2 * L + 1;   // 1/s on lines lo..hi
-    const int LR = d.LR;
     const int jc = min(j, L - 1);
     // tables that do not change along axis 1: 1/(s h^2) per row (LDS, zero
-    // past L) and, for this lane's column j, the couplings to rows j -+ 1
-    __shared__ zd srow[MAXL];
-    if (h == 0) srow[j] = csel(cj, sinv2[jc], mk(0.0, 0.0));
+    // past L) and, for this thread's column j, the couplings to rows j -+ 1
+    if (g == 0) srow[j] = csel(cj, sinv2[jc], mk(0.0, 0.0));
     const zd sj = csel(cj, sinv2[jc], mk(0.0, 0.0));
     const zd c_lo = ssh[jc], c_hi = ssh[jc + 1], sinvj = sinv[jc];
     const double* ksq_j = ksq + (long long)n * (d.lo + jc - 1);
+    // S_k^-1 column-major with leading dimension LR through a buffer resource:
+    // columns past L give an offset past the range (dropped writes)
+    const __amdgpu_buffer_rsrc_t rf =
+        __builtin_amdgcn_make_buffer_rsrc(fac + d.fac_off, 0, 0x7fffffff, BUF_DW3);
+    const unsigned foff = cj ? (unsigned)((j * LR + g * RPL) * sizeof(cplx<TS>)) : BUF_OOB;
+    const unsigned fstep = (unsigned)(L * LR * sizeof(cplx<TS>));
     bool bad = false;
-    zd v[16];
+    zd v[RPL];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = mk(0.0, 0.0);
+    for (int q = 0; q < RPL; ++q) v[q] = mk(0.0, 0.0);
 
     // the tables of block k (couplings s1 at k -+ 1/2, 1/(s1 h^2), 1/s1 and
-    // omega^2/c^2 on this lane's diagonal point), fetched one block ahead
+    // omega^2/c^2 on this thread's diagonal point), fetched one block ahead
     struct Step {
         zd sh_m, sh_p, is2, is;
         double kq;
@@ -102,6 +106,7 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
     // nothing outstanding on entry: the waits in the loop count its own operations
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    int pc = 0;   // pivots so far: their parity picks the LDS buffer
     for (int k = 1; k <= n; ++k) {
         fetch(nxt, min(k + 1, n));
         // S_k = D_k - E_{k-1} S_{k-1}^-1 E_{k-1} over S_{k-1}^-1; identity padding
@@ -111,8 +116,8 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
         const zd off_lo = c_lo * cur.is2;   // row j - 1
         const zd off_hi = c_hi * cur.is2;   // row j + 1
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = 16 * h + q;
+        for (int q = 0; q < RPL; ++q) {
+            const int i = g * RPL + q;
             zd val = csel(k > 1, -((cur.sh_m * srow[i]) * v[q] * ej), mk(0.0, 0.0));
             const zd add = csel(i == j, diag,
                                 csel(i == j - 1, off_lo, csel(i == j + 1, off_hi, mk(0.0, 0.0))));
@@ -120,48 +125,64 @@ __global__ __launch_bounds__(WAVE) void factor2d_kernel(const SubDesc* __restric
             const bool inside = i < L && cj;
             v[q] = csel(inside, val, mk(i == j ? 1.0 : 0.0, 0.0));
         }
-        // in-place inverse; the pivots run in groups of 16 with the pivot's
+        // in-place inverse; the pivots run in groups of RPL with the pivot's
         // register index fixed at compile time
-        for (int kb = 0; kb < L; kb += 16) {
-            const int hb = kb >> 4;
+        for (int kb = 0; kb < L; kb += RPL) {
+            const int gb = kb / RPL;
 #pragma unroll
-            for (int pq = 0; pq < 16; ++pq) {
+            for (int pq = 0; pq < RPL; ++pq) {
                 const int kk = kb + pq;
                 if (kk >= L) continue;
-                const int b = pq & 1;
-                if (h == hb) rowbuf[b][j] = v[pq];
+                const int b = pc & 1;
+                ++pc;
+                if (g == gb) rowbuf[b][j] = v[pq];
                 if (j == kk)
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) colbuf[b][16 * h + q] = v[q];
+                    for (int q = 0; q < RPL; ++q) colbuf[b][g * RPL + q] = v[q];
                 __syncthreads();
                 const zd p = colbuf[b][kk];
                 const double pa = abs2(p);
                 if (!(pa > 1e-300) || !isfinite(pa)) bad = true;
                 const zd pinv = cinv(p);
                 const zd rp = rowbuf[b][j] * pinv;            // A[kk][j] / p
-                const bool jp = j == kk, hp = h == hb;
+                const bool jp = j == kk, gp = g == gb;
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const zd ci = colbuf[b][16 * h + q];       // A[i][kk]
+                for (int q = 0; q < RPL; ++q) {
+                    const zd ci = colbuf[b][g * RPL + q];     // A[i][kk]
                     zd x = v[q] - ci * rp;
-                    if (q == pq) x = csel(hp, rp, x);
-                    const zd xc = csel(q == pq && hp, pinv, -(ci * pinv));
+                    if (q == pq) x = csel(gp, rp, x);
+                    const zd xc = csel(q == pq && gp, pinv, -(ci * pinv));
                     v[q] = csel(jp, xc, x);
                 }
             }
         }
-        // store S_k^-1 column-major with leading dimension LR (rows past L zero);
-        // lanes outside the block write to the discard buffer
-        cplx<TS>* out = fac + d.fac_off + (long long)(k - 1) * L * LR + (long long)j * LR;
+        // store S_k^-1 (rows past L zero)
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = 16 * h + q;
-            const bool keep = cj && i < LR;
-            *(keep ? out + i : sink + lane * 16 + q) = ccast<TS>(csel(i < L, v[q], mk(0.0, 0.0)));
+        for (int q = 0; q < RPL; ++q) {
+            const int i = g * RPL + q;
+            buf_store(rf, foff + (unsigned)(k - 1) * fstep + (unsigned)(q * sizeof(cplx<TS>)),
+                      ccast<TS>(csel(i < L, v[q], mk(0.0, 0.0))));
         }
         cur = nxt;
     }
     if (bad) *flag = 1;
+}
+
+template <typename TS>
+__global__ __launch_bounds__(FB) void factor2d_kernel(const SubDesc* __restrict__ desc,
+                                                     AxisTables ax,
+                                                     const zd* __restrict__ subtab,
+                                                     const double* __restrict__ ksq, int n,
+                                                     cplx<TS>* __restrict__ fac,
+                                                     int* __restrict__ flag) {
+    __shared__ zd rowbuf[2][MAXL];
+    __shared__ zd colbuf[2][MAXL];
+    __shared__ zd srow[MAXL];
+    const SubDesc d = desc[blockIdx.x];
+    if (d.LR == 16)
+        factor2d_body<TS, 16>(d, ax, subtab, ksq, n, fac, flag, rowbuf, colbuf, srow);
+    else
+        factor2d_body<TS, 32>(d, ax, subtab, ksq, n, fac, flag, rowbuf, colbuf, srow);
 }
 
 // ----------------------------------------------------------------------------
@@ -667,13 +688,13 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
     const int nsub = (int)P->subs.size();
     AxisTables ax{P->d_axis, P->d_axis + (P->n + 1), P->d_axis + (2 * P->n + 1)};
     if (P->prec != ASP_PREC_FP64)
-        hipLaunchKernelGGL(factor2d_kernel<float>, dim3(nsub), dim3(WAVE), 0, st, P->d_desc, ax,
+        hipLaunchKernelGGL(factor2d_kernel<float>, dim3(nsub), dim3(FB), 0, st, P->d_desc, ax,
                            P->d_subtab, P->d_ksq, P->n, reinterpret_cast<zf*>(P->d_fac),
-                           P->d_flag, reinterpret_cast<zf*>(P->d_sink));
+                           P->d_flag);
     else
-        hipLaunchKernelGGL(factor2d_kernel<double>, dim3(nsub), dim3(WAVE), 0, st, P->d_desc,
+        hipLaunchKernelGGL(factor2d_kernel<double>, dim3(nsub), dim3(FB), 0, st, P->d_desc,
                            ax, P->d_subtab, P->d_ksq, P->n, reinterpret_cast<zd*>(P->d_fac),
-                           P->d_flag, P->d_sink);
+                           P->d_flag);
     return hipGetLastError();
 }
 
