@@ -222,8 +222,9 @@ struct SolveArgs {
 
 constexpr int SB = 256;        // threads per solve workgroup: four wavefronts, one tile each
 
-template <typename T, int LR>
+template <typename T, int LR, int INM>
 __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
+    static_assert(INM == IN_GRID || INM == IN_BOUNDARY || INM == IN_UNIT, "input mode");
     constexpr int SRB = 1024 / LR;          // right-hand sides per workgroup
     constexpr int NCT = SRB / 16;           // right-hand-side tiles
     static_assert((LR / 16) * NCT == 4, "four 16 x 16 tiles, one per wavefront");
@@ -310,11 +311,11 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const long long bbase = ((long long)d.wrow * a.w_rhs + rid) * n;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const bool used = (a.in_mode == IN_GRID) ? inX[v]
-                          : (a.in_mode == IN_BOUNDARY) ? (rowv[v] && row[v] == grow)
+        const bool used = (INM == IN_GRID) ? inX[v]
+                          : (INM == IN_BOUNDARY) ? (rowv[v] && row[v] == grow)
                                                        : false;
         inp[v] = !used                      ? a.subtab
-                 : (a.in_mode == IN_GRID) ? a.r + (long long)rid * N + (long long)n * (lcl[v] - 1)
+                 : (INM == IN_GRID) ? a.r + (long long)rid * N + (long long)n * (lcl[v] - 1)
                                           : a.W + bbase;
         ink[v] = used ? 1 : 0;
     }
@@ -331,9 +332,9 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     bool wu[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        wg[v] = (a.in_mode == IN_GRID && inX[v]) ? 1.0 : 0.0;
-        wb[v] = (a.in_mode == IN_BOUNDARY && rowv[v] && row[v] == grow) ? 1.0 : 0.0;
-        wu[v] = a.in_mode == IN_UNIT && rowv[v] && row[v] == grow;
+        wg[v] = (INM == IN_GRID && inX[v]) ? 1.0 : 0.0;
+        wb[v] = (INM == IN_BOUNDARY && rowv[v] && row[v] == grow) ? 1.0 : 0.0;
+        wu[v] = INM == IN_UNIT && rowv[v] && row[v] == grow;
     }
     auto put_input = [&](int k, const zd (&g)[4], const cplx<T> (&y)[4], zd shm, zd ism) {
         const zd cin = -(coupl * ism);
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // unit data enters at i1 = slot + 1 >= ch SRB + 1: the forward results of
     // the blocks before the chunk's first column are zero, so the forward pass
     // starts there and the backward pass reads no results before it
-    const int kstart = (a.in_mode == IN_UNIT) ? min(ch * SRB + 1, n) : 1;
+    const int kstart = (INM == IN_UNIT) ? min(ch * SRB + 1, n) : 1;
     // The loads of a step are issued two steps ahead into one of two register
     // slots; the step loops run in pairs so that the slots stay in fixed
     // registers (a register copy would wait for its load).
@@ -698,13 +699,24 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int LR>
+// one kernel per (precision, row count, input mode): the M-solves, the R/L
+// solves and the transfer-map solves are separate kernels
+template <int LR, int INM>
 static hipError_t launch_solve_lr(const asp_plan* P, const SolveArgs& a, int blocks, hipStream_t st) {
     if (P->prec != ASP_PREC_FP64)
-        hipLaunchKernelGGL((solve2d_kernel<float, LR>), dim3(blocks), dim3(SB), 0, st, a);
+        hipLaunchKernelGGL((solve2d_kernel<float, LR, INM>), dim3(blocks), dim3(SB), 0, st, a);
     else
-        hipLaunchKernelGGL((solve2d_kernel<double, LR>), dim3(blocks), dim3(SB), 0, st, a);
+        hipLaunchKernelGGL((solve2d_kernel<double, LR, INM>), dim3(blocks), dim3(SB), 0, st, a);
     return hipGetLastError();
+}
+
+template <int LR>
+static hipError_t launch_solve_mode(const asp_plan* P, const SolveArgs& a, int blocks,
+                                    hipStream_t st) {
+    if (a.in_mode == IN_GRID) return launch_solve_lr<LR, IN_GRID>(P, a, blocks, st);
+    if (a.in_mode == IN_BOUNDARY) return launch_solve_lr<LR, IN_BOUNDARY>(P, a, blocks, st);
+    if (a.in_mode == IN_UNIT) return launch_solve_lr<LR, IN_UNIT>(P, a, blocks, st);
+    return hipErrorInvalidValue;
 }
 
 int solve_rhs_per_block(int LR) { return 1024 / LR; }
@@ -750,8 +762,8 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     const long long B = (long long)L.njobs * ((L.nact + srb - 1) / srb);
     if (B > P->y_waves) return hipErrorInvalidValue;   // scratch too small
     const int blocks = (int)(((B + 7) / 8) * 8);
-    if (LR == 16) return launch_solve_lr<16>(P, a, blocks, st);
-    return launch_solve_lr<32>(P, a, blocks, st);
+    if (LR == 16) return launch_solve_mode<16>(P, a, blocks, st);
+    return launch_solve_mode<32>(P, a, blocks, st);
 }
 
 static int sweep_slots(int nact) { return (nact + SW_RT - 1) / SW_RT * SW_RT; }
