@@ -35,6 +35,12 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
     __builtin_memcpy(&d, &v, sizeof(d));
     __builtin_amdgcn_raw_buffer_store_b128(d, r, off, 0, 0);
 }
+__device__ __forceinline__ zd buf_load_zd(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    zd v;
+    __builtin_memcpy(&v, &d, sizeof(v));
+    return v;
+}
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, zf v) {
     u32x2 d;
     __builtin_memcpy(&d, &v, sizeof(d));
@@ -234,6 +240,10 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     constexpr int TBS = SRB + 1;            // padded row stride of the step vectors
     __shared__ cplx<T> Fs[2][FMAX];
     __shared__ cplx<T> tb[2][LR][TBS];      // step vectors [row][rhs]
+    // grid outputs of the first SROW lines of X for KO steps, by group parity
+    constexpr int KO = sizeof(T) == 4 ? 8 : 4;
+    constexpr int SROW = 4;
+    __shared__ cplx<T> stg[INM == IN_UNIT ? 1 : 2 * KO * SROW * SRB];
 
     // XCD-aware order: the chunks of one problem are consecutive work items
     const int nchunk = (a.nact + SRB - 1) / SRB;
@@ -437,13 +447,26 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const bool add_out = !set_u && omode == OUT_GRID_ACC;
     const bool grid_out = omode != OUT_LINE;
     const bool use_add = set_u || add_out;
-    // values the outputs add to, on the rows this lane writes (others: a fixed
-    // table entry, stride 0)
+    // Grid outputs on the first SROW lines of X are staged in LDS and written
+    // KO steps at a time (whole 128-byte lines per right-hand side and line);
+    // the other lines of X (the first and last layers are wider) are written
+    // at every step.
+    const bool bufo = a.buf_ok != 0;
+    const bool staging = INM != IN_UNIT && grid_out && bufo;
+    int xr[4];
+    bool stgd[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        xr[v] = d.lo + row[v] - d.xs;
+        stgd[v] = staging && inX[v] && xr[v] < SROW;
+    }
+    // values the outputs add to, on the rows this lane writes at every step
+    // (others: a fixed table entry, stride 0)
     const zd* addp[4];
     int addk[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const bool used = use_add && grid_out && valid && inX[v];
+        const bool used = use_add && grid_out && valid && inX[v] && !stgd[v];
         addp[v] = used ? (set_u ? a.Ugrid : outp) + (long long)rid * N + (long long)n * (lcl[v] - 1)
                        : a.subtab;
         addk[v] = used ? 1 : 0;
@@ -478,14 +501,14 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // nothing gives an offset past the range and the hardware drops the write
     // (no memory traffic, no branch).  Otherwise such writes go to the discard
     // buffer.
-    const bool bufo = a.buf_ok != 0;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         grid_out ? static_cast<void*>(outp) : static_cast<void*>(Tbase), 0, 0x7fffffff, BUF_DW3);
     unsigned boff[4];   // byte offsets at step 1
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-        boff[e] = grid_out ? (keep[e] ? (unsigned)(((long long)rid * N + (long long)n * (lcl[e] - 1)) * 16)
-                                      : BUF_OOB)
+        boff[e] = grid_out ? ((keep[e] && !stgd[e])
+                                  ? (unsigned)(((long long)rid * N + (long long)n * (lcl[e] - 1)) * 16)
+                                  : BUF_OOB)
                            : (Tp ? (unsigned)((long long)slot * n * sizeof(cplx<T>)) : BUF_OOB);
     auto emit = [&](int k, const cplx<T> (&v)[4], const zd (&av)[4]) {
         if (!grid_out) {
@@ -498,6 +521,14 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
                 *(Tp ? Tp + (k - 1) : sinkT) = x;
             return;
         }
+        if constexpr (INM != IN_UNIT) {
+            if (staging) {
+                cplx<T>* sg = stg + ((((k - 1) / KO) & 1) * KO + (k - 1) % KO) * SROW * SRB;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (stgd[e]) sg[xr[e] * SRB + rloc] = v[e];
+            }
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const zd x = use_add ? ccast<double>(v[e]) + av[e] : ccast<double>(v[e]);
@@ -505,6 +536,37 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
                 buf_store(rs, boff[e] + (unsigned)(k - 1) * 16u, x);
             else
                 *(keep[e] ? gout[e] + (k - 1) : sink + e) = x;
+        }
+    };
+    // write out the staged steps g KO + 1 .. g KO + KO: thread (line, rhs) of
+    // the staged block writes KO consecutive entries (the values its outputs
+    // add to read the same way); lanes past the block pass offsets past the
+    // range
+    const int fx = min(tid / SRB, SROW - 1), frl = tid % SRB;
+    const int fslot = ch * SRB + frl;
+    const int nxs = min(d.xe - d.xs + 1, SROW);
+    const bool fvalid = staging && tid < SROW * SRB && tid / SRB < nxs && fslot < a.nact;
+    const int frid = fvalid ? (a.act ? a.act[fslot] : fslot) : 0;
+    const unsigned fbase =
+        fvalid ? (unsigned)(((long long)frid * N + (long long)n * (d.xs + fx - 1)) * 16) : BUF_OOB;
+    const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc(
+        static_cast<void*>(set_u ? const_cast<zd*>(a.Ugrid) : outp), 0, 0x7fffffff, BUF_DW3);
+    auto flush = [&](int g) {
+        if constexpr (INM != IN_UNIT) {
+            const cplx<T>* sg = stg + (g & 1) * KO * SROW * SRB + fx * SRB + frl;
+            zd av[KO];
+#pragma unroll
+            for (int q = 0; q < KO; ++q) {
+                const int st = g * KO + 1 + q;
+                const unsigned off = (st <= n) ? fbase + (unsigned)(st - 1) * 16u : BUF_OOB;
+                av[q] = use_add ? buf_load_zd(rsa, off) : mk(0.0, 0.0);
+            }
+#pragma unroll
+            for (int q = 0; q < KO; ++q) {
+                const int st = g * KO + 1 + q;
+                const unsigned off = (st <= n) ? fbase + (unsigned)(st - 1) * 16u : BUF_OOB;
+                buf_store(rs, off, ccast<double>(sg[q * SROW * SRB]) + av[q]);
+            }
         }
     };
     // E_k v_{k+1} for this lane's entries into tb[k & 1] (shk: s at line k + 1/2)
@@ -540,6 +602,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     auto bwd_step = [&](int k, BwdSlot& S, auto pre) {
         const int buf = k & 1;
         __syncthreads();
+        if (staging && k % KO == 0) flush(k / KO);   // steps k+1 .. k+KO are staged
         const CTile<T> acc = product(buf, buf);
 #pragma unroll
         for (int e = 0; e < 4; ++e) vk[e] = S.y[e] - mk<T>(acc.re[e], acc.im[e]);
@@ -555,6 +618,10 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         bwd_step(kb - 1, bsl[1], std::true_type{});
     }
     if (kb >= 1) bwd_step(kb, bsl[0], std::false_type{});
+    if (staging) {
+        __syncthreads();
+        flush(0);
+    }
 }
 
 // ----------------------------------------------------------------------------
