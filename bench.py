@@ -66,6 +66,9 @@ def parse():
                     help="requests of the seeded serving stream timed after the batch runs (0: none)")
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="auxiliary problems of each kind the oracle factors and solves")
+    ap.add_argument("--paper-tables", default="",
+                    help="comma-separated grid sizes of the paper's 2D experiments to run "
+                         "(e.g. 127,255,511,1023,2047); '' for none")
     return ap.parse_args()
 
 
@@ -284,6 +287,50 @@ def serving_run(count, prec_name):
     return summ
 
 
+def paper_tables(prec_name, sizes):
+    """The paper's 2D experiments (Tables 1-3 of Section 3.2) on this path: per
+    field and grid, the factorization time, the GMRES(40) iterations to 1e-3 for
+    force (a) point source and (b) wave packet (solved as one batch of two
+    right-hand sides) and the solve time, beside the printed iteration counts."""
+    import json as _json
+
+    import torch
+
+    import workloads
+    from paper_1504_04058_amd import asp
+
+    with open(os.path.join(ROOT, "tests", "golden", "paper_iterations.json")) as fh:
+        printed = _json.load(fh)
+    prec = {"fp32": asp.ASP_PREC_FP32, "fp64": asp.ASP_PREC_FP64}[prec_name]
+    rows = []
+    for n in sizes:
+        col = printed["n"].index(n) if n in printed["n"] else None
+        for field in workloads.PAPER_FIELDS:
+            w = workloads.paper_workload(field, n)
+            f = torch.from_numpy(w["f"]).cuda()
+            u = torch.empty_like(f)
+            with asp.Plan(2, w["c"], w["omega"], n, w["b"], w["gamma"], C=w["C"], prec=prec) as plan:
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                plan.factor()
+                torch.cuda.synchronize()
+                b = time.perf_counter()
+                st, iters, relres = asp.asp_gmres(plan.handle, f, u, 2, w["tol"], w["restart"], 200)
+                torch.cuda.synchronize()
+                c = time.perf_counter()
+            rows.append({"n": n, "omega_over_2pi": (n + 1) / 8, "field": field,
+                         "setup_ms": (b - a) * 1e3, "solve_ms": (c - b) * 1e3,
+                         "iters": [int(i) for i in iters], "max_relres": float(max(relres)),
+                         "status": asp.STATUS_NAMES.get(st, st),
+                         "paper_iters": None if col is None else
+                         [printed[field]["force_a"][col], printed[field]["force_b"][col]]})
+            del f, u
+            torch.cuda.empty_cache()
+    return {"settings": "gamma 9, b 8, C 25, 8 points per wavelength, GMRES(40) to 1e-3, "
+                        "forces (a) point source at (1/2, 1/8), (b) wave packet at (1/8, 1/8)",
+            "layer_precision": prec_name, "rows": rows}
+
+
 def workloads_dim(name):
     import workloads
 
@@ -346,6 +393,8 @@ def main():
             }
     if args.serve_requests > 0:
         out["serving"] = serving_run(args.serve_requests, args.prec)
+    if args.paper_tables:
+        out["paper_tables"] = paper_tables(args.prec, [int(x) for x in args.paper_tables.split(",")])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["w"], float(iters.mean()), args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -79,6 +79,24 @@ def test_iterations_within_printed_band():
         assert 1 <= it <= largest, (n, it)
 
 
+@pytest.mark.parametrize("field", list(workloads.PAPER_FIELDS))
+def test_paper_workloads_within_printed_band(field):
+    """The paper-settings problems of every field (lens, waveguide, random) and
+    both forces (point source, wave packet) at n = 127 stay within the largest
+    count printed in Tables 1-3."""
+    table = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))
+    largest = max(max(v) for fam in ("lens", "waveguide", "random") for v in table[fam].values())
+    w = workloads.paper_workload(field, 127)
+    P = Problem.from_workload(w)
+    A = P.A()
+    M = Preconditioner(P)
+    for k in range(2):
+        b = w["f"][k] / P.scale()
+        x, it, rr, _ = gmres(lambda v: A @ v, M.apply, b, w["tol"], w["restart"], 100)
+        assert rr <= w["tol"]
+        assert 1 <= it <= largest, (field, k, it)
+
+
 def test_one_dimension_is_nearly_exact():
     """In 1D the auxiliary PMLs absorb the transmitted wave almost perfectly, so
     the additive splitting is close to exact."""

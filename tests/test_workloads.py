@@ -28,3 +28,24 @@ def test_field_ranges_and_source_peak():
     # column-major flattening: first index fastest
     a = np.arange(6).reshape(2, 3)
     assert list(workloads.flat(a)) == [0, 3, 1, 4, 2, 5]
+
+
+def test_paper_recipes():
+    """The stand-ins for the paper's figure-only fields and forces: the
+    waveguide is slowest on x1 = 1/2 and constant along x2; the packet peaks
+    at its centre with unit modulus and its phase advances along (1, 1)."""
+    import math
+
+    n = 63
+    c = workloads.velocity_waveguide2d(n)
+    h = 1.0 / (n + 1)
+    assert np.allclose(c, c[:, :1])                       # no x2 dependence
+    assert abs(c[31, 0] - (4 / 3) * (1 - 0.5)) < 1e-12    # x1 = 32 h = 1/2
+    w = workloads.paper_workload("lens", n)
+    assert w["omega"] == 2 * math.pi * 8 and w["gamma"] == 9 and w["b"] == 8
+    assert w["restart"] == 40 and w["tol"] == 1e-3 and w["f"].shape == (2, n * n)
+    fb = w["f"][1].reshape(n, n, order="F")
+    i0 = round(0.125 / h) - 1                              # grid point at 1/8
+    assert abs(abs(fb[i0, i0]) - 1.0) < 1e-12
+    ph = np.angle(fb[i0 + 1, i0 + 1] / fb[i0, i0])
+    assert abs(ph - w["omega"] * 2 * h / math.sqrt(2)) < 1e-9

@@ -16,7 +16,12 @@ from .fields import (  # noqa: F401
     velocity_lens2d,
     velocity_lens3d,
     velocity_random,
+    velocity_waveguide2d,
     gaussian_source,
+    wave_packet,
+    paper_workload,
+    PAPER_FIELDS,
+    PAPER_SIZES,
     seeded_centres,
     workload,
     WORKLOADS,

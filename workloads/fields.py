@@ -11,8 +11,13 @@ waveguide, a random field) only as figures and gives no formulas for them
               Gaussian-smoothed with standard deviation ``width`` grid cells
               (reflecting boundary, truncated at 4 standard deviations), then
               mapped affinely so that min -> 0.8 and max -> 1.2
+* waveguide (2D): c = (4/3) (1 - 0.5 exp(-32 (x1 - 1/2)^2)), a slow channel
+              along x2 (the vertical axis of the paper's figures)
 * source:     f = exp(-(4 omega / pi)^2 |x - x0|^2), a Gaussian point source
               whose width shrinks with the wavelength.
+* packet:     f = exp(-|x - x0|^2 / (2 lambda^2)) exp(i omega d.(x - x0)) with
+              lambda = 2 pi / omega (one wavelength), a Gaussian wave packet
+              travelling along the unit vector d.
 
 Nothing here knows about PML, layers or solvers.
 """
@@ -61,6 +66,19 @@ def velocity_random(n, d, seed, width=8.0, lo=0.8, hi=1.2):
     return lo + (hi - lo) * (z - zmin) / (zmax - zmin)
 
 
+def velocity_waveguide2d(n):
+    x1, _ = grid_coords(n, 2)
+    return (4.0 / 3.0) * (1.0 - 0.5 * np.exp(-32.0 * (x1 - 0.5) ** 2))
+
+
+def wave_packet(n, d, omega, centre, direction):
+    xs = grid_coords(n, d)
+    lam = 2.0 * math.pi / omega
+    r2 = sum((x - c0) ** 2 for x, c0 in zip(xs, centre))
+    phase = sum(dk * (x - c0) for x, c0, dk in zip(xs, centre, direction))
+    return np.exp(-r2 / (2.0 * lam * lam)) * np.exp(1j * omega * phase)
+
+
 def gaussian_source(n, d, omega, centre):
     xs = grid_coords(n, d)
     r2 = sum((x - c0) ** 2 for x, c0 in zip(xs, centre))
@@ -101,6 +119,37 @@ def _velocity(spec):
     if kind == "random":
         return velocity_random(n, d, spec.get("velocity_seed", 3))
     raise ValueError(f"unknown velocity family {kind!r}")
+
+
+# The settings of the paper's 2D experiments (Section 3.2): PML width
+# gamma = 9, layers of b = 8 lines, 8 points per wavelength (omega / 2 pi =
+# (n + 1) / 8), GMRES(40) to a relative residual of 1e-3.  Two right-hand sides
+# per problem: force (a), a Gaussian point source at (1/2, 1/8), and force (b),
+# a wave packet at (1/8, 1/8) travelling along (1, 1) / sqrt 2.
+PAPER_2D = dict(d=2, gamma=9, C=25.0, b=8, restart=40, tol=1e-3)
+PAPER_FIELDS = ("lens", "waveguide", "random")
+PAPER_SIZES = (127, 255, 511, 1023, 2047)
+
+
+def paper_workload(field, n):
+    """A problem of the paper's 2D experiments (Tables 1-3) with the field
+    ``field`` in PAPER_FIELDS on an n x n grid; same keys as ``workload``."""
+    spec = dict(PAPER_2D, n=n, nrhs=2, omega=2 * math.pi * (n + 1) / 8, velocity=field)
+    if field == "lens":
+        c = velocity_lens2d(n)
+    elif field == "waveguide":
+        c = velocity_waveguide2d(n)
+    elif field == "random":
+        c = velocity_random(n, 2, 3)
+    else:
+        raise ValueError(f"unknown paper field {field!r}")
+    w = spec["omega"]
+    fa = gaussian_source(n, 2, w, (0.5, 0.125))
+    s2 = 1.0 / math.sqrt(2.0)
+    fb = wave_packet(n, 2, w, (0.125, 0.125), (s2, s2))
+    f = np.stack([flat(fa).astype(np.complex128), flat(fb).astype(np.complex128)])
+    spec.update(c=c, f=f, name=f"paper2d_{field}_n{n}")
+    return spec
 
 
 def workload(name, n=None, nrhs=None):
