@@ -218,8 +218,8 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
         t.end();
     }
     // u~_p = u~_{p,1:p-1} + u~_{p,p} + u~_{p,p+1:m}: one launch of every R_p
-    // (z = U + a on X_p, p > 1) and L_p (c into the staging grid), then
-    // z = U + c on X_1 and z += c on X_p, 1 < p < m
+    // (z = a on X_p, p > 1) and L_p (c into the staging grid), then
+    // z = U + c on X_1, z += U + c on X_p (1 < p < m) and z += U on X_m
     {
         SolveLaunch L;
         L.job0 = P->idx_R(2);
@@ -228,7 +228,7 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
         L.act = act;
         L.nact = nact;
         L.in_mode = IN_BOUNDARY;
-        L.out_mode = OUT_GRID_ADD_U;
+        L.out_mode = OUT_GRID_STORE;
         L.out = z;
         L.out_mode_L = OUT_GRID_STORE;
         L.out_L = P->d_stage;
@@ -241,9 +241,9 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
         t.end();
     }
     {
-        KTimer t(P, ASP_K_COMBINE, 4.0 * nact * (double)P->N * sizeof(zd), 0.0);
-        ASP_HIP(P, launch_combine3d(P, z, P->d_U, P->d_stage, P->X[0][1], P->X[m - 2][1], act,
-                                    nact, st));
+        KTimer t(P, ASP_K_COMBINE, 5.0 * nact * (double)P->N * sizeof(zd), 0.0);
+        ASP_HIP(P, launch_combine3d(P, z, P->d_U, P->d_stage, P->X[0][1], P->X[m - 2][1], true,
+                                    act, nact, st));
         t.end();
     }
     return ASP_OK;

@@ -196,8 +196,8 @@ asp_status apply3d_internal(asp_plan* P, const zd* r, zd* z, const int* act, int
     // u~_1 = u~_{1,1} + c_1;  u~_p += c_p for 1 < p < m
     {
         KTimer t(P, ASP_K_COMBINE, 4.0 * nact * (double)P->N * sizeof(zd), 0.0);
-        ASP_HIP(P, launch_combine3d(P, z, P->d_U, P->d_stage, P->X[0][1], P->X[m - 2][1], act, nact,
-                                    st));
+        ASP_HIP(P, launch_combine3d(P, z, P->d_U, P->d_stage, P->X[0][1], P->X[m - 2][1], false,
+                                    act, nact, st));
         t.end();
     }
     return ASP_OK;

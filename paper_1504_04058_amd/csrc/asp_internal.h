@@ -307,7 +307,7 @@ hipError_t launch_plane3d(const asp_plan* P, const zd* U, int line0, int line1, 
                           const int* act, int nact, hipStream_t st);
 // z = U + C on lines 1..split, z += C on lines split+1..upto
 hipError_t launch_combine3d(const asp_plan* P, zd* z, const zd* U, const zd* C, int split,
-                            int upto, const int* act, int nact, hipStream_t st);
+                            int upto, bool all_u, const int* act, int nact, hipStream_t st);
 
 // timing of one launch: constructed before the launch, end() after it
 struct KTimer {

@@ -681,16 +681,23 @@ __global__ __launch_bounds__(256) void plane3d_kernel(const zd* U, int line0, in
     W[((long long)job * S + p) * ws + slot] = U[(long long)rhs * N + S * (line - 1) + p];
 }
 
-// z = U + C on lines 1..split, z += C on lines split+1..upto
+// z = U + C on lines 1..split, z += C on lines split+1..upto; with all_u
+// (z holding the R outputs without U) also z += U on lines split+1..lines
 __global__ __launch_bounds__(256) void combine3d_kernel(zd* z, const zd* U, const zd* C, int split,
-                                                        int upto, const int* act, long long N,
-                                                        long long S) {
+                                                        int upto, int lines, int all_u,
+                                                        const int* act, long long N, long long S) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= S * upto) return;
+    if (i >= S * lines) return;
     const int rhs = act ? act[blockIdx.y] : blockIdx.y;
     const long long g = (long long)rhs * N + i;
     const int line = (int)(i / S) + 1;
-    z[g] = (line <= split) ? U[g] + C[g] : z[g] + C[g];
+    if (line <= split) {
+        z[g] = U[g] + C[g];
+    } else if (line <= upto) {
+        z[g] = all_u ? z[g] + C[g] + U[g] : z[g] + C[g];
+    } else {
+        z[g] = z[g] + U[g];
+    }
 }
 
 AxisTables axis_of(const asp_plan* P) {
@@ -827,10 +834,11 @@ hipError_t launch_plane3d(const asp_plan* P, const zd* U, int line0, int line1, 
 }
 
 hipError_t launch_combine3d(const asp_plan* P, zd* z, const zd* U, const zd* C, int split,
-                            int upto, const int* act, int nact, hipStream_t st) {
-    const long long cnt = P->S * upto;
+                            int upto, bool all_u, const int* act, int nact, hipStream_t st) {
+    const int lines = all_u ? (int)(P->N / P->S) : upto;
+    const long long cnt = P->S * lines;
     dim3 grid((unsigned)((cnt + 255) / 256), nact);
-    hipLaunchKernelGGL(combine3d_kernel, grid, dim3(256), 0, st, z, U, C, split, upto, act, P->N,
-                       P->S);
+    hipLaunchKernelGGL(combine3d_kernel, grid, dim3(256), 0, st, z, U, C, split, upto, lines,
+                       all_u ? 1 : 0, act, P->N, P->S);
     return hipGetLastError();
 }
