@@ -74,11 +74,13 @@ class Problem:
 
     d, n, omega as in the paper; gamma is the PML width in grid units
     (eta = gamma*h); C the PML constant; b the lines per interior layer;
-    c the velocity on the (n,)*d grid (first index = x1)."""
+    c the velocity on the (n,)*d grid (first index = x1); gamma_aux the width of
+    the auxiliary PML pads facing neighbouring layers (None: gamma)."""
 
-    def __init__(self, d, n, omega, gamma, C, b, c, pml_axes="all"):
+    def __init__(self, d, n, omega, gamma, C, b, c, pml_axes="all", gamma_aux=None):
         self.d, self.n, self.omega = int(d), int(n), float(omega)
         self.gamma, self.C, self.b = int(gamma), float(C), int(b)
+        self.gamma_aux = self.gamma if gamma_aux is None else int(gamma_aux)
         self.h = 1.0 / (self.n + 1)
         c = np.asarray(c, dtype=np.float64).reshape((self.n,) * self.d)
         self.c = c
@@ -98,7 +100,8 @@ class Problem:
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w["d"], w["n"], w["omega"], w["gamma"], w["C"], w["b"], w["c"])
+        return cls(w["d"], w["n"], w["omega"], w["gamma"], w["C"], w["b"], w["c"],
+                   gamma_aux=w.get("gamma_aux"))
 
     def axes(self):
         """Per-axis (s_int, s_half), fastest axis first; the sweep axis is last."""
@@ -116,10 +119,11 @@ class Problem:
         """Restriction of a grid vector to sweep lines lo..hi (1-based, inclusive)."""
         return np.asarray(vec)[(lo - 1) * self.S: hi * self.S]
 
-    def box_operator(self, lo, hi, phi, psi):
+    def box_operator(self, lo, hi, phi, psi, widths=None):
         """Symmetric-form operator on sweep lines lo..hi with Dirichlet data
         outside, the boundary PML on the cross axes and, on the sweep axis, the
-        profile that vanishes on [phi, psi]."""
-        sweep = pml.tables(lo, hi, phi, psi, self.C, self.gamma, self.h, self.omega)
+        profile that vanishes on [phi, psi] (widths: its PML width below phi and
+        above psi, default gamma on both sides)."""
+        sweep = pml.tables(lo, hi, phi, psi, self.C, widths or self.gamma, self.h, self.omega)
         ksq = self.lines(self.ksq, lo, hi)
         return symmetric_operator([self.cross] * (self.d - 1) + [sweep], ksq, self.h)

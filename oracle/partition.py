@@ -29,6 +29,12 @@ with [s_p, e_p] = X_p and its physical part phi_p = max(s_p, gamma),
 psi_p = min(e_p, n+1-gamma).  sigma^R_p vanishes from the Dirichlet line
 s_p - 1 (the left boundary of D^R_p) and sigma^L_p up to the Dirichlet line
 e_p + 1 (the right boundary of D^L_p), as in their definitions.
+
+Thinner auxiliary PML (Section 3.1 remarks, eta_aux < eta): a pad that faces a
+neighbouring layer (not the boundary of the domain) has g_a = gamma_aux - 1
+lines and the profile of width eta_aux = gamma_aux*h; a pad at the boundary of
+the domain is the boundary PML itself (g lines, width eta).  With
+gamma_aux = gamma every pad is as above.
 """
 from dataclasses import dataclass
 
@@ -41,6 +47,8 @@ class Sub:
     hi: int     # last grid line of the extended grid
     phi: float  # zero region of the sweep-axis PML profile
     psi: float
+    gamma_lo: int = 0   # PML width (grid units) of the profile below phi / above psi
+    gamma_hi: int = 0
 
     @property
     def L(self):
@@ -72,21 +80,30 @@ def physical(n, gamma, layer):
     return max(s_p, gamma), min(e_p, n + 1 - gamma)
 
 
-def subproblems(n, b, gamma):
+def subproblems(n, b, gamma, gamma_aux=None):
     """Dict with lists 'M' (q=1..m), 'R' (p=2..m) and 'L' (p=1..m-1) of Sub."""
     X = layers(n, b, gamma)
     m = len(X)
     g = gamma - 1
+    ga = gamma if gamma_aux is None else int(gamma_aux)
+    if not 2 <= ga <= gamma:
+        raise ValueError(f"invalid auxiliary PML width {gamma_aux} (gamma = {gamma})")
+    # pad below layer p (toward layer p-1) and above it (toward layer p+1)
+    low = lambda p: (g, gamma) if p == 1 else (ga - 1, ga)
+    high = lambda p: (g, gamma) if p == m else (ga - 1, ga)
     M, R, L = [], [], []
     for q in range(1, m + 1):
         phi, psi = physical(n, gamma, X[q - 1])
-        M.append(Sub("M", q, phi - g, psi + g, phi, psi))
+        (gl, wl), (gh, wh) = low(q), high(q)
+        M.append(Sub("M", q, phi - gl, psi + gh, phi, psi, wl, wh))
     for p in range(2, m + 1):
         s_p, _ = X[p - 1]
         _, psi = physical(n, gamma, X[p - 1])
-        R.append(Sub("R", p, s_p, psi + g, s_p - 1, psi))
+        gh, wh = high(p)
+        R.append(Sub("R", p, s_p, psi + gh, s_p - 1, psi, wh, wh))
     for p in range(1, m):
         _, e_p = X[p - 1]
         phi, _ = physical(n, gamma, X[p - 1])
-        L.append(Sub("L", p, phi - g, e_p, phi, e_p + 1))
+        gl, wl = low(p)
+        L.append(Sub("L", p, phi - gl, e_p, phi, e_p + 1, wl, wl))
     return {"M": M, "R": R, "L": L}

@@ -16,11 +16,21 @@ import numpy as np
 
 
 def sigma(t, phi, psi, C, gamma, h):
-    """sigma at x = t*h for a profile that vanishes on [phi*h, psi*h]."""
+    """sigma at x = t*h for a profile that vanishes on [phi*h, psi*h].
+
+    gamma is the PML width in grid units, or a pair (gamma below phi, gamma
+    above psi) when the two sides differ (a thinner auxiliary PML facing the
+    neighbouring layers, Section 3.1 remarks)."""
     t = np.asarray(t, dtype=np.float64)
-    eta = gamma * h
-    dist = np.maximum(0.0, np.maximum(phi - t, t - psi)) * h   # distance to the zero region
-    return (C / eta) * (dist / eta) ** 2
+    g_lo, g_hi = (gamma, gamma) if np.isscalar(gamma) else gamma
+    if g_lo == g_hi:
+        eta = g_lo * h
+        dist = np.maximum(0.0, np.maximum(phi - t, t - psi)) * h   # distance to the zero region
+        return (C / eta) * (dist / eta) ** 2
+    eta_lo, eta_hi = g_lo * h, g_hi * h
+    d_lo = np.maximum(0.0, phi - t) * h
+    d_hi = np.maximum(0.0, t - psi) * h
+    return (C / eta_lo) * (d_lo / eta_lo) ** 2 + (C / eta_hi) * (d_hi / eta_hi) ** 2
 
 
 def s(t, phi, psi, C, gamma, h, omega):

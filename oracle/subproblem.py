@@ -33,6 +33,12 @@ from scipy.linalg import lapack
 from .partition import Sub
 
 
+def _widths(prob, sub):
+    """PML widths of the sweep-axis profile below and above its zero region
+    (the sub's own, or gamma on both sides for a Sub built without them)."""
+    return (sub.gamma_lo or prob.gamma, sub.gamma_hi or prob.gamma)
+
+
 class BandLU:
     """Banded LU of a sparse matrix (LAPACK zgbtrf / zgbtrs)."""
 
@@ -70,7 +76,7 @@ class Subproblem:
         self.prob, self.sub = prob, sub
         self.X_p = X_p                 # (s_p, e_p) of the layer this G~ restricts to
         self.L = sub.L
-        self.H = prob.box_operator(sub.lo, sub.hi, sub.phi, sub.psi)
+        self.H = prob.box_operator(sub.lo, sub.hi, sub.phi, sub.psi, _widths(prob, sub))
         self.lu = None
         self._coupling = None
         if factor:
@@ -124,10 +130,10 @@ class Subproblem:
             return self._coupling
         S, sub = self.prob.S, self.sub
         if sub.kind == "R":
-            Hx = self.prob.box_operator(sub.lo - 1, sub.hi, sub.phi, sub.psi)
+            Hx = self.prob.box_operator(sub.lo - 1, sub.hi, sub.phi, sub.psi, _widths(self.prob, sub))
             blk = Hx[S:2 * S, 0:S]
         elif sub.kind == "L":
-            Hx = self.prob.box_operator(sub.lo, sub.hi + 1, sub.phi, sub.psi)
+            Hx = self.prob.box_operator(sub.lo, sub.hi + 1, sub.phi, sub.psi, _widths(self.prob, sub))
             n_rows = Hx.shape[0]
             blk = Hx[n_rows - 2 * S:n_rows - S, n_rows - S:n_rows]
         else:

@@ -24,7 +24,7 @@ class Preconditioner:
         self.prob = prob
         self.X = partition.layers(prob.n, prob.b, prob.gamma)
         self.m = len(self.X)
-        subs = partition.subproblems(prob.n, prob.b, prob.gamma)
+        subs = partition.subproblems(prob.n, prob.b, prob.gamma, prob.gamma_aux)
         self.keep = keep_factors
         # Algorithm 1 / 3: factor H^M_q (q=1..m), H^R_p (p=2..m), H^L_p (p=1..m-1).
         mk = lambda s: Subproblem(prob, s, self.X[s.p - 1], factor=keep_factors)

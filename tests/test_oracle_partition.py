@@ -94,3 +94,47 @@ def test_single_layer_and_invalid():
     for bad in [(20, 4, 12), (63, 0, 12), (63, 4, 1)]:
         with pytest.raises(ValueError):
             partition.layers(*bad)
+
+
+@pytest.mark.parametrize("n,gamma,gamma_aux,b", [(63, 9, 5, 4), (127, 9, 5, 8), (66, 12, 4, 4),
+                                                 (40, 6, 2, 5)])
+def test_thin_auxiliary_pads(n, gamma, gamma_aux, b):
+    """Thinner auxiliary PML (Section 3.1 remarks): a pad facing a neighbouring
+    layer has gamma_aux - 1 lines and width gamma_aux, a pad at the boundary of
+    the domain is the boundary PML (gamma - 1 lines, width gamma); the zero
+    regions and the layers do not change."""
+    g, ga = gamma - 1, gamma_aux - 1
+    base = partition.subproblems(n, b, gamma)
+    thin = partition.subproblems(n, b, gamma, gamma_aux)
+    m = len(partition.layers(n, b, gamma))
+    for kind in "MRL":
+        for s0, s in zip(base[kind], thin[kind]):
+            assert (s.kind, s.p, s.phi, s.psi) == (s0.kind, s0.p, s0.phi, s0.psi)
+    for s in thin["M"]:
+        assert s.phi - s.lo == (g if s.p == 1 else ga)
+        assert s.hi - s.psi == (g if s.p == m else ga)
+        assert (s.gamma_lo, s.gamma_hi) == (gamma if s.p == 1 else gamma_aux,
+                                            gamma if s.p == m else gamma_aux)
+    for s in thin["R"]:
+        assert s.lo == s.phi + 1 and s.hi - s.psi == (g if s.p == m else ga)
+        assert s.gamma_hi == (gamma if s.p == m else gamma_aux)
+    for s in thin["L"]:
+        assert s.hi == s.psi - 1 and s.phi - s.lo == (g if s.p == 1 else ga)
+        assert s.gamma_lo == (gamma if s.p == 1 else gamma_aux)
+    # gamma_aux = gamma is the default partition
+    same = partition.subproblems(n, b, gamma, gamma)
+    for kind in "MRL":
+        assert [(s.lo, s.hi, s.phi, s.psi) for s in same[kind]] == \
+               [(s.lo, s.hi, s.phi, s.psi) for s in base[kind]]
+
+
+def test_thin_auxiliary_sizes_at_the_3d_settings():
+    """Section 4.2's 3D settings (eta = 9h, eta_aux = 5h, b = 4): interior
+    M-problems span b + 2 (gamma_aux - 1) = 12 lines, interior R/L problems 8,
+    the first M-problem g + b + 4 = 16."""
+    n = 79
+    subs = partition.subproblems(n, 4, 9, 5)
+    assert subs["M"][0].L == 16 and all(s.L == 12 for s in subs["M"][1:-2])
+    assert all(s.L == 8 for s in subs["R"][:-1]) and all(s.L == 8 for s in subs["L"][1:])
+    with pytest.raises(ValueError):
+        partition.subproblems(n, 4, 9, 10)

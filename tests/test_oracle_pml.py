@@ -104,3 +104,19 @@ def test_auxiliary_profiles_match_printed_formulas(gamma, b, m):
                 want = printed_aux_sigma(kind, sub.p, t, gamma, b, m, eta)
                 got = float(pml.sigma(t, sub.phi, sub.psi, C, gamma, h))
                 assert got == pytest.approx(want, rel=1e-12, abs=1e-12), (kind, sub.p, t)
+
+
+def test_two_sided_widths():
+    """A profile with different widths below and above its zero region (a thin
+    auxiliary pad on one side): each side is the quadratic of its own width,
+    and equal widths give the one-width profile exactly."""
+    from oracle import pml as P2
+    h, C = 1.0 / 64, 25.0
+    phi, psi = 10.0, 30.0
+    t = np.array([4.0, 7.5, 10.0, 20.0, 30.0, 33.5, 36.0])
+    sg = P2.sigma(t, phi, psi, C, (9, 5), h)
+    e9, e5 = 9 * h, 5 * h
+    ref = [(C / e9) * ((phi - x) * h / e9) ** 2 if x < phi else
+           (C / e5) * ((x - psi) * h / e5) ** 2 if x > psi else 0.0 for x in t]
+    np.testing.assert_allclose(sg, ref, rtol=1e-15, atol=0)
+    np.testing.assert_array_equal(P2.sigma(t, phi, psi, C, (7, 7), h), P2.sigma(t, phi, psi, C, 7, h))

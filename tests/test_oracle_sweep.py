@@ -38,6 +38,36 @@ def test_accumulated_sweep_equals_componentwise(d, n, gamma, b):
     assert np.linalg.norm(z1 - z2) <= 1e-12 * np.linalg.norm(z1)
 
 
+@pytest.mark.parametrize("d,n,gamma,gamma_aux,b", [(2, 40, 6, 3, 5), (3, 15, 4, 2, 2)])
+def test_accumulated_sweep_with_thin_auxiliary_pml(d, n, gamma, gamma_aux, b):
+    """The accumulation identity holds for any auxiliary operators, so also
+    with thinner auxiliary pads (Section 3.1 remarks)."""
+    rng = np.random.default_rng(n + 1)
+    c = 0.8 + 0.4 * rng.random((n,) * d)
+    P = Problem(d, n, 2 * math.pi * (n + 1) / 10, gamma, 25.0, b, c, gamma_aux=gamma_aux)
+    M = Preconditioner(P)
+    assert M.m >= 3
+    f = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
+    z1, z2 = M.apply(f), M.apply_componentwise(f)
+    assert np.linalg.norm(z1 - z2) <= 1e-12 * np.linalg.norm(z1)
+
+
+def test_thin_auxiliary_pml_keeps_the_iteration_band():
+    """eta_aux = 5h with eta = 9h (the paper's 3D choice) at the 2D paper
+    settings, n = 127: still within the largest printed count."""
+    table = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))
+    largest = max(max(v) for fam in ("lens", "waveguide", "random") for v in table[fam].values())
+    w = workloads.paper_workload("lens", 127)
+    w["gamma_aux"] = 5
+    P = Problem.from_workload(w)
+    A = P.A()
+    M = Preconditioner(P)
+    for k in range(2):
+        b = w["f"][k] / P.scale()
+        x, it, rr, _ = gmres(lambda v: A @ v, M.apply, b, w["tol"], w["restart"], 100)
+        assert rr <= w["tol"] and 1 <= it <= largest
+
+
 def test_single_layer_is_exact():
     n, gamma = 20, 6
     P = Problem(2, n, 2 * math.pi * 2, gamma, 25.0, 20, 1.0 + 0.1 * np.random.default_rng(1).random((n, n)))
