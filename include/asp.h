@@ -72,6 +72,11 @@ typedef struct {
     int host_only;  /* nonzero: build the partition and tables on the host only, touch no
                        device; the plan then supports asp_layers, asp_tables, asp_info,
                        asp_last_error and asp_destroy (other calls return ASP_ERR_STATE) */
+    int pml_aux;    /* width (grid lines) of the auxiliary PML on the pads that face a
+                       neighbouring layer: the thinner auxiliary PML of the Section 3.1
+                       remarks, eta_aux = pml_aux * h.  Pads at the domain boundary keep
+                       the boundary PML.  0 (default): pml_eta; otherwise 2..pml_eta,
+                       else ASP_ERR_ARG */
 } asp_opts;
 
 typedef struct {

@@ -32,7 +32,7 @@ class AspError(RuntimeError):
 
 class asp_opts(ctypes.Structure):
     _fields_ = [("C", ctypes.c_double), ("prec", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("host_only", ctypes.c_int)]
+                ("host_only", ctypes.c_int), ("pml_aux", ctypes.c_int)]
 
 
 class asp_plan_info(ctypes.Structure):
@@ -117,13 +117,14 @@ def _current_stream():
 # -- the C entry points --------------------------------------------------------------
 
 def asp_setup(dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64, stream=None,
-              host_only=False):
+              host_only=False, pml_aux=0):
     """Returns a plan handle (ctypes.c_void_p).  c: host array, n**dim velocities
     (column-major, i.e. numpy order='F' flattening of an (n,)*dim array)."""
     c = np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(-1, order="F")
                              if np.asarray(c).ndim > 1 else np.asarray(c, dtype=np.float64))
     opts = asp_opts(C, prec, stream if stream is not None else
-                    (ctypes.c_void_p(0) if host_only else _current_stream()), int(host_only))
+                    (ctypes.c_void_p(0) if host_only else _current_stream()), int(host_only),
+                    int(pml_aux or 0))
     plan = ctypes.c_void_p()
     st = lib().asp_setup(ctypes.byref(plan), dim, c.ctypes.data_as(ctypes.c_void_p), omega, n,
                          layer_b, pml_eta, ctypes.byref(opts))
@@ -228,11 +229,11 @@ class Plan:
     """Owning wrapper around a plan handle (destroyed with the object)."""
 
     def __init__(self, dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64,
-                 host_only=False):
+                 host_only=False, pml_aux=0):
         self.dim, self.n = dim, n
         self.N = n ** dim
         self.handle = asp_setup(dim, c, omega, n, layer_b, pml_eta, C=C, prec=prec,
-                                host_only=host_only)
+                                host_only=host_only, pml_aux=pml_aux)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -93,6 +93,7 @@ struct SubDesc {
     int xs, xe;          // lines of X_p (output lines)
     int src_line;        // R: last line of X_{p-1};  L: first line of X_{p+1};  M: 0
     int phi, psi;        // zero region of the sweep-axis PML profile
+    int gam_lo, gam_hi;  // its PML width (grid units) below phi / above psi
     long long fac_off;   // offset of block k = 1 in the factor buffer (complex entries)
     long long tab_off;   // offset of this problem's tables in the table buffer
     long long tr_off;    // offset of its boundary-to-boundary map (R_p, L_p with 1 < p < m), else -1
@@ -128,6 +129,7 @@ constexpr int SINK_ELEMS = 1024;   // complex128 entries of the discard buffer
 struct asp_plan {
     // problem
     int dim = 0, n = 0, b = 0, gamma = 0, g = 0, m = 0;
+    int gamma_aux = 0;                // PML width of the pads facing another layer
     double omega = 0, h = 0, C = 25.0;
     int prec = ASP_PREC_FP64;
     hipStream_t stream = nullptr;

@@ -20,27 +20,34 @@ namespace {
 using cd = std::complex<double>;
 
 // sigma at grid coordinate t for a profile vanishing on [phi, psi] (line units):
-// (C/eta) (dist/eta)^2 with eta = gamma h and dist the distance to [phi, psi].
-double sigma_at(double t, double phi, double psi, double C, int gamma, double h) {
+// (C/eta) (dist/eta)^2 with dist the distance to [phi, psi] and eta = gamma h,
+// gamma = g_lo below phi and g_hi above psi (a thinner auxiliary pad on a side
+// facing another layer, Section 3.1 remarks).
+double sigma_at(double t, double phi, double psi, double C, int g_lo, int g_hi, double h) {
     double dist = 0.0;
+    int gamma = g_lo;
     if (t < phi) dist = phi - t;
-    if (t > psi) dist = t - psi;
+    if (t > psi) {
+        dist = t - psi;
+        gamma = g_hi;
+    }
     const double eta = gamma * h;
     const double r = dist * h / eta;
     return (C / eta) * r * r;
 }
 
-cd s_at(double t, double phi, double psi, double C, int gamma, double h, double omega) {
-    return 1.0 / cd(1.0, sigma_at(t, phi, psi, C, gamma, h) / omega);
+cd s_at(double t, double phi, double psi, double C, int g_lo, int g_hi, double h, double omega) {
+    return 1.0 / cd(1.0, sigma_at(t, phi, psi, C, g_lo, g_hi, h) / omega);
 }
 
-void fill_tables(int lo, int hi, double phi, double psi, const asp_plan* P,
+void fill_tables(int lo, int hi, double phi, double psi, int g_lo, int g_hi, const asp_plan* P,
                  std::vector<cd>& s_int, std::vector<cd>& s_half) {
     s_int.resize(hi - lo + 1);
     s_half.resize(hi - lo + 2);
-    for (int t = lo; t <= hi; ++t) s_int[t - lo] = s_at(t, phi, psi, P->C, P->gamma, P->h, P->omega);
+    for (int t = lo; t <= hi; ++t)
+        s_int[t - lo] = s_at(t, phi, psi, P->C, g_lo, g_hi, P->h, P->omega);
     for (int k = 0; k <= hi - lo + 1; ++k)
-        s_half[k] = s_at(lo - 0.5 + k, phi, psi, P->C, P->gamma, P->h, P->omega);
+        s_half[k] = s_at(lo - 0.5 + k, phi, psi, P->C, g_lo, g_hi, P->h, P->omega);
 }
 
 template <typename T>
@@ -78,8 +85,16 @@ static void build_partition(asp_plan* P) {
 // vanishing on X_q's physical part [phi_q, psi_q]; R_p on [s_p, psi_p + g]
 // vanishing on [s_p - 1, psi_p] (from the Dirichlet line of D^R_p); L_p on
 // [phi_p - g, e_p] vanishing on [phi_p, e_p + 1] (up to the Dirichlet line of D^L_p).
+// A pad facing a neighbouring layer has gamma_aux - 1 lines and width gamma_aux
+// (the thinner auxiliary PML of the Section 3.1 remarks); a pad at the domain
+// boundary is the boundary PML (g lines, width gamma).
 static void build_subproblems(asp_plan* P) {
     const int n = P->n, gamma = P->gamma, g = P->g, m = P->m;
+    const int ga = P->gamma_aux;
+    auto pad_lo = [&](int p) { return p == 1 ? g : ga - 1; };
+    auto pad_hi = [&](int p) { return p == m ? g : ga - 1; };
+    auto wid_lo = [&](int p) { return p == 1 ? gamma : ga; };
+    auto wid_hi = [&](int p) { return p == m ? gamma : ga; };
     P->subs.clear();
     auto phys = [&](int p, int& phi, int& psi) {
         phi = std::max(P->X[p - 1][0], gamma);
@@ -89,7 +104,9 @@ static void build_subproblems(asp_plan* P) {
         SubDesc d{};
         int phi, psi;
         phys(q, phi, psi);
-        d.kind = ASP_SUB_M; d.p = q; d.lo = phi - g; d.hi = psi + g; d.phi = phi; d.psi = psi;
+        d.kind = ASP_SUB_M; d.p = q; d.lo = phi - pad_lo(q); d.hi = psi + pad_hi(q);
+        d.phi = phi; d.psi = psi;
+        d.gam_lo = wid_lo(q); d.gam_hi = wid_hi(q);
         d.src_line = 0;
         P->subs.push_back(d);
     }
@@ -97,8 +114,9 @@ static void build_subproblems(asp_plan* P) {
         SubDesc d{};
         int phi, psi;
         phys(p, phi, psi);
-        d.kind = ASP_SUB_R; d.p = p; d.lo = P->X[p - 1][0]; d.hi = psi + g;
+        d.kind = ASP_SUB_R; d.p = p; d.lo = P->X[p - 1][0]; d.hi = psi + pad_hi(p);
         d.phi = P->X[p - 1][0] - 1; d.psi = psi;
+        d.gam_lo = d.gam_hi = wid_hi(p);
         d.src_line = P->X[p - 2][1];
         P->subs.push_back(d);
     }
@@ -106,8 +124,9 @@ static void build_subproblems(asp_plan* P) {
         SubDesc d{};
         int phi, psi;
         phys(p, phi, psi);
-        d.kind = ASP_SUB_L; d.p = p; d.lo = phi - g; d.hi = P->X[p - 1][1];
+        d.kind = ASP_SUB_L; d.p = p; d.lo = phi - pad_lo(p); d.hi = P->X[p - 1][1];
         d.phi = phi; d.psi = P->X[p - 1][1] + 1;
+        d.gam_lo = d.gam_hi = wid_lo(p);
         d.src_line = P->X[p][0];
         P->subs.push_back(d);
     }
@@ -126,6 +145,7 @@ extern "C" void asp_default_opts(asp_opts* o) {
     o->prec = ASP_PREC_FP64;
     o->stream = nullptr;
     o->host_only = 0;
+    o->pml_aux = 0;
 }
 
 extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double omega, int n,
@@ -149,6 +169,8 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (pml_eta < 2) return fail(ASP_ERR_ARG, "pml_eta must be >= 2");
     if (layer_b < 1) return fail(ASP_ERR_ARG, "layer_b must be >= 1");
     if (n < 1 || n - 2 * (pml_eta - 1) < 1) return fail(ASP_ERR_ARG, "n too small for the PML");
+    if (o.pml_aux != 0 && (o.pml_aux < 2 || o.pml_aux > pml_eta))
+        return fail(ASP_ERR_ARG, "pml_aux must be 0 or in [2, pml_eta]");
     if (!(o.C >= 0.0) || !std::isfinite(o.C)) return fail(ASP_ERR_ARG, "C must be finite and >= 0");
     if (o.prec != ASP_PREC_FP64 && o.prec != ASP_PREC_FP32 && o.prec != ASP_PREC_BF16X3)
         return fail(ASP_ERR_ARG, "unknown precision");
@@ -161,6 +183,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     P->b = layer_b;
     P->gamma = pml_eta;
     P->g = pml_eta - 1;
+    P->gamma_aux = o.pml_aux ? o.pml_aux : pml_eta;
     P->omega = omega;
     P->h = 1.0 / (n + 1);
     P->C = o.C;
@@ -181,13 +204,13 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
 
     // PML tables: the boundary profile of one axis, and the sweep-axis profile
     // of every auxiliary problem
-    fill_tables(1, n, P->gamma, n + 1 - P->gamma, P, P->ax_int, P->ax_half);
+    fill_tables(1, n, P->gamma, n + 1 - P->gamma, P->gamma, P->gamma, P, P->ax_int, P->ax_half);
     P->sub_int.resize(P->subs.size());
     P->sub_half.resize(P->subs.size());
     int maxL_M = 0, maxL_RL = 0;
     for (size_t s = 0; s < P->subs.size(); ++s) {
         const SubDesc& d = P->subs[s];
-        fill_tables(d.lo, d.hi, d.phi, d.psi, P, P->sub_int[s], P->sub_half[s]);
+        fill_tables(d.lo, d.hi, d.phi, d.psi, d.gam_lo, d.gam_hi, P, P->sub_int[s], P->sub_half[s]);
         if (d.kind == ASP_SUB_M) maxL_M = std::max(maxL_M, d.L);
         else maxL_RL = std::max(maxL_RL, d.L);
     }

@@ -72,6 +72,37 @@ def test_pml_tables_match_oracle(dim, n, b, gamma):
         asp.asp_destroy(plan)
 
 
+AUX_CONFIGS = [(2, 127, 8, 9, 5), (3, 39, 4, 9, 5), (2, 63, 4, 12, 4), (2, 40, 5, 6, 2)]
+
+
+@pytest.mark.parametrize("dim,n,b,gamma,aux", AUX_CONFIGS)
+def test_thin_auxiliary_pml_matches_oracle(dim, n, b, gamma, aux):
+    """pml_aux: the partition (bit-exact) and every sweep-axis table against
+    the oracle's thin auxiliary pads (Section 3.1 remarks)."""
+    omega = 2 * np.pi * (n + 1) / 8
+    c = np.ones(n ** dim)
+    plan = asp.asp_setup(dim, c, omega, n, b, gamma, host_only=True, pml_aux=aux)
+    h = 1.0 / (n + 1)
+    try:
+        layers, subs = asp.asp_layers(plan)
+        ref = partition.subproblems(n, b, gamma, aux)
+        kinds = {"M": asp.ASP_SUB_M, "R": asp.ASP_SUB_R, "L": asp.ASP_SUB_L}
+        refl = [s for k in ("M", "R", "L") for s in ref[k]]
+        want = [(kinds[s.kind], s.p, s.lo, s.hi, s.phi, s.psi) for s in refl]
+        assert [tuple(r) for r in subs.tolist()] == want
+        for k, s in enumerate(refl):
+            s_int, s_half = asp.asp_tables(plan, k, s.hi - s.lo + 1)
+            ref_int, ref_half = pml.tables(s.lo, s.hi, s.phi, s.psi, 25.0, (s.gamma_lo, s.gamma_hi),
+                                           h, omega)
+            np.testing.assert_allclose(s_int, ref_int, rtol=4e-16, atol=0)
+            np.testing.assert_allclose(s_half, ref_half, rtol=4e-16, atol=0)
+    finally:
+        asp.asp_destroy(plan)
+    with pytest.raises(asp.AspError) as ei:
+        asp.asp_setup(dim, c, omega, n, b, gamma, host_only=True, pml_aux=gamma + 1)
+    assert ei.value.status == asp.ASP_ERR_ARG and "pml_aux" in str(ei.value)
+
+
 @pytest.mark.parametrize("args,frag", [
     ((4, 63, 4, 12), "dim"),
     ((2, 20, 4, 12), "n too small"),

@@ -1,0 +1,113 @@
+"""GPU parity of the thinner auxiliary PML (Section 3.1 remarks: pads facing a
+neighbouring layer with eta_aux < eta, pads at the domain boundary keep the
+boundary PML) against the CPU FP64 oracle, through the C ABI: one auxiliary
+Green's operator of each kind and the whole apply, 2D and 3D, FP64 factors
+1e-11 and FP32 factors 2e-4 / 1e-3 (the bars of the full-width tests), and
+GMRES at the paper's 3D choice eta = 9h, eta_aux = 5h with the oracle's
+iteration count."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import partition
+from oracle.gmres import gmres as oracle_gmres
+from oracle.operator import Problem
+from oracle.subproblem import Subproblem
+from oracle.sweep import Preconditioner
+
+pytestmark = pytest.mark.gpu
+asp = pytest.importorskip("paper_1504_04058_amd.asp")
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _problem(d, n, gamma, aux, b, seed=1):
+    c = workloads.velocity_random(n, d, seed=seed, width=3.0 if d == 3 else 8.0)
+    return Problem(d, n, 2 * math.pi * (n + 1) / 8, gamma, 25.0, b, c, gamma_aux=aux)
+
+
+def _plan(P, prec):
+    return asp.Plan(P.d, P.c, P.omega, P.n, P.b, P.gamma, C=P.C, prec=prec, pml_aux=P.gamma_aux)
+
+
+CASES = [(2, 127, 9, 5, 8), (2, 63, 12, 4, 4), (3, 23, 8, 4, 4), (3, 26, 9, 5, 3)]
+
+
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 2e-4)])
+@pytest.mark.parametrize("d,n,gamma,aux,b", CASES)
+def test_thin_auxiliary_operators(d, n, gamma, aux, b, prec, tol):
+    print(f"thin pml operators d={d} n={n} gamma={gamma} aux={aux} b={b} prec={prec}", flush=True)
+    P = _problem(d, n, gamma, aux, b)
+    X = partition.layers(n, b, gamma)
+    subs = partition.subproblems(n, b, gamma, aux)
+    m = len(X)
+    rng = np.random.default_rng(11)
+    picks = {"M": [1, 2, m], "R": [2, m], "L": [1, m - 1]}
+    kinds = {"M": asp.ASP_SUB_M, "R": asp.ASP_SUB_R, "L": asp.ASP_SUB_L}
+    with _plan(P, prec) as plan:
+        plan.factor()
+        for kind, ps in picks.items():
+            for p in sorted(set(ps)):
+                sub = [s for s in subs[kind] if s.p == p][0]
+                ref = Subproblem(P, sub, X[p - 1])
+                Np = P.S * (X[p - 1][1] - X[p - 1][0] + 1)
+                k_in = Np if kind == "M" else P.S
+                data = rng.standard_normal((2, k_in)) + 1j * rng.standard_normal((2, k_in))
+                out = host(plan.subsolve(kinds[kind], p, dev(data), Np)).reshape(2, Np)
+                for r in range(2):
+                    assert rel(out[r], ref.G(data[r])) < tol, (kind, p)
+
+
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
+@pytest.mark.parametrize("d,n,gamma,aux,b", CASES)
+def test_thin_apply(d, n, gamma, aux, b, prec, tol):
+    print(f"thin pml apply d={d} n={n} aux={aux} prec={prec}", flush=True)
+    P = _problem(d, n, gamma, aux, b)
+    M = Preconditioner(P)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
+    with _plan(P, prec) as plan:
+        plan.factor()
+        z = host(plan.apply(dev(r)))
+    for k in range(2):
+        assert rel(z[k], M.apply(r[k])) < tol
+
+
+@pytest.mark.parametrize("d,n", [(2, 127), (3, 31)])
+def test_thin_gmres_iterations(d, n):
+    """eta = 9h, eta_aux = 5h, b = 4 (3D) / 8 (2D), GMRES(40) to 1e-3 on a
+    lens with a point source: the GPU count equals the oracle's within 1."""
+    print(f"thin pml gmres d={d} n={n}", flush=True)
+    b = 8 if d == 2 else 4
+    c = workloads.velocity_lens2d(n) if d == 2 else workloads.velocity_lens3d(n)
+    omega = 2 * math.pi * (n + 1) / 8
+    P = Problem(d, n, omega, 9, 25.0, b, c, gamma_aux=5)
+    centre = (0.5, 0.125) if d == 2 else (0.5, 0.5, 0.25)
+    f = workloads.flat(workloads.gaussian_source(n, d, omega, centre)).astype(np.complex128)
+    bvec = f / P.scale()
+    A = P.A()
+    _, it_ref, rr, _ = oracle_gmres(lambda v: A @ v, Preconditioner(P).apply, bvec, 1e-3, 40, 100)
+    with _plan(P, asp.ASP_PREC_FP64) as plan:
+        u, it, rres, st = plan.gmres(dev(f[None]), tol=1e-3, restart=40, maxit=100)
+        u = host(u)
+    assert st == asp.ASP_OK
+    print(f"  gpu {int(it[0])} oracle {it_ref}", flush=True)
+    assert abs(int(it[0]) - it_ref) <= 1
+    assert np.linalg.norm(bvec - A @ u[0]) / np.linalg.norm(bvec) <= 1e-3 * (1 + 1e-9)
