@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--paper-tables", default="",
                     help="comma-separated grid sizes of the paper's 2D experiments to run "
                          "(e.g. 127,255,511,1023,2047); '' for none")
+    ap.add_argument("--paper-tables3d", default="",
+                    help="grid sizes of the paper's 3D experiments to run (e.g. 39,79); '' for none")
     return ap.parse_args()
 
 
@@ -287,11 +289,12 @@ def serving_run(count, prec_name):
     return summ
 
 
-def paper_tables(prec_name, sizes):
-    """The paper's 2D experiments (Tables 1-3 of Section 3.2) on this path: per
-    field and grid, the factorization time, the GMRES(40) iterations to 1e-3 for
-    force (a) point source and (b) wave packet (solved as one batch of two
-    right-hand sides) and the solve time, beside the printed iteration counts."""
+def paper_tables(prec_name, sizes, dim=2):
+    """The paper's experiments (Tables 1-3 of Section 3.2 in 2D, Tables 4-6 of
+    Section 4.2 in 3D) on this path: per field and grid, the factorization
+    time, the GMRES(40) iterations to 1e-3 for force (a) point source and (b)
+    wave packet (solved as one batch of two right-hand sides) and the solve
+    time, beside the printed iteration counts."""
     import json as _json
 
     import torch
@@ -299,17 +302,20 @@ def paper_tables(prec_name, sizes):
     import workloads
     from paper_1504_04058_amd import asp
 
-    with open(os.path.join(ROOT, "tests", "golden", "paper_iterations.json")) as fh:
+    golden = "paper_iterations.json" if dim == 2 else "paper_iterations_3d.json"
+    with open(os.path.join(ROOT, "tests", "golden", golden)) as fh:
         printed = _json.load(fh)
-    prec = {"fp32": asp.ASP_PREC_FP32, "fp64": asp.ASP_PREC_FP64}[prec_name]
+    prec = {"fp32": asp.ASP_PREC_FP32, "fp64": asp.ASP_PREC_FP64,
+            "bf16x3": asp.ASP_PREC_BF16X3}[prec_name]
     rows = []
     for n in sizes:
         col = printed["n"].index(n) if n in printed["n"] else None
         for field in workloads.PAPER_FIELDS:
-            w = workloads.paper_workload(field, n)
+            w = workloads.paper_workload(field, n) if dim == 2 else workloads.paper_workload3d(field, n)
             f = torch.from_numpy(w["f"]).cuda()
             u = torch.empty_like(f)
-            with asp.Plan(2, w["c"], w["omega"], n, w["b"], w["gamma"], C=w["C"], prec=prec) as plan:
+            with asp.Plan(dim, w["c"], w["omega"], n, w["b"], w["gamma"], C=w["C"], prec=prec,
+                          pml_aux=w.get("gamma_aux", 0)) as plan:
                 torch.cuda.synchronize()
                 a = time.perf_counter()
                 plan.factor()
@@ -326,9 +332,11 @@ def paper_tables(prec_name, sizes):
                          [printed[field]["force_a"][col], printed[field]["force_b"][col]]})
             del f, u
             torch.cuda.empty_cache()
-    return {"settings": "gamma 9, b 8, C 25, 8 points per wavelength, GMRES(40) to 1e-3, "
-                        "forces (a) point source at (1/2, 1/8), (b) wave packet at (1/8, 1/8)",
-            "layer_precision": prec_name, "rows": rows}
+    settings = ("gamma 9, b 8, C 25, 8 points per wavelength, GMRES(40) to 1e-3, "
+                "forces (a) point source at (1/2, 1/8), (b) wave packet at (1/8, 1/8)") if dim == 2 else \
+               ("gamma 9, gamma_aux 5, b 4, C 25, 8 points per wavelength, GMRES(40) to 1e-3, "
+                "forces (a) point source at (1/2, 1/2, 1/4), (b) wave packet at (1/2, 1/4, 1/4)")
+    return {"settings": settings, "dim": dim, "layer_precision": prec_name, "rows": rows}
 
 
 def workloads_dim(name):
@@ -395,6 +403,9 @@ def main():
         out["serving"] = serving_run(args.serve_requests, args.prec)
     if args.paper_tables:
         out["paper_tables"] = paper_tables(args.prec, [int(x) for x in args.paper_tables.split(",")])
+    if args.paper_tables3d:
+        out["paper_tables3d"] = paper_tables(args.prec, [int(x) for x in args.paper_tables3d.split(",")],
+                                             dim=3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["w"], float(iters.mean()), args.cpu_sample)
     print(json.dumps(out), flush=True)

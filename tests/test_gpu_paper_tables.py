@@ -33,9 +33,13 @@ PRINTED = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))
 LARGEST = max(max(v) for fam in workloads.PAPER_FIELDS for v in PRINTED[fam].values())
 
 
+PRINTED3 = json.load(open(os.path.join(GOLDEN, "paper_iterations_3d.json")))
+LARGEST3 = max(max(v) for fam in workloads.PAPER_FIELDS for v in PRINTED3[fam].values())
+
+
 @functools.lru_cache(maxsize=None)
-def _oracle(field, n):
-    w = workloads.paper_workload(field, n)
+def _oracle(field, n, dim=2):
+    w = workloads.paper_workload(field, n) if dim == 2 else workloads.paper_workload3d(field, n)
     P = Problem.from_workload(w)
     A = P.A()
     M = Preconditioner(P)
@@ -64,6 +68,30 @@ def test_paper_settings_iterations(field, n, prec):
         print(f"  force {'ab'[k]}: gpu {int(it[k])} oracle {its_ref[k]}", flush=True)
         assert abs(int(it[k]) - its_ref[k]) <= 1
         assert int(it[k]) <= LARGEST
+        if prec == asp.ASP_PREC_FP64:
+            b = w["f"][k] / P.scale()
+            assert np.linalg.norm(b - A @ u[k]) / np.linalg.norm(b) <= w["tol"] * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("prec", [asp.ASP_PREC_FP64, asp.ASP_PREC_FP32])
+@pytest.mark.parametrize("n", [23, 31])
+@pytest.mark.parametrize("field", list(workloads.PAPER_FIELDS))
+def test_paper_3d_settings_iterations(field, n, prec):
+    """Section 4.2's settings (eta = 9h, eta_aux = 5h, b = 4) at reduced n: the
+    GPU count equals the oracle's within 1 and stays within Tables 4-6."""
+    print(f"paper 3D settings {field} n={n} prec={prec}", flush=True)
+    w, P, A, its_ref = _oracle(field, n, 3)
+    f = torch.from_numpy(w["f"]).cuda()
+    with asp.Plan(3, w["c"], w["omega"], n, w["b"], w["gamma"], C=w["C"], prec=prec,
+                  pml_aux=w["gamma_aux"]) as plan:
+        u, it, rr, st = plan.gmres(f, tol=w["tol"], restart=w["restart"], maxit=100)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()
+    assert st == asp.ASP_OK
+    for k in range(2):
+        print(f"  force {'ab'[k]}: gpu {int(it[k])} oracle {its_ref[k]}", flush=True)
+        assert abs(int(it[k]) - its_ref[k]) <= 1
+        assert int(it[k]) <= LARGEST3
         if prec == asp.ASP_PREC_FP64:
             b = w["f"][k] / P.scale()
             assert np.linalg.norm(b - A @ u[k]) / np.linalg.norm(b) <= w["tol"] * (1 + 1e-9)

@@ -68,6 +68,24 @@ def test_thin_auxiliary_pml_keeps_the_iteration_band():
         assert rr <= w["tol"] and 1 <= it <= largest
 
 
+@pytest.mark.parametrize("field", list(workloads.PAPER_FIELDS))
+def test_paper_3d_workloads_within_printed_band(field):
+    """The 3D paper-settings problems (eta = 9h, eta_aux = 5h, b = 4) of every
+    field and both forces at n = 23 stay within the largest count printed in
+    Tables 4-6."""
+    table = json.load(open(os.path.join(GOLDEN, "paper_iterations_3d.json")))
+    largest = max(max(v) for fam in ("lens", "waveguide", "random") for v in table[fam].values())
+    w = workloads.paper_workload3d(field, 23)
+    P = Problem.from_workload(w)
+    A = P.A()
+    M = Preconditioner(P)
+    for k in range(2):
+        b = w["f"][k] / P.scale()
+        x, it, rr, _ = gmres(lambda v: A @ v, M.apply, b, w["tol"], w["restart"], 100)
+        assert rr <= w["tol"]
+        assert 1 <= it <= largest, (field, k, it)
+
+
 def test_single_layer_is_exact():
     n, gamma = 20, 6
     P = Problem(2, n, 2 * math.pi * 2, gamma, 25.0, 20, 1.0 + 0.1 * np.random.default_rng(1).random((n, n)))

@@ -20,8 +20,10 @@ from .fields import (  # noqa: F401
     gaussian_source,
     wave_packet,
     paper_workload,
+    paper_workload3d,
     PAPER_FIELDS,
     PAPER_SIZES,
+    PAPER_SIZES_3D,
     seeded_centres,
     workload,
     WORKLOADS,

@@ -13,6 +13,10 @@ waveguide, a random field) only as figures and gives no formulas for them
               mapped affinely so that min -> 0.8 and max -> 1.2
 * waveguide (2D): c = (4/3) (1 - 0.5 exp(-32 (x1 - 1/2)^2)), a slow channel
               along x2 (the vertical axis of the paper's figures)
+* paper 3D fields: lens c = (4/3) (1 - 0.5 exp(-32 |x - (1/2, 1/2, 1/2)|^2)),
+              waveguide c = (4/3) (1 - 0.5 exp(-32 ((x1 - 1/2)^2 + (x2 - 1/2)^2)))
+              (a slow channel along x3), random as above with a correlation
+              width of (n + 1) / 16 cells
 * source:     f = exp(-(4 omega / pi)^2 |x - x0|^2), a Gaussian point source
               whose width shrinks with the wavelength.
 * packet:     f = exp(-|x - x0|^2 / (2 lambda^2)) exp(i omega d.(x - x0)) with
@@ -149,6 +153,38 @@ def paper_workload(field, n):
     fb = wave_packet(n, 2, w, (0.125, 0.125), (s2, s2))
     f = np.stack([flat(fa).astype(np.complex128), flat(fb).astype(np.complex128)])
     spec.update(c=c, f=f, name=f"paper2d_{field}_n{n}")
+    return spec
+
+
+# The settings of the paper's 3D experiments (Section 4.2): boundary PML
+# gamma = 9, auxiliary PML gamma_aux = 5, layers of b = 4 lines, 8 points per
+# wavelength, GMRES(40) to 1e-3.  Force (a): a Gaussian point source at
+# (1/2, 1/2, 1/4); force (b): a wave packet at (1/2, 1/4, 1/4) travelling along
+# (0, 1, 1) / sqrt 2.
+PAPER_3D = dict(d=3, gamma=9, gamma_aux=5, C=25.0, b=4, restart=40, tol=1e-3)
+PAPER_SIZES_3D = (39, 79)
+
+
+def paper_workload3d(field, n):
+    """A problem of the paper's 3D experiments (Tables 4-6) with the field
+    ``field`` in PAPER_FIELDS on an n^3 grid; same keys as ``workload``."""
+    spec = dict(PAPER_3D, n=n, nrhs=2, omega=2 * math.pi * (n + 1) / 8, velocity=field)
+    x1, x2, x3 = grid_coords(n, 3)
+    if field == "lens":
+        c = (4.0 / 3.0) * (1.0 - 0.5 * np.exp(-32.0 * ((x1 - 0.5) ** 2 + (x2 - 0.5) ** 2 +
+                                                        (x3 - 0.5) ** 2)))
+    elif field == "waveguide":
+        c = (4.0 / 3.0) * (1.0 - 0.5 * np.exp(-32.0 * ((x1 - 0.5) ** 2 + (x2 - 0.5) ** 2)))
+    elif field == "random":
+        c = velocity_random(n, 3, 3, width=(n + 1) / 16.0)
+    else:
+        raise ValueError(f"unknown paper field {field!r}")
+    w = spec["omega"]
+    fa = gaussian_source(n, 3, w, (0.5, 0.5, 0.25))
+    s2 = 1.0 / math.sqrt(2.0)
+    fb = wave_packet(n, 3, w, (0.5, 0.25, 0.25), (0.0, s2, s2))
+    f = np.stack([flat(fa).astype(np.complex128), flat(fb).astype(np.complex128)])
+    spec.update(c=c, f=f, name=f"paper3d_{field}_n{n}")
     return spec
 
 
