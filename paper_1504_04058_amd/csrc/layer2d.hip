@@ -488,8 +488,11 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
         if (rowv[e] && row[e] == jout) jsel = e;
+    // boundary maps in row tiles of 16: entry (row r, column c) at (r / 16) n 16 +
+    // 16 c + r % 16, so that a sweep workgroup's 16 rows are one contiguous run
     cplx<T>* const Tbase = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off;
-    cplx<T>* const Tp = (valid && jsel >= 0) ? Tbase + (long long)slot * n : nullptr;
+    const bool tkeep = valid && jsel >= 0;
+    auto tidx = [&](int k) { return ((long long)((k - 1) >> 4) * n + slot) * 16 + ((k - 1) & 15); };
     bool keep[4];
     zd* gout[4];
 #pragma unroll
@@ -509,16 +512,16 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         boff[e] = grid_out ? ((keep[e] && !stgd[e])
                                   ? (unsigned)(((long long)rid * N + (long long)n * (lcl[e] - 1)) * 16)
                                   : BUF_OOB)
-                           : (Tp ? (unsigned)((long long)slot * n * sizeof(cplx<T>)) : BUF_OOB);
+                           : BUF_OOB;   // OUT_LINE offsets are formed per step
     auto emit = [&](int k, const cplx<T> (&v)[4], const zd (&av)[4]) {
         if (!grid_out) {
             cplx<T> x = v[0];
 #pragma unroll
             for (int e = 1; e < 4; ++e) x = csel(jsel == e, v[e], x);
             if (bufo)
-                buf_store(rs, boff[0] + (unsigned)(k - 1) * (unsigned)sizeof(cplx<T>), x);
+                buf_store(rs, tkeep ? (unsigned)(tidx(k) * sizeof(cplx<T>)) : BUF_OOB, x);
             else
-                *(Tp ? Tp + (k - 1) : sinkT) = x;
+                *(tkeep ? Tbase + tidx(k) : sinkT) = x;
             return;
         }
         if constexpr (INM != IN_UNIT) {
@@ -647,6 +650,20 @@ struct SweepArgs {
     long long N;
 };
 
+// complex 16 x 16 FP32 accumulator of the three-product (Gauss) form
+struct KTile3 {
+    f32x4 p1, p2, p3;
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) p1[v] = p2[v] = p3[v] = 0.f;
+    }
+};
+__device__ __forceinline__ void kmac3(KTile3& c, zf a, zf b) {
+    c.p1 = Mfma<float>::mac(a.x + a.y, b.x, c.p1);
+    c.p2 = Mfma<float>::mac(a.x, b.y - b.x, c.p2);
+    c.p3 = Mfma<float>::mac(a.y, b.x + b.y, c.p3);
+}
+
 constexpr int SW_ROWS = 16;    // output rows (i1) per block: one matrix-core tile
 constexpr int SW_RT = 32;      // right-hand sides per block: two tiles
 constexpr int SW_W = 8;        // wavefronts per block, splitting the columns of T
@@ -670,12 +687,20 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
     const cplx<T>* __restrict__ Tm = reinterpret_cast<const cplx<T>*>(a.T) + a.t_off[side];
     const cplx<T>* __restrict__ Wi = reinterpret_cast<const cplx<T>*>(a.Wt_in[side]);
     const int ws = a.ws;
-    const int kr = min(k0 + li, n - 1);               // rows past n repeat the last (not stored)
+    // this block's 16 rows of T: one contiguous run of row-tile blockIdx.x (rows
+    // past n are padding, their outputs are not stored)
+    const cplx<T>* __restrict__ Tt = Tm + (long long)blockIdx.x * n * 16 + li;
     const int per = (n + 16 * SW_W - 1) / (16 * SW_W) * 16;
     const int cb = wv * per;
+    // FP32: three real products per complex one (p1 = (ar + ai) br,
+    // p2 = ar (bi - br), p3 = ai (br + bi); re = p1 - p3, im = p1 + p2), the
+    // matrix-core work of the step down by a quarter; FP64: the four products
+    KTile3 kacc[2];
     CTile<T> acc[2];
     acc[0].zero();
     acc[1].zero();
+    kacc[0].zero();
+    kacc[1].zero();
     // operands of 4 k-steps (16 columns); the next batch is loaded before the
     // current batch's products
     struct Batch {
@@ -686,7 +711,7 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
         for (int u = 0; u < 4; ++u) {
             const int c = c0 + 4 * u + lk;
             const int cc = min(c, n - 1);
-            B.av[u] = Tm[(long long)cc * n + kr];
+            B.av[u] = Tt[(long long)cc * 16];
 #pragma unroll
             for (int t2 = 0; t2 < 2; ++t2) B.bv[u][t2] = Wi[(long long)cc * ws + s0 + 16 * t2 + li];
             if (c >= n) B.av[u] = mk<T>(T(0), T(0));
@@ -699,8 +724,22 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int t2 = 0; t2 < 2; ++t2) cmac(acc[t2], cur.av[u], cur.bv[u][t2]);
+            for (int t2 = 0; t2 < 2; ++t2) {
+                if constexpr (sizeof(T) == 4)
+                    kmac3(kacc[t2], cur.av[u], cur.bv[u][t2]);
+                else
+                    cmac(acc[t2], cur.av[u], cur.bv[u][t2]);
+            }
         cur = nxt;
+    }
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                acc[t2].re[v] = kacc[t2].p1[v] - kacc[t2].p3[v];
+                acc[t2].im[v] = kacc[t2].p1[v] + kacc[t2].p2[v];
+            }
     }
 #pragma unroll
     for (int t2 = 0; t2 < 2; ++t2)

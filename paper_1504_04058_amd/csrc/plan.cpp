@@ -234,10 +234,11 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
             d.LR = (d.kind == ASP_SUB_M) ? P->LR_M : P->LR_RL;
             d.B = 0;
             fac_off += (long long)n * d.L * d.LR;
-            // the sweeps step through R_p and L_p for 1 < p < m with their dense maps
+            // the sweeps step through R_p and L_p for 1 < p < m with their dense
+            // maps, stored in row tiles of 16 (rows padded to a multiple of 16)
             if (d.kind != ASP_SUB_M && d.p > 1 && d.p < P->m) {
                 d.tr_off = tr_off;
-                tr_off += (long long)n * n;
+                tr_off += (long long)((n + 15) / 16 * 16) * n;
             }
         } else {
             // dense x1-blocks of n L unknowns, padded to a multiple of 64

@@ -169,7 +169,7 @@ def test_planned_factor_bytes(dim, n, b, gamma, prec):
                 LR = 16 if max(Ls) <= 16 else 32
                 want += n * L * LR
                 if kind != "M" and 1 < s.p < m:
-                    want += n * n
+                    want += -(-n // 16) * 16 * n     # boundary map, rows padded to 16
             else:
                 B = -(-n * L // 64) * 64
                 want += n * B * B
