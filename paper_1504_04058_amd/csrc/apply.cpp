@@ -81,7 +81,8 @@ double factor_bytes_of(const asp_plan* P, const SubDesc& d) {
 // ---------------------------------------------------------------------------
 // timing
 // ---------------------------------------------------------------------------
-KTimer::KTimer(asp_plan* p, int c, double bytes, double flops) : P(p), cls(c), on(p->timing) {
+KTimer::KTimer(asp_plan* p, int c, double bytes, double flops, int launches)
+    : P(p), cls(c), on(p->timing) {
     if (!on) return;
     if (P->tpool_used + 2 > P->tpool.size()) {
         for (int k = 0; k < 64; ++k) {
@@ -94,14 +95,14 @@ KTimer::KTimer(asp_plan* p, int c, double bytes, double flops) : P(p), cls(c), o
         }
     }
     hipEvent_t a = P->tpool[P->tpool_used++], b = P->tpool[P->tpool_used++];
-    P->tev[cls].push_back({a, b});
+    P->tev[cls].push_back({a, b, launches});
     P->tbytes[cls] += bytes;
     P->tflops[cls] += flops;
     (void)hipEventRecord(a, P->stream);
 }
 
 void KTimer::end() {
-    if (on) (void)hipEventRecord(P->tev[cls].back().second, P->stream);
+    if (on) (void)hipEventRecord(P->tev[cls].back().b, P->stream);
     on = false;
 }
 
@@ -124,12 +125,14 @@ extern "C" asp_status asp_timing_read(asp_plan* P, int cls, int* launches, doubl
     if (!P || cls < 0 || cls >= ASP_K_COUNT) return ASP_ERR_ARG;
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     double tot = 0;
-    for (auto& pr : P->tev[cls]) {
+    int nl = 0;
+    for (auto& sp : P->tev[cls]) {
         float t = 0;
-        ASP_HIP(P, hipEventElapsedTime(&t, pr.first, pr.second));
+        ASP_HIP(P, hipEventElapsedTime(&t, sp.a, sp.b));
         tot += t;
+        nl += sp.launches;
     }
-    if (launches) *launches = (int)P->tev[cls].size();
+    if (launches) *launches = nl;
     if (ms) *ms = tot;
     if (bytes) *bytes = P->tbytes[cls];
     if (flops) *flops = P->tflops[cls];
@@ -201,20 +204,19 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
     }
     if (m == 1) return ASP_OK;
     // the two sweeps: the boundary values u~^R_{p,1:p} and u~^L_{p,p:m}
-    // accumulated layer by layer (W rows hold the data entering R_p / L_p)
+    // accumulated layer by layer (W rows hold the data entering R_p / L_p); the
+    // seed and the m-2 steps are timed as one span of m-1 launches
     {
+        const double esz = elem_bytes(P);
+        const double nn = (double)P->n * P->n;
+        const double steps = m - 2;
+        KTimer t(P, ASP_K_SWEEP,
+                 4.0 * nact * P->n * sizeof(zd) + steps * (2.0 * nn * esz + 6.0 * nact * P->n * sizeof(zd)),
+                 steps * 2.0 * nn * nact * 8.0, m - 1);
         const long long rowR = (long long)P->wrow(P->idx_R(2)) * w_rhs * P->n;
         const long long rowL = (long long)P->wrow(P->idx_L(m - 1)) * w_rhs * P->n;
-        KTimer t(P, ASP_K_SWEEP, 4.0 * nact * P->n * sizeof(zd), 0.0);
         ASP_HIP(P, launch_sweep_seed(P, P->d_W, rowR, rowL, act, nact, st));
-        t.end();
-    }
-    const double esz = elem_bytes(P);
-    for (int s = 1; s <= m - 2; ++s) {
-        const double nn = (double)P->n * P->n;
-        KTimer t(P, ASP_K_SWEEP, 2.0 * nn * esz + 6.0 * nact * P->n * sizeof(zd),
-                 2.0 * nn * nact * 8.0);
-        ASP_HIP(P, launch_sweep_step(P, s, P->d_W, w_rhs, act, nact, st));
+        for (int s = 1; s <= m - 2; ++s) ASP_HIP(P, launch_sweep_step(P, s, P->d_W, w_rhs, act, nact, st));
         t.end();
     }
     // u~_p = u~_{p,1:p-1} + u~_{p,p} + u~_{p,p+1:m}: one launch of every R_p

@@ -181,7 +181,11 @@ struct asp_plan {
 
     // per-kernel-class timing (asp_timing_enable / asp_timing_read)
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[ASP_K_COUNT];
+    struct TimedSpan {
+        hipEvent_t a, b;
+        int launches;        // kernel launches between the two events
+    };
+    std::vector<TimedSpan> tev[ASP_K_COUNT];
     std::vector<hipEvent_t> tpool;
     size_t tpool_used = 0;
     double tbytes[ASP_K_COUNT] = {0};
@@ -316,7 +320,10 @@ struct KTimer {
     asp_plan* P;
     int cls;
     bool on;
-    KTimer(asp_plan* p, int c, double bytes, double flops);
+    // one event pair around `launches` launches of class c (a chain of
+    // dependent launches is timed as one span: an event per launch would add
+    // its own gap to every step of the chain)
+    KTimer(asp_plan* p, int c, double bytes, double flops, int launches = 1);
     void end();
 };
 
