@@ -10,11 +10,14 @@ namespace {
 constexpr int BS = 256;
 constexpr int CHUNK = 8;   // Krylov vectors per multi-dot / multi-axpy pass
 
-// y = A x for the symmetric form.  One thread per grid point; the stencil
-// coefficients are formed once from the 1D PML tables and omega^2/c^2 and used
-// for every right-hand side.
+// y = A x for the symmetric form.  2D: a thread walks SEG2 consecutive lines
+// i2 at one i1, keeping x on lines i2-1, i2, i2+1 in registers (each value is
+// read from memory once; the i1 neighbours come from the cache).  The stencil
+// coefficients are formed from the 1D PML tables and omega^2/c^2:
 //   coupling along axis a at the half line t+1/2:  s(t+1/2) / (h^2 prod_{b != a} s(i_b))
 //   diagonal: -(sum of the couplings) + omega^2 / (c^2 prod_b s(i_b))
+constexpr int SEG2 = 8;
+
 __global__ __launch_bounds__(BS) void stencil2d_kernel(const zd* __restrict__ x,
                                                      zd* __restrict__ y,
                                                      const int* __restrict__ act,
@@ -22,22 +25,32 @@ __global__ __launch_bounds__(BS) void stencil2d_kernel(const zd* __restrict__ x,
                                                      const double* __restrict__ ksq, int n,
                                                      long long N) {
     const int i1 = blockIdx.x * BS + threadIdx.x;
-    const int i2 = blockIdx.y;
+    const int i2a = blockIdx.y * SEG2;
     if (i1 >= n) return;
     const int rhs = act ? act[blockIdx.z] : (int)blockIdx.z;
-    const long long idx = (long long)i2 * n + i1;
-    const zd ce = ax.sh[i1 + 1] * ax.inv_sh2[i2];
-    const zd cw = ax.sh[i1] * ax.inv_sh2[i2];
-    const zd cn = ax.sh[i2 + 1] * ax.inv_sh2[i1];
-    const zd cs = ax.sh[i2] * ax.inv_sh2[i1];
-    const zd dg = (ksq[idx] * ax.inv_s[i1]) * ax.inv_s[i2] - (ce + cw + cn + cs);
     const zd* xr = x + (long long)rhs * N;
-    zd acc = dg * xr[idx];
-    if (i1 + 1 < n) acc = cfma(ce, xr[idx + 1], acc);
-    if (i1 > 0) acc = cfma(cw, xr[idx - 1], acc);
-    if (i2 + 1 < n) acc = cfma(cn, xr[idx + n], acc);
-    if (i2 > 0) acc = cfma(cs, xr[idx - n], acc);
-    y[(long long)rhs * N + idx] = acc;
+    zd* yr = y + (long long)rhs * N;
+    const zd sh_e = ax.sh[i1 + 1], sh_w = ax.sh[i1], is2_1 = ax.inv_sh2[i1], is_1 = ax.inv_s[i1];
+    zd xm = (i2a > 0) ? xr[(long long)(i2a - 1) * n + i1] : mk(0.0, 0.0);
+    zd xc = xr[(long long)i2a * n + i1];
+    const int i2e = min(i2a + SEG2, n);
+    for (int i2 = i2a; i2 < i2e; ++i2) {
+        const long long idx = (long long)i2 * n + i1;
+        const zd xp = (i2 + 1 < n) ? xr[idx + n] : mk(0.0, 0.0);
+        const zd ce = sh_e * ax.inv_sh2[i2];
+        const zd cw = sh_w * ax.inv_sh2[i2];
+        const zd cn = ax.sh[i2 + 1] * is2_1;
+        const zd cs = ax.sh[i2] * is2_1;
+        const zd dg = (ksq[idx] * is_1) * ax.inv_s[i2] - (ce + cw + cn + cs);
+        zd acc = dg * xc;
+        if (i1 + 1 < n) acc = cfma(ce, xr[idx + 1], acc);
+        if (i1 > 0) acc = cfma(cw, xr[idx - 1], acc);
+        if (i2 + 1 < n) acc = cfma(cn, xp, acc);
+        if (i2 > 0) acc = cfma(cs, xm, acc);
+        yr[idx] = acc;
+        xm = xc;
+        xc = xp;
+    }
 }
 
 __global__ __launch_bounds__(BS) void stencil3d_kernel(const zd* __restrict__ x,
@@ -314,7 +327,7 @@ hipError_t launch_stencil(const asp_plan* P, const zd* x, zd* y, const int* act,
     if (nact <= 0) return hipSuccess;
     const int n = P->n;
     if (P->dim == 2) {
-        dim3 grid((n + BS - 1) / BS, n, nact);
+        dim3 grid((n + BS - 1) / BS, (n + SEG2 - 1) / SEG2, nact);
         hipLaunchKernelGGL(stencil2d_kernel, grid, dim3(BS), 0, st, x, y, act, axis_of(P), P->d_ksq,
                            n, P->N);
     } else {
