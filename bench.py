@@ -71,6 +71,10 @@ def parse():
                          "(e.g. 127,255,511,1023,2047); '' for none")
     ap.add_argument("--paper-tables3d", default="",
                     help="grid sizes of the paper's 3D experiments to run (e.g. 39,79); '' for none")
+    ap.add_argument("--paper-widths", default="",
+                    help="NARROW:WIDE: run the 2D paper tables also with unequal layers of NARROW "
+                         "or WIDE lines, wide where the velocity varies along the sweep axis "
+                         "(workloads.variation_widths); '' for equal widths only")
     return ap.parse_args()
 
 
@@ -289,12 +293,13 @@ def serving_run(count, prec_name):
     return summ
 
 
-def paper_tables(prec_name, sizes, dim=2):
+def paper_tables(prec_name, sizes, dim=2, widths=None):
     """The paper's experiments (Tables 1-3 of Section 3.2 in 2D, Tables 4-6 of
     Section 4.2 in 3D) on this path: per field and grid, the factorization
     time, the GMRES(40) iterations to 1e-3 for force (a) point source and (b)
     wave packet (solved as one batch of two right-hand sides) and the solve
-    time, beside the printed iteration counts."""
+    time, beside the printed iteration counts.  widths = (narrow, wide): every
+    problem once more with unequal layer widths from workloads.variation_widths."""
     import json as _json
 
     import torch
@@ -314,22 +319,36 @@ def paper_tables(prec_name, sizes, dim=2):
             w = workloads.paper_workload(field, n) if dim == 2 else workloads.paper_workload3d(field, n)
             f = torch.from_numpy(w["f"]).cuda()
             u = torch.empty_like(f)
-            with asp.Plan(dim, w["c"], w["omega"], n, w["b"], w["gamma"], C=w["C"], prec=prec,
-                          pml_aux=w.get("gamma_aux", 0)) as plan:
-                torch.cuda.synchronize()
-                a = time.perf_counter()
-                plan.factor()
-                torch.cuda.synchronize()
-                b = time.perf_counter()
-                st, iters, relres = asp.asp_gmres(plan.handle, f, u, 2, w["tol"], w["restart"], 200)
-                torch.cuda.synchronize()
-                c = time.perf_counter()
-            rows.append({"n": n, "omega_over_2pi": (n + 1) / 8, "field": field,
-                         "setup_ms": (b - a) * 1e3, "solve_ms": (c - b) * 1e3,
-                         "iters": [int(i) for i in iters], "max_relres": float(max(relres)),
-                         "status": asp.STATUS_NAMES.get(st, st),
-                         "paper_iters": None if col is None else
-                         [printed[field]["force_a"][col], printed[field]["force_b"][col]]})
+            layouts = [w["b"]]
+            if widths:
+                layouts.append(workloads.variation_widths(w["c"], w["gamma"], *widths))
+            for lb in layouts:
+                with asp.Plan(dim, w["c"], w["omega"], n, lb, w["gamma"], C=w["C"], prec=prec,
+                              pml_aux=w.get("gamma_aux", 0)) as plan:
+                    torch.cuda.synchronize()
+                    a = time.perf_counter()
+                    plan.factor()
+                    torch.cuda.synchronize()
+                    b = time.perf_counter()
+                    st, iters, relres = asp.asp_gmres(plan.handle, f, u, 2, w["tol"], w["restart"],
+                                                      200)
+                    torch.cuda.synchronize()
+                    c0 = time.perf_counter()
+                    # again with the workspaces allocated: the steady-state solve time
+                    st, iters, relres = asp.asp_gmres(plan.handle, f, u, 2, w["tol"], w["restart"],
+                                                      200)
+                    torch.cuda.synchronize()
+                    c = time.perf_counter()
+                    m = asp.asp_info(plan.handle)["m"]
+                rows.append({"n": n, "omega_over_2pi": (n + 1) / 8, "field": field,
+                             "layers": "equal" if isinstance(lb, int) else
+                             f"variation {widths[0]}/{widths[1]}", "m": m,
+                             "setup_ms": (b - a) * 1e3, "first_solve_ms": (c0 - b) * 1e3,
+                             "solve_ms": (c - c0) * 1e3,
+                             "iters": [int(i) for i in iters], "max_relres": float(max(relres)),
+                             "status": asp.STATUS_NAMES.get(st, st),
+                             "paper_iters": None if col is None else
+                             [printed[field]["force_a"][col], printed[field]["force_b"][col]]})
             del f, u
             torch.cuda.empty_cache()
     settings = ("gamma 9, b 8, C 25, 8 points per wavelength, GMRES(40) to 1e-3, "
@@ -402,7 +421,9 @@ def main():
     if args.serve_requests > 0:
         out["serving"] = serving_run(args.serve_requests, args.prec)
     if args.paper_tables:
-        out["paper_tables"] = paper_tables(args.prec, [int(x) for x in args.paper_tables.split(",")])
+        out["paper_tables"] = paper_tables(args.prec, [int(x) for x in args.paper_tables.split(",")],
+                                           widths=[int(x) for x in args.paper_widths.split(":")]
+                                           if args.paper_widths else None)
     if args.paper_tables3d:
         out["paper_tables3d"] = paper_tables(args.prec, [int(x) for x in args.paper_tables3d.split(",")],
                                              dim=3)

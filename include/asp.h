@@ -77,6 +77,15 @@ typedef struct {
                        remarks, eta_aux = pml_aux * h.  Pads at the domain boundary keep
                        the boundary PML.  0 (default): pml_eta; otherwise 2..pml_eta,
                        else ASP_ERR_ARG */
+    int n_layers;   /* 0 (default): layers of layer_b physical lines each, the last one
+                       holding the remainder.  > 0: arbitrary layer widths (Section 3.1
+                       remarks: the layers need not have equal widths); layer_widths
+                       then holds n_layers widths and layer_b is ignored */
+    const int* layer_widths;  /* HOST pointer, n_layers entries: physical grid lines of
+                       layer p = 1..m along the sweep axis, each >= 1, summing to
+                       n - 2(pml_eta - 1); read during asp_setup only, not kept.
+                       Layer 1 also takes the pml_eta - 1 PML lines below it, layer m
+                       those above it.  Violations: ASP_ERR_ARG */
 } asp_opts;
 
 typedef struct {
@@ -102,7 +111,8 @@ void asp_default_opts(asp_opts* opts);
  *            copied, the caller may free it on return.
  *   omega    angular frequency, > 0.
  *   n        interior points per side; n - 2(pml_eta - 1) >= 1.
- *   layer_b  grid lines per interior layer (Section 2, b), >= 1.
+ *   layer_b  grid lines per interior layer (Section 2, b), >= 1; ignored when
+ *            opts->n_layers > 0 (arbitrary widths).
  *   pml_eta  PML width in grid units (eta = pml_eta * h, Section 2), >= 2.
  *   opts     NULL for defaults.
  * Only host work and uploads of small tables; no factorization.

@@ -73,13 +73,15 @@ class Problem:
     """The discretized problem of Section 1 with PML on all sides.
 
     d, n, omega as in the paper; gamma is the PML width in grid units
-    (eta = gamma*h); C the PML constant; b the lines per interior layer;
+    (eta = gamma*h); C the PML constant; b the lines per interior layer, or a
+    list of physical lines per layer (arbitrary widths, Section 3.1 remarks);
     c the velocity on the (n,)*d grid (first index = x1); gamma_aux the width of
     the auxiliary PML pads facing neighbouring layers (None: gamma)."""
 
     def __init__(self, d, n, omega, gamma, C, b, c, pml_axes="all", gamma_aux=None):
         self.d, self.n, self.omega = int(d), int(n), float(omega)
-        self.gamma, self.C, self.b = int(gamma), float(C), int(b)
+        self.gamma, self.C = int(gamma), float(C)
+        self.b = int(b) if isinstance(b, (int, np.integer)) else tuple(int(x) for x in b)
         self.gamma_aux = self.gamma if gamma_aux is None else int(gamma_aux)
         self.h = 1.0 / (self.n + 1)
         c = np.asarray(c, dtype=np.float64).reshape((self.n,) * self.d)

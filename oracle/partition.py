@@ -17,6 +17,15 @@ lines and the last b+gamma-2):
 so the last layer holds r = n_phys - (m-1)b in [1, b] physical lines plus the
 g PML lines; with n = 2*gamma + m*b - 2 this is exactly the paper's partition.
 
+Arbitrary layer widths (Section 3.1 remarks: the subdomains need not have the
+same width): b may instead be a list (w_1, ..., w_m) of physical lines per
+layer, each >= 1, summing to n_phys.  With t_p = gamma + w_1 + ... + w_{p-1}
+the first physical line of layer p,
+
+    X_1 = [1, t_2 - 1],  X_p = [t_p, t_{p+1} - 1] (1<p<m),  X_m = [t_m, n];
+
+the uniform rule is the list (b, ..., b, r).
+
 Extended grids and the zero regions of their sweep-axis PML profiles
 (Section 2.1 definitions of D^M_q, X^M_q, sigma^M_q, D^R_p, X^R_p, sigma^R_p,
 D^L_p, X^L_p, sigma^L_p; the same sets in 2D and 3D):
@@ -38,6 +47,8 @@ gamma_aux = gamma every pad is as above.
 """
 from dataclasses import dataclass
 
+import numpy as np
+
 
 @dataclass(frozen=True)
 class Sub:
@@ -56,22 +67,34 @@ class Sub:
 
 
 def check_args(n, b, gamma):
-    if gamma < 2 or b < 1 or n - 2 * (gamma - 1) < 1:
-        raise ValueError(f"invalid partition n={n} b={b} gamma={gamma}")
+    widths(n, b, gamma)
+
+
+def widths(n, b, gamma):
+    """Physical lines (w_1, ..., w_m) of the layers: the uniform rule for an
+    integer b, else b itself after checking it."""
+    if gamma < 2 or n - 2 * (gamma - 1) < 1:
+        raise ValueError(f"invalid partition n={n} gamma={gamma}")
+    n_phys = n - 2 * (gamma - 1)
+    if isinstance(b, (int, np.integer)):
+        if b < 1:
+            raise ValueError(f"invalid layer width b={b}")
+        m = -(-n_phys // b)
+        return [int(b)] * (m - 1) + [n_phys - (m - 1) * int(b)]
+    w = [int(x) for x in b]
+    if not w or min(w) < 1 or sum(w) != n_phys:
+        raise ValueError(f"layer widths {w} must be >= 1 and sum to n_phys = {n_phys}")
+    return w
 
 
 def layers(n, b, gamma):
     """[(s_p, e_p)] for p = 1..m."""
-    check_args(n, b, gamma)
-    g = gamma - 1
-    n_phys = n - 2 * g
-    m = -(-n_phys // b)
-    if m == 1:
-        return [(1, n)]
-    X = [(1, g + b)]
-    for p in range(2, m):
-        X.append((gamma + (p - 1) * b, gamma + p * b - 1))
-    X.append((gamma + (m - 1) * b, n))
+    w = widths(n, b, gamma)
+    m = len(w)
+    X, t = [], gamma
+    for p in range(m):
+        X.append((1 if p == 0 else t, n if p == m - 1 else t + w[p] - 1))
+        t += w[p]
     return X
 
 

@@ -32,7 +32,8 @@ class AspError(RuntimeError):
 
 class asp_opts(ctypes.Structure):
     _fields_ = [("C", ctypes.c_double), ("prec", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("host_only", ctypes.c_int), ("pml_aux", ctypes.c_int)]
+                ("host_only", ctypes.c_int), ("pml_aux", ctypes.c_int),
+                ("n_layers", ctypes.c_int), ("layer_widths", ctypes.POINTER(ctypes.c_int))]
 
 
 class asp_plan_info(ctypes.Structure):
@@ -119,15 +120,22 @@ def _current_stream():
 def asp_setup(dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64, stream=None,
               host_only=False, pml_aux=0):
     """Returns a plan handle (ctypes.c_void_p).  c: host array, n**dim velocities
-    (column-major, i.e. numpy order='F' flattening of an (n,)*dim array)."""
+    (column-major, i.e. numpy order='F' flattening of an (n,)*dim array).
+    layer_b: lines per layer, or a sequence of physical lines per layer
+    (arbitrary widths: opts.n_layers / opts.layer_widths)."""
     c = np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(-1, order="F")
                              if np.asarray(c).ndim > 1 else np.asarray(c, dtype=np.float64))
     opts = asp_opts(C, prec, stream if stream is not None else
                     (ctypes.c_void_p(0) if host_only else _current_stream()), int(host_only),
-                    int(pml_aux or 0))
+                    int(pml_aux or 0), 0, None)
+    if not isinstance(layer_b, (int, np.integer)):
+        widths = (ctypes.c_int * len(layer_b))(*[int(w) for w in layer_b])
+        opts.n_layers = len(layer_b)
+        opts.layer_widths = widths
+        layer_b = 0
     plan = ctypes.c_void_p()
     st = lib().asp_setup(ctypes.byref(plan), dim, c.ctypes.data_as(ctypes.c_void_p), omega, n,
-                         layer_b, pml_eta, ctypes.byref(opts))
+                         int(layer_b), pml_eta, ctypes.byref(opts))
     if st != ASP_OK:
         msg = asp_last_error(plan)
         asp_destroy(plan)

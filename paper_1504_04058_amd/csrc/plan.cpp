@@ -4,6 +4,7 @@
 // eq. (1D)), the descriptors of the 3m-2 auxiliary problems and their upload.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -63,20 +64,18 @@ zd to_zd(cd v) { return mk(v.real(), v.imag()); }
 }  // namespace
 
 // Partition along the sweep axis (1-based lines).  g = gamma - 1 lines carry
-// sigma > 0 in each boundary PML; n_phys = n - 2g physical lines are cut into
-// m = ceil(n_phys / b) layers: X_1 = [1, g+b], X_p = [gamma+(p-1)b, gamma+pb-1],
-// X_m = [gamma+(m-1)b, n] (the last one holds the r <= b remaining physical lines).
-static void build_partition(asp_plan* P) {
-    const int n = P->n, b = P->b, gamma = P->gamma, g = P->g;
-    const int n_phys = n - 2 * g;
-    const int m = (n_phys + b - 1) / b;
+// sigma > 0 in each boundary PML; the n_phys = n - 2g physical lines are cut
+// into m layers of w_1..w_m lines (uniform: m = ceil(n_phys / b) layers of b,
+// the last one holding the remainder; or the caller's widths, Section 3.1
+// remarks).  With t_p = gamma + w_1 + ... + w_{p-1}: X_1 = [1, t_2 - 1],
+// X_p = [t_p, t_{p+1} - 1], X_m = [t_m, n].
+static void build_partition(asp_plan* P, const std::vector<int>& w) {
+    const int n = P->n, m = (int)w.size();
     P->X.clear();
-    if (m == 1) {
-        P->X.push_back({1, n});
-    } else {
-        P->X.push_back({1, g + b});
-        for (int p = 2; p < m; ++p) P->X.push_back({gamma + (p - 1) * b, gamma + p * b - 1});
-        P->X.push_back({gamma + (m - 1) * b, n});
+    int t = P->gamma;
+    for (int p = 0; p < m; ++p) {
+        P->X.push_back({p == 0 ? 1 : t, p == m - 1 ? n : t + w[p] - 1});
+        t += w[p];
     }
     P->m = m;
 }
@@ -146,6 +145,8 @@ extern "C" void asp_default_opts(asp_opts* o) {
     o->stream = nullptr;
     o->host_only = 0;
     o->pml_aux = 0;
+    o->n_layers = 0;
+    o->layer_widths = nullptr;
 }
 
 extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double omega, int n,
@@ -167,8 +168,26 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (!c) return fail(ASP_ERR_ARG, "c is NULL");
     if (!(omega > 0.0) || !std::isfinite(omega)) return fail(ASP_ERR_ARG, "omega must be finite and > 0");
     if (pml_eta < 2) return fail(ASP_ERR_ARG, "pml_eta must be >= 2");
-    if (layer_b < 1) return fail(ASP_ERR_ARG, "layer_b must be >= 1");
     if (n < 1 || n - 2 * (pml_eta - 1) < 1) return fail(ASP_ERR_ARG, "n too small for the PML");
+    std::vector<int> widths;
+    const int n_phys = n - 2 * (pml_eta - 1);
+    if (o.n_layers < 0) return fail(ASP_ERR_ARG, "n_layers must be >= 0");
+    if (o.n_layers > 0) {
+        if (!o.layer_widths) return fail(ASP_ERR_ARG, "layer_widths is NULL with n_layers > 0");
+        long long sum = 0;
+        for (int p = 0; p < o.n_layers; ++p) {
+            if (o.layer_widths[p] < 1) return fail(ASP_ERR_ARG, "layer_widths must be >= 1");
+            sum += o.layer_widths[p];
+        }
+        if (sum != n_phys)
+            return fail(ASP_ERR_ARG, "layer_widths must sum to n - 2(pml_eta - 1)");
+        widths.assign(o.layer_widths, o.layer_widths + o.n_layers);
+    } else {
+        if (layer_b < 1) return fail(ASP_ERR_ARG, "layer_b must be >= 1");
+        const int m = (n_phys + layer_b - 1) / layer_b;
+        widths.assign(m, layer_b);
+        widths.back() = n_phys - (m - 1) * layer_b;
+    }
     if (o.pml_aux != 0 && (o.pml_aux < 2 || o.pml_aux > pml_eta))
         return fail(ASP_ERR_ARG, "pml_aux must be 0 or in [2, pml_eta]");
     if (!(o.C >= 0.0) || !std::isfinite(o.C)) return fail(ASP_ERR_ARG, "C must be finite and >= 0");
@@ -180,7 +199,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
 
     P->dim = dim;
     P->n = n;
-    P->b = layer_b;
+    P->b = *std::max_element(widths.begin(), widths.end());
     P->gamma = pml_eta;
     P->g = pml_eta - 1;
     P->gamma_aux = o.pml_aux ? o.pml_aux : pml_eta;
@@ -199,7 +218,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     for (long long i = 0; i < P->N; ++i)
         if (!(P->c[i] > 0.0) || !std::isfinite(P->c[i])) return fail(ASP_ERR_ARG, "c must be finite and > 0");
 
-    build_partition(P);
+    build_partition(P, widths);
     build_subproblems(P);
 
     // PML tables: the boundary profile of one axis, and the sweep-axis profile
@@ -216,7 +235,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     }
     P->max_L = std::max(maxL_M, maxL_RL);
     if (dim == 2 && P->max_L > 32) {
-        return fail(ASP_ERR_ARG, "2D auxiliary problems are limited to 32 sweep lines (b + 2(pml_eta-1) <= 32)");
+        return fail(ASP_ERR_ARG, "2D auxiliary problems are limited to 32 sweep lines (widest layer + 2(pml_eta-1) <= 32)");
     }
     P->LR_M = rows_per_wave(maxL_M);
     P->LR_RL = rows_per_wave(maxL_RL > 0 ? maxL_RL : 1);

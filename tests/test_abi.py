@@ -103,6 +103,56 @@ def test_thin_auxiliary_pml_matches_oracle(dim, n, b, gamma, aux):
     assert ei.value.status == asp.ASP_ERR_ARG and "pml_aux" in str(ei.value)
 
 
+WIDTH_CONFIGS = [(2, 40, 6, [3, 7, 1, 5, 6, 8]), (2, 127, 9, [4, 8, 16, 12, 16, 16, 8, 8, 4, 4, 6, 9]),
+                 (3, 31, 8, [1, 4, 2, 3, 7]), (2, 63, 12, [1, 1, 9, 2, 4, 8, 8, 8]), (2, 30, 5, [22])]
+
+
+@pytest.mark.parametrize("dim,n,gamma,w", WIDTH_CONFIGS)
+def test_arbitrary_layer_widths_match_oracle(dim, n, gamma, w):
+    """opts.n_layers / opts.layer_widths (Section 3.1 remarks: unequal layer
+    widths): partition bit-exact with the oracle's, sweep-axis tables to
+    rounding, and the planned factor bytes from the per-problem line counts."""
+    omega = 2 * np.pi * (n + 1) / 8
+    c = np.ones(n ** dim)
+    plan = asp.asp_setup(dim, c, omega, n, w, gamma, host_only=True, prec=asp.ASP_PREC_FP32)
+    h = 1.0 / (n + 1)
+    try:
+        layers, subs = asp.asp_layers(plan)
+        assert [tuple(r) for r in layers.tolist()] == partition.layers(n, w, gamma)
+        ref = partition.subproblems(n, w, gamma)
+        kinds = {"M": asp.ASP_SUB_M, "R": asp.ASP_SUB_R, "L": asp.ASP_SUB_L}
+        refl = [s for k in ("M", "R", "L") for s in ref[k]]
+        assert [tuple(r) for r in subs.tolist()] == \
+            [(kinds[s.kind], s.p, s.lo, s.hi, s.phi, s.psi) for s in refl]
+        for k, s in enumerate(refl):
+            s_int, s_half = asp.asp_tables(plan, k, s.hi - s.lo + 1)
+            ref_int, ref_half = pml.tables(s.lo, s.hi, s.phi, s.psi, 25.0, gamma, h, omega)
+            np.testing.assert_allclose(s_int, ref_int, rtol=4e-16, atol=0)
+            np.testing.assert_allclose(s_half, ref_half, rtol=4e-16, atol=0)
+        info = asp.asp_info(plan)
+        assert info["m"] == len(w) and info["max_lines"] == max(s.L for s in refl)
+        if dim == 2:
+            m = len(w)
+            want = 0
+            for kind in [k for k in "MRL" if ref[k]]:
+                group = ref["M"] if kind == "M" else ref["R"] + ref["L"]   # one row count per group
+                LR = 16 if max(s.L for s in group) <= 16 else 32
+                for s in ref[kind]:
+                    want += n * s.L * LR + (-(-n // 16) * 16 * n if kind != "M" and 1 < s.p < m else 0)
+            assert info["factor_bytes"] == want * 8
+    finally:
+        asp.asp_destroy(plan)
+
+
+@pytest.mark.parametrize("w,frag", [([3, 7, 1, 5, 6, 7], "sum"), ([3, 0, 28], ">= 1"),
+                                    ([31, -1], ">= 1"), ([30, 3], "32 sweep lines")])
+def test_bad_layer_widths_rejected(L, w, frag):
+    n, gamma = 40 if frag != "32 sweep lines" else 43, 6
+    with pytest.raises(asp.AspError) as ei:
+        asp.asp_setup(2, np.ones(n * n), 10.0, n, w, gamma, host_only=True)
+    assert ei.value.status == asp.ASP_ERR_ARG and frag in str(ei.value)
+
+
 @pytest.mark.parametrize("args,frag", [
     ((4, 63, 4, 12), "dim"),
     ((2, 20, 4, 12), "n too small"),

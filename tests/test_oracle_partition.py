@@ -138,3 +138,49 @@ def test_thin_auxiliary_sizes_at_the_3d_settings():
     assert all(s.L == 8 for s in subs["R"][:-1]) and all(s.L == 8 for s in subs["L"][1:])
     with pytest.raises(ValueError):
         partition.subproblems(n, 4, 9, 10)
+
+
+@pytest.mark.parametrize("n,b,gamma", [(63, 4, 12), (127, 8, 9), (100, 4, 12), (30, 8, 12),
+                                       (2 * 9 + 6 * 8 - 2, 8, 9)])
+def test_uniform_widths_list_is_the_uniform_partition(n, b, gamma):
+    """Arbitrary widths (Section 3.1 remarks) with the list (b, ..., b, r)
+    reproduce the uniform partition, whose index sets are pinned above."""
+    w = partition.widths(n, b, gamma)
+    assert w[:-1] == [b] * (len(w) - 1) and 1 <= w[-1] <= b and sum(w) == n - 2 * (gamma - 1)
+    assert partition.layers(n, w, gamma) == partition.layers(n, b, gamma)
+    for kind in "MRL":
+        assert partition.subproblems(n, w, gamma)[kind] == partition.subproblems(n, b, gamma)[kind]
+
+
+@pytest.mark.parametrize("n,gamma,w", [(40, 6, [3, 7, 1, 5, 6, 8]), (63, 12, [1, 1, 9, 2, 4, 24]),
+                                       (30, 5, [22]), (31, 9, [1, 14])])
+def test_arbitrary_layer_widths(n, gamma, w):
+    """Layers of the given physical widths tile [1, n]; layer 1 also holds the
+    lower PML, layer m the upper one; the auxiliary grids follow the same
+    definitions as for equal widths (zero regions on each layer's physical part)."""
+    g = gamma - 1
+    X = partition.layers(n, w, gamma)
+    assert len(X) == len(w) and X[0][0] == 1 and X[-1][1] == n
+    for p in range(1, len(X)):
+        assert X[p][0] == X[p - 1][1] + 1
+    for p, (s, e) in enumerate(X):
+        phi, psi = partition.physical(n, gamma, (s, e))
+        assert psi - phi + 1 == w[p]
+    assert X[0][1] - X[0][0] + 1 == w[0] + g * (1 if len(w) > 1 else 2)
+    subs = partition.subproblems(n, w, gamma)
+    m = len(X)
+    for s in subs["M"]:
+        assert (s.phi, s.psi) == partition.physical(n, gamma, X[s.p - 1])
+        assert (s.phi - s.lo, s.hi - s.psi) == (g, g)
+    for s in subs["R"]:
+        assert s.lo == X[s.p - 1][0] and s.phi == s.lo - 1
+    for s in subs["L"]:
+        assert s.hi == X[s.p - 1][1] and s.psi == s.hi + 1
+    assert len(subs["R"]) == len(subs["L"]) == m - 1
+
+
+@pytest.mark.parametrize("n,gamma,w", [(40, 6, [3, 7, 1, 5, 6, 7]), (40, 6, [3, 0, 27]),
+                                       (40, 6, []), (40, 6, [31, -1])])
+def test_bad_layer_widths(n, gamma, w):
+    with pytest.raises(ValueError):
+        partition.layers(n, w, gamma)

@@ -52,6 +52,49 @@ def test_accumulated_sweep_with_thin_auxiliary_pml(d, n, gamma, gamma_aux, b):
     assert np.linalg.norm(z1 - z2) <= 1e-12 * np.linalg.norm(z1)
 
 
+@pytest.mark.parametrize("d,n,gamma,w", [(2, 40, 6, [3, 7, 1, 5, 6, 8]), (2, 31, 5, [2, 1, 6, 4, 10]),
+                                         (3, 15, 3, [1, 4, 2, 4])])
+def test_accumulated_sweep_with_arbitrary_widths(d, n, gamma, w):
+    """Layers of unequal widths (Section 3.1 remarks): the accumulation
+    identity does not depend on the widths."""
+    rng = np.random.default_rng(n + 7)
+    c = 0.8 + 0.4 * rng.random((n,) * d)
+    P = Problem(d, n, 2 * math.pi * (n + 1) / 10, gamma, 25.0, w, c)
+    M = Preconditioner(P)
+    assert M.m == len(w)
+    f = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
+    z1, z2 = M.apply(f), M.apply_componentwise(f)
+    assert np.linalg.norm(z1 - z2) <= 1e-12 * np.linalg.norm(z1)
+
+
+def test_one_layer_of_full_width_is_exact():
+    n, gamma = 24, 5
+    P = Problem(2, n, 2 * math.pi * 2, gamma, 25.0, [n - 2 * (gamma - 1)],
+                1.0 + 0.1 * np.random.default_rng(3).random((n, n)))
+    M = Preconditioner(P)
+    assert M.m == 1
+    b = np.random.default_rng(4).standard_normal(P.N) + 0j
+    np.testing.assert_allclose(M.apply(b), direct.solve(P.A(), b), rtol=1e-10, atol=1e-14)
+
+
+def test_unequal_widths_keep_the_iteration_band():
+    """Wider layers across the lens and thinner ones elsewhere (widths 4..16
+    at gamma = 9, n = 127): GMRES(40) to 1e-3 stays within the largest count
+    printed in Tables 1-3."""
+    table = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))
+    largest = max(max(v) for fam in ("lens", "waveguide", "random") for v in table[fam].values())
+    w = workloads.paper_workload("lens", 127)
+    w["b"] = [4, 8, 16, 12, 16, 16, 8, 8, 4, 4, 6, 9]
+    assert sum(w["b"]) == 127 - 16
+    P = Problem.from_workload(w)
+    A = P.A()
+    M = Preconditioner(P)
+    for k in range(2):
+        b = w["f"][k] / P.scale()
+        x, it, rr, _ = gmres(lambda v: A @ v, M.apply, b, w["tol"], w["restart"], 100)
+        assert rr <= w["tol"] and 1 <= it <= largest
+
+
 def test_thin_auxiliary_pml_keeps_the_iteration_band():
     """eta_aux = 5h with eta = 9h (the paper's 3D choice) at the 2D paper
     settings, n = 127: still within the largest printed count."""

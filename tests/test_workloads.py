@@ -49,3 +49,18 @@ def test_paper_recipes():
     assert abs(abs(fb[i0, i0]) - 1.0) < 1e-12
     ph = np.angle(fb[i0 + 1, i0 + 1] / fb[i0, i0])
     assert abs(ph - w["omega"] * 2 * h / math.sqrt(2)) < 1e-9
+
+
+def test_variation_widths():
+    """Unequal layer widths recipe: NARROW/WIDE layers tiling the physical
+    lines; wide layers across the lens (where c varies along the sweep axis),
+    narrow ones where it does not (the waveguide is constant along it)."""
+    for field in workloads.PAPER_FIELDS:
+        w = workloads.paper_workload(field, 127)
+        ws = workloads.variation_widths(w["c"], 9, 4, 16)
+        assert sum(ws) == 127 - 16 and all(1 <= x <= 16 for x in ws)
+        assert all(x in (4, 16) for x in ws[:-1])
+    lens = workloads.variation_widths(workloads.velocity_lens2d(127), 9, 4, 16)
+    assert 16 in lens and lens[0] == 4 and lens[-2] == 4
+    guide = workloads.variation_widths(workloads.velocity_waveguide2d(127), 9, 4, 16)
+    assert guide[:-1] == [4] * (len(guide) - 1)

@@ -17,6 +17,7 @@ from .fields import (  # noqa: F401
     velocity_lens3d,
     velocity_random,
     velocity_waveguide2d,
+    variation_widths,
     gaussian_source,
     wave_packet,
     paper_workload,

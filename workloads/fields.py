@@ -75,6 +75,31 @@ def velocity_waveguide2d(n):
     return (4.0 / 3.0) * (1.0 - 0.5 * np.exp(-32.0 * (x1 - 0.5) ** 2))
 
 
+def variation_widths(c, gamma, narrow, wide, quantile=0.5):
+    """Unequal layer widths (Section 3.1 remarks: wider layers where the
+    velocity varies strongly).  v(t) is the largest relative change of c
+    between physical sweep lines t and t + 1 (the sweep axis is the last
+    index).  From the first physical line on, a layer takes ``wide`` lines if
+    v exceeds its ``quantile`` anywhere in those lines, else ``narrow``; the
+    last layer takes what remains.  Returns the list of physical lines per
+    layer (summing to n - 2(gamma - 1))."""
+    c = np.asarray(c, dtype=np.float64)
+    n, g = c.shape[-1], gamma - 1
+    phys = c[..., g:n - g]
+    n_phys = phys.shape[-1]
+    diff = np.abs(np.diff(phys, axis=-1)) / float(np.mean(phys))
+    v = diff.reshape(-1, n_phys - 1).max(axis=0) if n_phys > 1 else np.zeros(0)
+    v = np.append(v, 0.0)
+    thr = float(np.quantile(v, quantile))
+    w, t = [], 0
+    while t < n_phys:
+        k = wide if v[t:t + wide].max() > thr else narrow
+        k = min(k, n_phys - t)
+        w.append(int(k))
+        t += k
+    return w
+
+
 def wave_packet(n, d, omega, centre, direction):
     xs = grid_coords(n, d)
     lam = 2.0 * math.pi / omega
