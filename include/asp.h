@@ -86,6 +86,12 @@ typedef struct {
                        n - 2(pml_eta - 1); read during asp_setup only, not kept.
                        Layer 1 also takes the pml_eta - 1 PML lines below it, layer m
                        those above it.  Violations: ASP_ERR_ARG */
+    int nd3d;       /* 3D factorization of the quasi-2D auxiliary problems: 0 (default) a
+                       dense block recurrence along x1 (n blocks of n L unknowns); nonzero
+                       nested dissection of the n x n columns of L unknowns (Section 4.1),
+                       multifrontal, with O(n^2 L^2 log n) factor entries instead of
+                       O(n^3 L^2).  The result is the same operator G~ either way.
+                       Nonzero with dim = 2: ASP_ERR_ARG */
 } asp_opts;
 
 typedef struct {

@@ -33,7 +33,8 @@ class AspError(RuntimeError):
 class asp_opts(ctypes.Structure):
     _fields_ = [("C", ctypes.c_double), ("prec", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("host_only", ctypes.c_int), ("pml_aux", ctypes.c_int),
-                ("n_layers", ctypes.c_int), ("layer_widths", ctypes.POINTER(ctypes.c_int))]
+                ("n_layers", ctypes.c_int), ("layer_widths", ctypes.POINTER(ctypes.c_int)),
+                ("nd3d", ctypes.c_int)]
 
 
 class asp_plan_info(ctypes.Structure):
@@ -118,7 +119,7 @@ def _current_stream():
 # -- the C entry points --------------------------------------------------------------
 
 def asp_setup(dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64, stream=None,
-              host_only=False, pml_aux=0):
+              host_only=False, pml_aux=0, nd3d=False):
     """Returns a plan handle (ctypes.c_void_p).  c: host array, n**dim velocities
     (column-major, i.e. numpy order='F' flattening of an (n,)*dim array).
     layer_b: lines per layer, or a sequence of physical lines per layer
@@ -127,7 +128,7 @@ def asp_setup(dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64, st
                              if np.asarray(c).ndim > 1 else np.asarray(c, dtype=np.float64))
     opts = asp_opts(C, prec, stream if stream is not None else
                     (ctypes.c_void_p(0) if host_only else _current_stream()), int(host_only),
-                    int(pml_aux or 0), 0, None)
+                    int(pml_aux or 0), 0, None, int(bool(nd3d)))
     if not isinstance(layer_b, (int, np.integer)):
         widths = (ctypes.c_int * len(layer_b))(*[int(w) for w in layer_b])
         opts.n_layers = len(layer_b)
@@ -237,11 +238,11 @@ class Plan:
     """Owning wrapper around a plan handle (destroyed with the object)."""
 
     def __init__(self, dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64,
-                 host_only=False, pml_aux=0):
+                 host_only=False, pml_aux=0, nd3d=False):
         self.dim, self.n = dim, n
         self.N = n ** dim
         self.handle = asp_setup(dim, c, omega, n, layer_b, pml_eta, C=C, prec=prec,
-                                host_only=host_only, pml_aux=pml_aux)
+                                host_only=host_only, pml_aux=pml_aux, nd3d=nd3d)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -99,6 +99,31 @@ struct SubDesc {
     long long tr_off;    // offset of its boundary-to-boundary map (R_p, L_p with 1 < p < m), else -1
     int wrow;            // R/L problems: row of its boundary data in the sweep buffer, else -1
     long long vec_off;   // 3D: offset of this problem's per-entry vectors (B entries each)
+    long long xoff;      // 3D nested dissection: this problem's slab vector (n^2 L x 16 per chunk)
+};
+
+// 3D nested dissection (Section 4.1).  The elimination tree is built over the
+// n x n columns (i1, i2) of a slab, each column holding the L unknowns of its
+// sweep lines; every auxiliary problem shares the tree (only L differs).  A
+// node eliminates its separator columns (all columns at a leaf); its boundary
+// is the set of columns outside its region next to it, which belong to the
+// separators of its ancestors.  Its dense front has the rows and columns
+// [I (padded to ipad, a multiple of 64) | B (padded to a multiple of 64)],
+// column c of the front column list holding rows c L .. c L + L - 1 of its part.
+struct NdNode {
+    int i_off, nI;       // separator columns: nd_cols[i_off .. i_off + nI)
+    int b_off, nB;       // boundary columns: nd_cols[b_off .. b_off + nB)
+    int inv_off[2];      // per child: front column (I then B) -> the child's boundary
+                         // column holding it, or -1 (nd_inv[inv_off + c]); -1: no child
+    int ch[2];           // children: positions in the next level, or -1
+};
+// one front: (auxiliary problem, tree node); fronts are ordered [level][problem][node]
+struct NdFront {
+    long long moff;      // [F_II^-1 | F_II^-1 F_IB] in the factor buffer: ipad x f, column-major
+    long long foff;      // the dense front in its level buffer while factoring (f x f)
+    long long roff;      // panel rows of the Gauss-Jordan steps (f x 64) while factoring
+    long long voff;      // front vector in the solve buffer (f x 16 per chunk)
+    int f, ipad, L, sub, node;
 };
 
 // solve launch modes
@@ -207,6 +232,26 @@ struct asp_plan {
     zd* d_w3 = nullptr;           // sweep planes [pingpong][side][n^2][ws]
     long long w3_elems = 0;
     int ws3 = 0;                  // right-hand-side stride of the planes (multiple of 16)
+    // 3D nested dissection (opts.nd3d): tree and fronts (host and device copies)
+    bool nd = false;
+    int nd_levels = 0;
+    std::vector<int> nd_lvl_nodes;            // nodes per level (root: level 0)
+    std::vector<long long> nd_lvl_front0;     // first front of each level
+    std::vector<int> nd_lvl_fmax;             // largest front of each level
+    std::vector<NdNode> nd_nodes;             // level by level
+    std::vector<int> nd_node0;                // first node of each level
+    std::vector<int> nd_cols, nd_inv;
+    std::vector<NdFront> nd_fronts;
+    std::vector<std::array<int, 2>> nd_groups;   // problems factored together [s0, s1)
+    long long nd_lvlbuf = 0, nd_rbuf = 0;     // level / panel buffer entries of the factorization
+    int nd_dbuf = 0;                          // fronts of the largest (group, level)
+    long long nd_vtot = 0, nd_xtot = 0;       // solve vector entries per chunk of 16
+    NdNode* d_nd_nodes = nullptr;
+    int* d_nd_cols = nullptr;
+    int* d_nd_inv = nullptr;
+    NdFront* d_nd_fronts = nullptr;
+    void* d_nd_v = nullptr;                   // front vectors [chunk][vtot]
+    void* d_nd_x = nullptr;                   // slab vectors [chunk][xtot]
 
     // GMRES workspaces
     int kr_rhs = 0, kr_restart = 0;
@@ -365,6 +410,44 @@ size_t workspace_estimate3(const asp_plan* P, int nrhs);
 asp_status factor3d(asp_plan* P);
 asp_status apply3d_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
 asp_status subsolve3d(asp_plan* P, int idx, const void* in, void* out, int nrhs);
+// nested dissection (nd3d.cpp): tree and fronts at setup (sizes only for a
+// host-only plan), factorization, apply, one auxiliary solve
+asp_status nd_setup(asp_plan* P);
+asp_status nd_upload(asp_plan* P);
+asp_status nd_factor(asp_plan* P);
+asp_status nd_apply(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
+asp_status nd_subsolve(asp_plan* P, int idx, const void* in, void* out, int nrhs);
+asp_status nd_ensure_ws(asp_plan* P, int nrhs);
+size_t nd_workspace_estimate(const asp_plan* P, int nrhs);
+
+// nested-dissection kernels (nd3d.hip); fronts fr[0..nfr) of one level
+struct NdLevel {
+    const NdFront* fr_all;   // every front
+    long long front0;        // first front of the level
+    int nn;                  // nodes in the level
+    long long child0;        // first front of the next level (children), -1: none
+    int nnc;                 // nodes in the next level
+};
+// dense fronts of problems [s0, s1) at one level: original entries + the
+// children's Schur complements (from Fchild); F in Flevel
+hipError_t launch_nd_assemble(const asp_plan* P, const NdLevel& lv, int s0, int s1, void* Flevel,
+                              const void* Fchild, int fmax, hipStream_t st);
+// Gauss-Jordan panel jp of the separator part of nfr fronts
+hipError_t launch_gj_fronts(const asp_plan* P, const NdFront* fr, int nfr, void* Flevel, int jp,
+                            int ntmax, void* Rbuf, void* Dbuf, hipStream_t st);
+// [F_II^-1 | F_II^-1 F_IB] of each front into the factor buffer
+hipError_t launch_nd_copyout(const asp_plan* P, const NdFront* fr, int nfr, const void* Flevel,
+                             int fmax, hipStream_t st);
+// solve inputs into the slab vectors: M data on X_q (grid r), or R/L data from planes
+hipError_t launch_nd_input(const asp_plan* P, const int* jobs, int njobs, int in_mode,
+                           const zd* r, const zd* Win, const int* act, int nact, hipStream_t st);
+// forward (fwd = 1) or backward step over one level for the jobs
+hipError_t launch_nd_level(const asp_plan* P, const NdLevel& lv, const int* jobs, int njobs,
+                           int fwd, int fmax, int nact, hipStream_t st);
+// outputs of the solved slabs on X_p, as launch modes of the block solves
+hipError_t launch_nd_output(const asp_plan* P, const int* jobs, int njobs, bool two_sided,
+                            const int out_mode[2], zd* const out[2], const zd* U, zd* Wout,
+                            const int* act, int nact, hipStream_t st);
 
 // a launch bracketed by a KTimer of class cls
 #define ASP_TIMED(plan, cls, bytes, flops, call)        \

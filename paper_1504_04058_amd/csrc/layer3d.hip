@@ -173,6 +173,7 @@ __global__ __launch_bounds__(256) void form3d_kernel(Form3Args a) {
 struct GjArgs {
     const SubDesc* desc;
     const int* jobs;
+    const NdFront* fr;   // non-NULL: nested-dissection fronts (only the separator part pivots)
     void* fac;
     void* Rbuf;     // [job][Bmax][64]: the panel rows before the step
     void* Dbuf;     // [job][64][64]: the inverse of the pivot tile
@@ -180,6 +181,31 @@ struct GjArgs {
     long long rstride;
     int k, jp, ntmax;
 };
+
+// the matrix of job js: block k of a problem (all panels pivot), or a front
+// whose first ipad / 64 panels pivot
+struct GjMat {
+    long long off, roff;
+    int Bp, npiv;
+};
+
+__device__ __forceinline__ GjMat gj_mat(const GjArgs& a, int js) {
+    GjMat m;
+    if (a.fr) {
+        const NdFront& f = a.fr[js];
+        m.off = f.foff;
+        m.roff = f.roff;
+        m.Bp = f.f;
+        m.npiv = f.ipad / TB;
+    } else {
+        const SubDesc& d = a.desc[a.jobs[js]];
+        m.Bp = d.B;
+        m.off = d.fac_off + (long long)a.k * d.B * d.B;
+        m.roff = js * a.rstride;
+        m.npiv = d.B / TB;
+    }
+    return m;
+}
 
 // Pivot tile of panel jp: Dbuf = D^-1 for D = A[J,J], one 1024-thread
 // workgroup per job.  Gauss-Jordan elimination without pivoting: thread t holds
@@ -191,10 +217,10 @@ __global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
     __shared__ cplx<T> rowbuf[2][TB], colbuf[2][TB];
     __shared__ int bad;
     const int js = blockIdx.x;
-    const SubDesc d = a.desc[a.jobs[js]];
-    const int Bp = d.B;
-    if (a.jp >= Bp / TB) return;
-    const cplx<T>* A = static_cast<const cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    const GjMat gm = gj_mat(a, js);
+    const int Bp = gm.Bp;
+    if (a.jp >= gm.npiv) return;
+    const cplx<T>* A = static_cast<const cplx<T>*>(a.fac) + gm.off;
     const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;     // cg = 0..15
     const int J0 = a.jp * TB;
     if (threadIdx.x == 0) bad = 0;
@@ -253,13 +279,13 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
     __shared__ cplx<T> sD[TB * LDT];
     __shared__ cplx<T> sA[TB * LDT];
     const int js = blockIdx.y;
-    const SubDesc d = a.desc[a.jobs[js]];
-    const int Bp = d.B, nt = Bp / TB;
-    if (a.jp >= nt) return;
+    const GjMat gm = gj_mat(a, js);
+    const int Bp = gm.Bp, nt = Bp / TB;
+    if (a.jp >= gm.npiv) return;
     const bool rowt = (int)blockIdx.x < a.ntmax;
     const int t = rowt ? blockIdx.x : blockIdx.x - a.ntmax;
     if (t >= nt || t == a.jp) return;
-    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + gm.off;
     const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
     const int J0 = a.jp * TB;
     load_tile(sD, static_cast<const cplx<T>*>(a.Dbuf) + (long long)js * TB * TB, TB, 0, 0);
@@ -276,7 +302,7 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
     } else {
         load_tile(sA, A, Bp, J0, t * TB);
         __syncthreads();
-        cplx<T>* R = static_cast<cplx<T>*>(a.Rbuf) + js * a.rstride;
+        cplx<T>* R = static_cast<cplx<T>*>(a.Rbuf) + gm.roff;
 #pragma unroll 4
         for (int e = 0; e < 16; ++e) {
             const int c = cg + 4 * e;
@@ -294,12 +320,12 @@ __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
     __shared__ cplx<T> sP[TB * LDT];
     __shared__ cplx<T> sQ[TB * LDT];
     const int js = blockIdx.y;
-    const SubDesc d = a.desc[a.jobs[js]];
-    const int Bp = d.B, nt = Bp / TB;
-    if (a.jp >= nt) return;
+    const GjMat gm = gj_mat(a, js);
+    const int Bp = gm.Bp, nt = Bp / TB;
+    if (a.jp >= gm.npiv) return;
     const int ti = blockIdx.x % a.ntmax, tj = blockIdx.x / a.ntmax;
     if (ti >= nt || tj >= nt) return;
-    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    cplx<T>* A = static_cast<cplx<T>*>(a.fac) + gm.off;
     const int J0 = a.jp * TB;
     if (tj == a.jp) {
         if (ti == a.jp) {
@@ -314,7 +340,7 @@ __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
         return;
     }
     if (ti == a.jp) return;
-    const cplx<T>* R = static_cast<const cplx<T>*>(a.Rbuf) + js * a.rstride;
+    const cplx<T>* R = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff;
     load_tile(sP, A, Bp, ti * TB, J0);
     load_tile(sQ, R, TB, 0, tj * TB);
     CTile<T> acc[2][2];
@@ -368,12 +394,12 @@ __device__ __forceinline__ f32x4 split_mac(bf16x8 xh, bf16x8 xl, bf16x8 yh, bf16
 __global__ __launch_bounds__(NT) void gj_update_bf16x3_kernel(GjArgs a) {
     __shared__ SplitPlanes sP, sQ;   // P[r][k], Q^T[c][k]
     const int js = blockIdx.y;
-    const SubDesc d = a.desc[a.jobs[js]];
-    const int Bp = d.B, nt = Bp / TB;
-    if (a.jp >= nt) return;
+    const GjMat gm = gj_mat(a, js);
+    const int Bp = gm.Bp, nt = Bp / TB;
+    if (a.jp >= gm.npiv) return;
     const int ti = blockIdx.x % a.ntmax, tj = blockIdx.x / a.ntmax;
     if (ti >= nt || tj >= nt) return;
-    zf* A = static_cast<zf*>(a.fac) + d.fac_off + (long long)a.k * Bp * Bp;
+    zf* A = static_cast<zf*>(a.fac) + gm.off;
     const int J0 = a.jp * TB;
     if (tj == a.jp) {
         if (ti == a.jp) {
@@ -388,7 +414,7 @@ __global__ __launch_bounds__(NT) void gj_update_bf16x3_kernel(GjArgs a) {
         return;
     }
     if (ti == a.jp) return;
-    const zf* R = static_cast<const zf*>(a.Rbuf) + js * a.rstride;
+    const zf* R = static_cast<const zf*>(a.Rbuf) + gm.roff;
     {
         // P(r, k) = A(ti*64 + r, J0 + k): reads coalesced over r
         const int r = threadIdx.x & 63, kg = threadIdx.x >> 6;
@@ -730,19 +756,9 @@ hipError_t launch_form3d(const asp_plan* P, const int* jobs, int njobs, int k, h
     return hipGetLastError();
 }
 
-hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int jp, void* Rbuf,
-                       void* Dbuf, hipStream_t st) {
-    GjArgs a;
-    a.desc = P->d_desc;
-    a.jobs = jobs;
-    a.fac = P->d_fac;
-    a.Rbuf = Rbuf;
-    a.Dbuf = Dbuf;
-    a.flag = P->d_flag;
-    a.rstride = (long long)P->Bmax * TB;
-    a.k = k;
-    a.jp = jp;
-    a.ntmax = P->Bmax / TB;
+namespace {
+
+void launch_gj(const asp_plan* P, const GjArgs& a, int njobs, hipStream_t st) {
     dim3 g0(njobs), g1(2 * a.ntmax, njobs), g2(a.ntmax * a.ntmax, njobs);
     if (P->prec != ASP_PREC_FP64) {
         hipLaunchKernelGGL(gj_pivot_kernel<float>, g0, dim3(1024), 0, st, a);
@@ -756,6 +772,43 @@ hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int
         hipLaunchKernelGGL(gj_panel_kernel<double>, g1, dim3(NT), 0, st, a);
         hipLaunchKernelGGL(gj_update_kernel<double>, g2, dim3(NT), 0, st, a);
     }
+}
+
+}  // namespace
+
+hipError_t launch_gj_fronts(const asp_plan* P, const NdFront* fr, int nfr, void* Flevel, int jp,
+                            int ntmax, void* Rbuf, void* Dbuf, hipStream_t st) {
+    const size_t esz = P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd);
+    constexpr int YMAX = 65535;
+    for (int y0 = 0; y0 < nfr; y0 += YMAX) {
+        GjArgs a{};
+        a.fr = fr + y0;
+        a.fac = Flevel;
+        a.Rbuf = Rbuf;
+        a.Dbuf = static_cast<char*>(Dbuf) + (size_t)y0 * TB * TB * esz;
+        a.flag = P->d_flag;
+        a.jp = jp;
+        a.ntmax = ntmax;
+        launch_gj(P, a, std::min(YMAX, nfr - y0), st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int jp, void* Rbuf,
+                       void* Dbuf, hipStream_t st) {
+    GjArgs a;
+    a.desc = P->d_desc;
+    a.jobs = jobs;
+    a.fr = nullptr;
+    a.fac = P->d_fac;
+    a.Rbuf = Rbuf;
+    a.Dbuf = Dbuf;
+    a.flag = P->d_flag;
+    a.rstride = (long long)P->Bmax * TB;
+    a.k = k;
+    a.jp = jp;
+    a.ntmax = P->Bmax / TB;
+    launch_gj(P, a, njobs, st);
     return hipGetLastError();
 }
 

@@ -147,6 +147,7 @@ extern "C" void asp_default_opts(asp_opts* o) {
     o->pml_aux = 0;
     o->n_layers = 0;
     o->layer_widths = nullptr;
+    o->nd3d = 0;
 }
 
 extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double omega, int n,
@@ -196,6 +197,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (o.prec == ASP_PREC_BF16X3 && dim != 3)
         return fail(ASP_ERR_ARG, "the bf16 split precision applies to the 3D factorization only");
     if (dim == 3 && (long long)n * n * n > (1LL << 31)) return fail(ASP_ERR_ARG, "grid too large");
+    if (o.nd3d && dim != 3) return fail(ASP_ERR_ARG, "nd3d (nested dissection) applies to 3D plans only");
 
     P->dim = dim;
     P->n = n;
@@ -273,6 +275,12 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     const size_t esz = (P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd));
     P->fac_elems = fac_off;
     P->fac_bytes = (size_t)fac_off * esz;
+    if (dim == 3 && o.nd3d) {
+        // nested dissection: the tree, the fronts and the factor size
+        P->nd = true;
+        asp_status s_nd = nd_setup(P);
+        if (s_nd != ASP_OK) return fail(s_nd, P->err.c_str());
+    }
     P->t_elems = tr_off;
     P->t_bytes = (size_t)tr_off * esz;
 
@@ -339,6 +347,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
         if ((st = upload(P, &P->d_e3, e3.data(), e3.size())) != ASP_OK) return fail(st, P->err.c_str());
         if ((st = upload(P, &P->d_gv3, gv3.data(), gv3.size())) != ASP_OK) return fail(st, P->err.c_str());
     }
+    if (P->nd && (st = nd_upload(P)) != ASP_OK) return fail(st, P->err.c_str());
     if (hipMalloc(reinterpret_cast<void**>(&P->d_flag), sizeof(int)) != hipSuccess)
         return fail(ASP_ERR_OOM, "hipMalloc failed");
     if (hipMalloc(reinterpret_cast<void**>(&P->d_sink), SINK_ELEMS * sizeof(zd)) != hipSuccess)
@@ -358,7 +367,8 @@ extern "C" void asp_destroy(asp_plan* P) {
     void* bufs[] = {P->d_ksq, P->d_axis, P->d_subtab, P->d_desc, P->d_jobs, P->d_fac, P->d_flag, P->d_sink,
                     P->d_T, P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_y, P->d_V, P->d_Z, P->d_b,
                     P->d_red, P->d_small, P->d_act, P->d_e3, P->d_gv3, P->d_y3,
-                    P->d_g3, P->d_w3};
+                    P->d_g3, P->d_w3, P->d_nd_nodes, P->d_nd_cols, P->d_nd_inv, P->d_nd_fronts,
+                    P->d_nd_v, P->d_nd_x};
     (void)hipStreamSynchronize(P->stream);
     for (void* b : bufs)
         if (b) (void)hipFree(b);

@@ -229,6 +229,29 @@ def test_planned_factor_bytes(dim, n, b, gamma, prec):
         assert 13.9e9 < info["factor_bytes"] < 15.0e9     # 13.9 GB unpadded, ~3% padding
 
 
+@pytest.mark.parametrize("n,b,gamma,aux", [(63, 4, 8, 0), (79, 4, 9, 5), (39, 4, 9, 5)])
+def test_nested_dissection_plan(L, n, b, gamma, aux):
+    """opts.nd3d (Section 4.1): same partition, fewer factor entries than the
+    dense x1-blocks at these sizes; 2D plans reject it."""
+    c = np.ones(n ** 3)
+    nd = asp.asp_setup(3, c, 10.0, n, b, gamma, host_only=True, pml_aux=aux, nd3d=True,
+                       prec=asp.ASP_PREC_FP32)
+    dense = asp.asp_setup(3, c, 10.0, n, b, gamma, host_only=True, pml_aux=aux,
+                          prec=asp.ASP_PREC_FP32)
+    try:
+        a, b_ = asp.asp_info(nd), asp.asp_info(dense)
+        assert a["m"] == b_["m"] and a["n_sub"] == b_["n_sub"]
+        assert 0 < a["factor_bytes"] < b_["factor_bytes"]
+        assert [tuple(r) for r in asp.asp_layers(nd)[1].tolist()] == \
+            [tuple(r) for r in asp.asp_layers(dense)[1].tolist()]
+    finally:
+        asp.asp_destroy(nd)
+        asp.asp_destroy(dense)
+    with pytest.raises(asp.AspError) as ei:
+        asp.asp_setup(2, np.ones(63 * 63), 10.0, 63, 4, 12, host_only=True, nd3d=True)
+    assert ei.value.status == asp.ASP_ERR_ARG and "3D" in str(ei.value)
+
+
 def test_bf16_split_precision_is_3d_only(L):
     with pytest.raises(asp.AspError) as e:
         asp.asp_setup(2, np.ones(63 * 63), 10.0, 63, 4, 12, prec=asp.ASP_PREC_BF16X3, host_only=True)
