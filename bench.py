@@ -71,6 +71,9 @@ def parse():
                          "(e.g. 127,255,511,1023,2047); '' for none")
     ap.add_argument("--paper-tables3d", default="",
                     help="grid sizes of the paper's 3D experiments to run (e.g. 39,79); '' for none")
+    ap.add_argument("--paper-blocks3d", action="store_true",
+                    help="factor the 3D paper tables by the dense block recurrence instead of "
+                         "nested dissection")
     ap.add_argument("--paper-widths", default="",
                     help="NARROW:WIDE: run the 2D paper tables also with unequal layers of NARROW "
                          "or WIDE lines, wide where the velocity varies along the sweep axis "
@@ -186,7 +189,7 @@ def recorded_traffic(workload, prec_name, cls):
     return c["fetch_bytes"] + c["write_bytes"]
 
 
-def run_workload(name, prec_name, steps, warmup, restart=None, tol=None):
+def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=True):
     """Time `steps` passes of the hot path (factor + GMRES of the whole batch)
     after `warmup` untimed passes; returns the measurements."""
     import ctypes
@@ -205,7 +208,8 @@ def run_workload(name, prec_name, steps, warmup, restart=None, tol=None):
     dev = torch.device("cuda:0")
     f = torch.from_numpy(w["f"]).to(dev)
     u = torch.empty_like(f)
-    plan = asp.Plan(w["d"], w["c"], w["omega"], w["n"], w["b"], w["gamma"], C=w["C"], prec=prec)
+    plan = asp.Plan(w["d"], w["c"], w["omega"], w["n"], w["b"], w["gamma"], C=w["C"], prec=prec,
+                    nd3d=nd3d)
     h = plan.handle
     L = asp.lib()
     for _ in range(warmup):
@@ -293,7 +297,7 @@ def serving_run(count, prec_name):
     return summ
 
 
-def paper_tables(prec_name, sizes, dim=2, widths=None):
+def paper_tables(prec_name, sizes, dim=2, widths=None, nd3d=True):
     """The paper's experiments (Tables 1-3 of Section 3.2 in 2D, Tables 4-6 of
     Section 4.2 in 3D) on this path: per field and grid, the factorization
     time, the GMRES(40) iterations to 1e-3 for force (a) point source and (b)
@@ -324,7 +328,7 @@ def paper_tables(prec_name, sizes, dim=2, widths=None):
                 layouts.append(workloads.variation_widths(w["c"], w["gamma"], *widths))
             for lb in layouts:
                 with asp.Plan(dim, w["c"], w["omega"], n, lb, w["gamma"], C=w["C"], prec=prec,
-                              pml_aux=w.get("gamma_aux", 0)) as plan:
+                              pml_aux=w.get("gamma_aux", 0), nd3d=nd3d and dim == 3) as plan:
                     torch.cuda.synchronize()
                     a = time.perf_counter()
                     plan.factor()
@@ -355,7 +359,8 @@ def paper_tables(prec_name, sizes, dim=2, widths=None):
                 "forces (a) point source at (1/2, 1/8), (b) wave packet at (1/8, 1/8)") if dim == 2 else \
                ("gamma 9, gamma_aux 5, b 4, C 25, 8 points per wavelength, GMRES(40) to 1e-3, "
                 "forces (a) point source at (1/2, 1/2, 1/4), (b) wave packet at (1/2, 1/4, 1/4)")
-    return {"settings": settings, "dim": dim, "layer_precision": prec_name, "rows": rows}
+    return {"settings": settings, "dim": dim, "layer_precision": prec_name, "rows": rows,
+            "factorization": ("nested dissection" if nd3d else "block recurrence") if dim == 3 else None}
 
 
 def workloads_dim(name):
@@ -406,12 +411,15 @@ def main():
         "cpu_baseline": None,
     }
     if args.secondary:
-        for key, prec in (("secondary", args.prec), ("secondary_bf16x3", "bf16x3")):
-            if prec == "bf16x3" and workloads_dim(args.secondary) != 3:
+        for key, prec, nd in (("secondary", args.prec, True), ("secondary_bf16x3", "bf16x3", True),
+                              ("secondary_blocks", args.prec, False)):
+            if (prec == "bf16x3" or not nd) and workloads_dim(args.secondary) != 3:
                 continue
-            s2 = run_workload(args.secondary, prec, 1, 1)
+            s2 = run_workload(args.secondary, prec, 1, 1, nd3d=nd)
             out[key] = {
-                "config": config_of(args.secondary, s2, prec),
+                "config": dict(config_of(args.secondary, s2, prec),
+                               factorization=("nested dissection" if nd else "block recurrence")
+                               if workloads_dim(args.secondary) == 3 else None),
                 "value": s2["value"], "unit": "solves/s", "ms_per_step": s2["ms_per_step"],
                 "warm_solves_per_s": s2["warm_solves_per_s"], "factor_ms": s2["factor_ms"],
                 "gmres_ms": s2["gmres_ms"], "iters_mean": float(s2["iters"].mean()),
@@ -426,7 +434,7 @@ def main():
                                            if args.paper_widths else None)
     if args.paper_tables3d:
         out["paper_tables3d"] = paper_tables(args.prec, [int(x) for x in args.paper_tables3d.split(",")],
-                                             dim=3)
+                                             dim=3, nd3d=not args.paper_blocks3d)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["w"], float(iters.mean()), args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -65,6 +65,15 @@ typedef enum {
 
 typedef enum { ASP_SUB_M = 0, ASP_SUB_R = 1, ASP_SUB_L = 2 } asp_sub_kind;
 
+typedef enum {
+    ASP_FACT3D_ND = 0,      /* nested dissection (Section 4.1): the unknowns grouped into
+                               columns along the sweep axis, the n x n columns ordered by
+                               nested dissection, multifrontal elimination;
+                               O(n^2 L^2 log n) factor entries per problem */
+    ASP_FACT3D_BLOCKS = 1   /* a dense block recurrence along x1: n blocks of n L
+                               unknowns, O(n^3 L^2) factor entries per problem */
+} asp_fact3d;
+
 typedef struct {
     double C;       /* PML strength (Section 2, "an appropriate positive constant"); default 25 */
     int prec;       /* asp_prec; default ASP_PREC_FP64 */
@@ -86,12 +95,9 @@ typedef struct {
                        n - 2(pml_eta - 1); read during asp_setup only, not kept.
                        Layer 1 also takes the pml_eta - 1 PML lines below it, layer m
                        those above it.  Violations: ASP_ERR_ARG */
-    int nd3d;       /* 3D factorization of the quasi-2D auxiliary problems: 0 (default) a
-                       dense block recurrence along x1 (n blocks of n L unknowns); nonzero
-                       nested dissection of the n x n columns of L unknowns (Section 4.1),
-                       multifrontal, with O(n^2 L^2 log n) factor entries instead of
-                       O(n^3 L^2).  The result is the same operator G~ either way.
-                       Nonzero with dim = 2: ASP_ERR_ARG */
+    int fact3d;     /* asp_fact3d: how the quasi-2D auxiliary problems of a 3D plan are
+                       factored; default ASP_FACT3D_ND.  Either way the result is the
+                       same operator G~.  Ignored by 2D plans; other values ASP_ERR_ARG */
 } asp_opts;
 
 typedef struct {

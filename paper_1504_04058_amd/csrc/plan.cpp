@@ -147,7 +147,7 @@ extern "C" void asp_default_opts(asp_opts* o) {
     o->pml_aux = 0;
     o->n_layers = 0;
     o->layer_widths = nullptr;
-    o->nd3d = 0;
+    o->fact3d = ASP_FACT3D_ND;
 }
 
 extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double omega, int n,
@@ -197,7 +197,8 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (o.prec == ASP_PREC_BF16X3 && dim != 3)
         return fail(ASP_ERR_ARG, "the bf16 split precision applies to the 3D factorization only");
     if (dim == 3 && (long long)n * n * n > (1LL << 31)) return fail(ASP_ERR_ARG, "grid too large");
-    if (o.nd3d && dim != 3) return fail(ASP_ERR_ARG, "nd3d (nested dissection) applies to 3D plans only");
+    if (o.fact3d != ASP_FACT3D_ND && o.fact3d != ASP_FACT3D_BLOCKS)
+        return fail(ASP_ERR_ARG, "unknown fact3d");
 
     P->dim = dim;
     P->n = n;
@@ -275,7 +276,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     const size_t esz = (P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd));
     P->fac_elems = fac_off;
     P->fac_bytes = (size_t)fac_off * esz;
-    if (dim == 3 && o.nd3d) {
+    if (dim == 3 && o.fact3d == ASP_FACT3D_ND) {
         // nested dissection: the tree, the fronts and the factor size
         P->nd = true;
         asp_status s_nd = nd_setup(P);

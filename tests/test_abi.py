@@ -200,10 +200,11 @@ def test_host_only_plan_refuses_device_calls(L):
                                                 (3, 63, 4, 8, 1), (3, 31, 4, 8, 0)])
 def test_planned_factor_bytes(dim, n, b, gamma, prec):
     """The planned factor size: 2D, n blocks of L x LR per problem (LR = 16 or
-    32 rows) plus an n x n boundary map for R_p, L_p with 1 < p < m; 3D, n dense
-    blocks of B x B with B = n L rounded up to a multiple of 64."""
+    32 rows) plus an n x n boundary map for R_p, L_p with 1 < p < m; 3D with the
+    block recurrence, n dense blocks of B x B with B = n L rounded up to a
+    multiple of 64."""
     c = np.ones(n ** dim)
-    plan = asp.asp_setup(dim, c, 2 * np.pi * 4, n, b, gamma, prec=prec, host_only=True)
+    plan = asp.asp_setup(dim, c, 2 * np.pi * 4, n, b, gamma, prec=prec, host_only=True, nd3d=False)
     try:
         info = asp.asp_info(plan)
     finally:
@@ -231,12 +232,13 @@ def test_planned_factor_bytes(dim, n, b, gamma, prec):
 
 @pytest.mark.parametrize("n,b,gamma,aux", [(63, 4, 8, 0), (79, 4, 9, 5), (39, 4, 9, 5)])
 def test_nested_dissection_plan(L, n, b, gamma, aux):
-    """opts.nd3d (Section 4.1): same partition, fewer factor entries than the
-    dense x1-blocks at these sizes; 2D plans reject it."""
+    """opts.fact3d (Section 4.1): nested dissection (the default) has the same
+    partition and fewer factor entries than the dense x1-blocks at these
+    sizes; 2D plans ignore the field; unknown values are rejected."""
     c = np.ones(n ** 3)
-    nd = asp.asp_setup(3, c, 10.0, n, b, gamma, host_only=True, pml_aux=aux, nd3d=True,
+    nd = asp.asp_setup(3, c, 10.0, n, b, gamma, host_only=True, pml_aux=aux,
                        prec=asp.ASP_PREC_FP32)
-    dense = asp.asp_setup(3, c, 10.0, n, b, gamma, host_only=True, pml_aux=aux,
+    dense = asp.asp_setup(3, c, 10.0, n, b, gamma, host_only=True, pml_aux=aux, nd3d=False,
                           prec=asp.ASP_PREC_FP32)
     try:
         a, b_ = asp.asp_info(nd), asp.asp_info(dense)
@@ -247,9 +249,15 @@ def test_nested_dissection_plan(L, n, b, gamma, aux):
     finally:
         asp.asp_destroy(nd)
         asp.asp_destroy(dense)
-    with pytest.raises(asp.AspError) as ei:
-        asp.asp_setup(2, np.ones(63 * 63), 10.0, 63, 4, 12, host_only=True, nd3d=True)
-    assert ei.value.status == asp.ASP_ERR_ARG and "3D" in str(ei.value)
+    for flag in (True, False):
+        p2 = asp.asp_setup(2, np.ones(63 * 63), 10.0, 63, 4, 12, host_only=True, nd3d=flag)
+        asp.asp_destroy(p2)
+    opts = asp.asp_opts(25.0, asp.ASP_PREC_FP64, None, 1, 0, 0, None, 7)
+    plan = ctypes.c_void_p()
+    st = L.asp_setup(ctypes.byref(plan), 3, c.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(10.0),
+                     n, b, gamma, ctypes.byref(opts))
+    assert st == asp.ASP_ERR_ARG and "fact3d" in asp.asp_last_error(plan)
+    asp.asp_destroy(plan)
 
 
 def test_bf16_split_precision_is_3d_only(L):

@@ -2,7 +2,8 @@
 FP64 oracle, through the C ABI.
 
 Tolerances (relative 2-norm): one auxiliary Green's operator and the whole
-apply with FP64 factors 1e-11; FP32 factors 2e-4 per operator and 1e-3 for the
+apply with FP64 factors 1e-11 (both factorizations: nested dissection, the
+default, and the dense block recurrence); FP32 factors 2e-4 per operator and 1e-3 for the
 apply; GMRES to tol 1e-6: iterations within +-1 of the oracle, the true
 relative residual (recomputed by the oracle's operator) <= 1e-6, the solution
 within 1e-6 (FP64) or 1e-5 (FP32 factors) of the oracle's.  The cases span one
@@ -68,17 +69,23 @@ def _oracle_workload(name, n, nrhs):
     return w, P, P.A(), Preconditioner(P)
 
 
-def _plan(P, prec=asp.ASP_PREC_FP64):
-    return asp.Plan(3, P.c, P.omega, P.n, P.b, P.gamma, C=P.C, prec=prec)
+def _plan(P, prec=asp.ASP_PREC_FP64, nd=True):
+    """nd: nested dissection (the default factorization), else the dense block
+    recurrence along x1"""
+    return asp.Plan(3, P.c, P.omega, P.n, P.b, P.gamma, C=P.C, prec=prec, nd3d=nd)
+
+
+FACT = pytest.mark.parametrize("nd", [True, False], ids=["nd", "blocks"])
 
 
 CASES = [(19, 4, 4), (23, 8, 4), (26, 5, 3)]
 
 
+@FACT
 @pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 2e-4)])
 @pytest.mark.parametrize("n,gamma,b", CASES)
-def test_auxiliary_operators_3d(n, gamma, b, prec, tol):
-    print(f"3D operators n={n} gamma={gamma} b={b} prec={prec}", flush=True)
+def test_auxiliary_operators_3d(n, gamma, b, prec, tol, nd):
+    print(f"3D operators n={n} gamma={gamma} b={b} prec={prec} nd={nd}", flush=True)
     P = _problem(n, gamma, b)
     X = partition.layers(n, b, gamma)
     subs = partition.subproblems(n, b, gamma)
@@ -86,7 +93,7 @@ def test_auxiliary_operators_3d(n, gamma, b, prec, tol):
     rng = np.random.default_rng(5)
     picks = {"M": [1, 2, m], "R": [2, m], "L": [1, m - 1]}
     kinds = {"M": asp.ASP_SUB_M, "R": asp.ASP_SUB_R, "L": asp.ASP_SUB_L}
-    with _plan(P, prec) as plan:
+    with _plan(P, prec, nd) as plan:
         plan.factor()
         for kind, ps in picks.items():
             for p in sorted(set(ps)):
@@ -100,37 +107,40 @@ def test_auxiliary_operators_3d(n, gamma, b, prec, tol):
                     assert rel(out[r], ref.G(data[r])) < tol, (kind, p)
 
 
+@FACT
 @pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
 @pytest.mark.parametrize("n,gamma,b", CASES + [(31, 8, 4)])
-def test_apply_3d(n, gamma, b, prec, tol):
-    print(f"3D apply n={n} gamma={gamma} b={b} prec={prec}", flush=True)
+def test_apply_3d(n, gamma, b, prec, tol, nd):
+    print(f"3D apply n={n} gamma={gamma} b={b} prec={prec} nd={nd}", flush=True)
     P, M = _oracle(n, gamma, b)
     rng = np.random.default_rng(3)
     r = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
-    with _plan(P, prec) as plan:
+    with _plan(P, prec, nd) as plan:
         plan.factor()
         z = host(plan.apply(dev(r)))
     for k in range(2):
         assert rel(z[k], M.apply(r[k])) < tol
 
 
-def test_single_layer_3d():
+@FACT
+def test_single_layer_3d(nd):
     """n = 15, gamma = 8: one layer, so the preconditioner is A^-1."""
     P = _problem(15, 8, 4, velocity="constant")
     assert len(partition.layers(15, 4, 8)) == 1
     r = np.random.default_rng(0).standard_normal(P.N) + 0j
-    with _plan(P) as plan:
+    with _plan(P, nd=nd) as plan:
         plan.factor()
         z = host(plan.apply(dev(r[None])))[0]
     assert rel(z, direct.solve(P.A(), r)) < 1e-10
 
 
-def test_many_rhs_3d():
+@FACT
+def test_many_rhs_3d(nd):
     """More than one 16-wide chunk of right-hand sides (ragged: 19)."""
     P, M = _oracle(19, 4, 4)
     rng = np.random.default_rng(9)
     r = rng.standard_normal((19, P.N)) + 1j * rng.standard_normal((19, P.N))
-    with _plan(P) as plan:
+    with _plan(P, nd=nd) as plan:
         plan.factor()
         z = host(plan.apply(dev(r)))
     for k in (0, 15, 16, 18):
@@ -166,8 +176,9 @@ def test_alone_equals_in_batch_3d():
             assert np.array_equal(host(u1)[0], u_all[k])
 
 
+@FACT
 @pytest.mark.parametrize("n,gamma,b", [(19, 4, 4), (31, 8, 4)])
-def test_apply_3d_bf16_split(n, gamma, b):
+def test_apply_3d_bf16_split(n, gamma, b, nd):
     """Real-split bf16 Schur updates: the apply against the FP64 oracle, with
     the FP32 path printed beside it.  The split keeps hi*hi + hi*lo + lo*hi of
     every real product (16 of FP32's 24 significant bits survive in each
@@ -176,10 +187,10 @@ def test_apply_3d_bf16_split(n, gamma, b):
     P, M = _oracle(n, gamma, b)
     rng = np.random.default_rng(3)
     r = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
-    with _plan(P, asp.ASP_PREC_BF16X3) as plan:
+    with _plan(P, asp.ASP_PREC_BF16X3, nd) as plan:
         plan.factor()
         z = host(plan.apply(dev(r)))
-    with _plan(P, asp.ASP_PREC_FP32) as plan:
+    with _plan(P, asp.ASP_PREC_FP32, nd) as plan:
         plan.factor()
         z32 = host(plan.apply(dev(r)))
     for k in range(2):
