@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "asp_internal.h"
 #include "mfma.h"
@@ -51,24 +52,70 @@ __device__ __forceinline__ void load_tile(cplx<T>* S, const cplx<T>* A, long lon
 // 32 (w / 2) .. + 32 and columns 32 (w % 2) .. + 32 as four transposed 16 x 16
 // blocks: acc[a][b], lane l, element v is C(R0 + 16 b + l % 16, C0 + 16 a +
 // row(l, v)), so that a column of C leaves the lanes contiguously.
+// FP32 uses the three-product (Gauss) form, seeded from the accumulators:
+// p1 = 0, p2 = im, p3 = -re, then p1 += (q_r + q_i) p_r, p2 += q_r (p_i - p_r),
+// p3 += q_i (p_r + p_i), and re = p1 - p3, im = p1 + p2 (three real products
+// per complex one instead of four).
 template <typename T>
 __device__ __forceinline__ void tile_product(const cplx<T>* P, const cplx<T>* Q,
                                              CTile<T> acc[2][2]) {
     const int l = lane_id(), w = wave_id();
     const int R0 = 32 * (w >> 1), C0 = 32 * (w & 1);
     const int li = l & 15, lk = l >> 4;
-#pragma unroll 2
-    for (int k0 = 0; k0 < TB; k0 += 4) {
-        const int kq = k0 + lk;
-        cplx<T> qa[2], pb[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) qa[a] = Q[kq * LDT + C0 + 16 * a + li];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) pb[b] = P[(R0 + 16 * b + li) * LDT + kq];
+    if constexpr (std::is_same<T, float>::value) {
+        f32x4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) cmac(acc[a][b], qa[a], pb[b]);
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    p1[a][b][v] = 0.f;
+                    p2[a][b][v] = acc[a][b].im[v];
+                    p3[a][b][v] = -acc[a][b].re[v];
+                }
+#pragma unroll 2
+        for (int k0 = 0; k0 < TB; k0 += 4) {
+            const int kq = k0 + lk;
+            zf qa[2], pb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) qa[a] = Q[kq * LDT + C0 + 16 * a + li];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) pb[b] = P[(R0 + 16 * b + li) * LDT + kq];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float qs = qa[a].x + qa[a].y;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    p1[a][b] = Mfma<float>::mac(qs, pb[b].x, p1[a][b]);
+                    p2[a][b] = Mfma<float>::mac(qa[a].x, pb[b].y - pb[b].x, p2[a][b]);
+                    p3[a][b] = Mfma<float>::mac(qa[a].y, pb[b].x + pb[b].y, p3[a][b]);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    acc[a][b].re[v] = p1[a][b][v] - p3[a][b][v];
+                    acc[a][b].im[v] = p1[a][b][v] + p2[a][b][v];
+                }
+    } else {
+#pragma unroll 2
+        for (int k0 = 0; k0 < TB; k0 += 4) {
+            const int kq = k0 + lk;
+            cplx<T> qa[2], pb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) qa[a] = Q[kq * LDT + C0 + 16 * a + li];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) pb[b] = P[(R0 + 16 * b + li) * LDT + kq];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) cmac(acc[a][b], qa[a], pb[b]);
+        }
     }
 }
 
