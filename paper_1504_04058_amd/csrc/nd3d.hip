@@ -70,77 +70,96 @@ struct AsmArgs {
 // F(r, c): the symmetric-form couplings of the 7-point operator between the
 // unknowns of rows r and c if one of them is a separator unknown, plus the
 // children's Schur complements on the pairs they share; identity / zero on
-// the padding.
+// the padding.  One workgroup per front column c (what depends on c is
+// decoded once), threads over the rows.
 template <typename T>
 __global__ __launch_bounds__(NT) void nd_assemble_kernel(AsmArgs a) {
     const long long fi = a.fbase + blockIdx.y;
     const NdFront F = a.fr[fi];
-    const long long idx = (long long)blockIdx.x * NT + threadIdx.x;
-    if (idx >= (long long)F.f * F.f) return;
-    const int r = (int)(idx % F.f), c = (int)(idx / F.f);
+    const int c = blockIdx.x;
+    if (c >= F.f) return;
     const NdNode nd = a.nodes[F.node];
     const int L = F.L;
-    const Part pr = decode(r, F.ipad, nd.nI, nd.nB, L), pc = decode(c, F.ipad, nd.nI, nd.nB, L);
-    cplx<T>* out = static_cast<cplx<T>*>(a.F) + F.foff + (long long)c * F.f + r;
-    if (pr.part >= 2 || pc.part >= 2) {
-        *out = mk<T>((r == c && pr.part == 2) ? T(1) : T(0), T(0));
+    const Part pc = decode(c, F.ipad, nd.nI, nd.nB, L);
+    cplx<T>* out = static_cast<cplx<T>*>(a.F) + F.foff + (long long)c * F.f;
+    if (pc.part >= 2) {
+        for (int r = threadIdx.x; r < F.f; r += NT)
+            out[r] = mk<T>((r == c && pc.part == 2) ? T(1) : T(0), T(0));
         return;
     }
     const SubDesc d = a.desc[F.sub];
-    zd val = mk(0.0, 0.0);
-    if (pr.c < nd.nI || pc.c < nd.nI) {
-        const int colr = front_col(a.cols, nd, pr.c), colc = front_col(a.cols, nd, pc.c);
-        const int i1r = colr % a.n, i2r = colr / a.n, i1c = colc % a.n, i2c = colc / a.n;
-        const zd* sh3 = a.subtab + d.tab_off;   // s3 at the half lines lo - 1/2 ..
-        const zd* ish3 = sh3 + L + 1;           // 1 / (s3 h^2)
-        const zd* is3 = sh3 + 2 * L + 1;        // 1 / s3
-        if (colr == colc) {
-            const int k = pr.k;
-            if (pr.k == pc.k) {
-                const zd s23 = a.ax.inv_s[i2r] * ish3[k];
-                const zd s13 = a.ax.inv_s[i1r] * ish3[k];
-                const zd s12 = a.ax.inv_s[i1r] * a.ax.inv_sh2[i2r];
-                const zd c1 = (a.ax.sh[i1r + 1] + a.ax.sh[i1r]) * s23;
-                const zd c2 = (a.ax.sh[i2r + 1] + a.ax.sh[i2r]) * s13;
-                const zd c3 = (sh3[k + 1] + sh3[k]) * s12;
-                const long long g = (long long)colr + a.S * (d.lo - 1 + k);
-                val = ((a.ksq[g] * a.ax.inv_s[i1r]) * a.ax.inv_s[i2r]) * is3[k] - (c1 + c2 + c3);
-            } else if (pr.k - pc.k == 1 || pc.k - pr.k == 1) {
-                val = sh3[max(pr.k, pc.k)] * (a.ax.inv_s[i1r] * a.ax.inv_sh2[i2r]);
-            }
-        } else if (pr.k == pc.k) {
-            const int k = pr.k;
-            if (i2r == i2c && (i1r - i1c == 1 || i1c - i1r == 1))
-                val = a.ax.sh[max(i1r, i1c)] * (a.ax.inv_s[i2r] * ish3[k]);
-            else if (i1r == i1c && (i2r - i2c == 1 || i2c - i2r == 1))
-                val = a.ax.sh[max(i2r, i2c)] * (a.ax.inv_s[i1r] * ish3[k]);
-        }
-    }
+    const int colc = front_col(a.cols, nd, pc.c);
+    const int i1c = colc % a.n, i2c = colc / a.n;
+    const bool csep = pc.c < nd.nI;
+    const zd* sh3 = a.subtab + d.tab_off;   // s3 at the half lines lo - 1/2 ..
+    const zd* ish3 = sh3 + L + 1;           // 1 / (s3 h^2)
+    const zd* is3 = sh3 + 2 * L + 1;        // 1 / s3
+    // the children's Schur complements: this column's position in each, if any
+    const cplx<T>* U[2] = {nullptr, nullptr};
+    int cc[2] = {-1, -1};
     if (a.child0 >= 0) {
-        const long long pos_base = a.child0 + (long long)F.sub * a.nnc;
+        const long long base = a.child0 + (long long)F.sub * a.nnc;
         for (int ch = 0; ch < 2; ++ch) {
             const int io = nd.inv_off[ch];
-            const int cr = io < 0 ? -1 : a.inv[io + pr.c];
-            const int cc = io < 0 ? -1 : a.inv[io + pc.c];
-            if (cr >= 0 && cc >= 0) {
-                const NdFront C = a.fr[pos_base + nd.ch[ch]];
-                const cplx<T>* U = static_cast<const cplx<T>*>(a.Fc) + C.foff;
-                val = val + ccast<double>(U[(long long)(C.ipad + cc * L + pc.k) * C.f + C.ipad + cr * L + pr.k]);
+            cc[ch] = io < 0 ? -1 : a.inv[io + pc.c];
+            if (cc[ch] >= 0) {
+                const NdFront C = a.fr[base + nd.ch[ch]];
+                U[ch] = static_cast<const cplx<T>*>(a.Fc) + C.foff +
+                        (long long)(C.ipad + cc[ch] * L + pc.k) * C.f + C.ipad;
             }
         }
     }
-    *out = ccast<T>(val);
+    for (int r = threadIdx.x; r < F.f; r += NT) {
+        const Part pr = decode(r, F.ipad, nd.nI, nd.nB, L);
+        if (pr.part >= 2) {
+            out[r] = mk<T>((r == c && pr.part == 2) ? T(1) : T(0), T(0));
+            continue;
+        }
+        zd val = mk(0.0, 0.0);
+        if (csep || pr.c < nd.nI) {
+            const int colr = front_col(a.cols, nd, pr.c);
+            const int i1r = colr % a.n, i2r = colr / a.n;
+            if (colr == colc) {
+                const int k = pr.k;
+                if (pr.k == pc.k) {
+                    const zd s23 = a.ax.inv_s[i2r] * ish3[k];
+                    const zd s13 = a.ax.inv_s[i1r] * ish3[k];
+                    const zd s12 = a.ax.inv_s[i1r] * a.ax.inv_sh2[i2r];
+                    const zd c1 = (a.ax.sh[i1r + 1] + a.ax.sh[i1r]) * s23;
+                    const zd c2 = (a.ax.sh[i2r + 1] + a.ax.sh[i2r]) * s13;
+                    const zd c3 = (sh3[k + 1] + sh3[k]) * s12;
+                    const long long g = (long long)colr + a.S * (d.lo - 1 + k);
+                    val = ((a.ksq[g] * a.ax.inv_s[i1r]) * a.ax.inv_s[i2r]) * is3[k] - (c1 + c2 + c3);
+                } else if (pr.k - pc.k == 1 || pc.k - pr.k == 1) {
+                    val = sh3[max(pr.k, pc.k)] * (a.ax.inv_s[i1r] * a.ax.inv_sh2[i2r]);
+                }
+            } else if (pr.k == pc.k) {
+                const int k = pr.k;
+                if (i2r == i2c && (i1r - i1c == 1 || i1c - i1r == 1))
+                    val = a.ax.sh[max(i1r, i1c)] * (a.ax.inv_s[i2r] * ish3[k]);
+                else if (i1r == i1c && (i2r - i2c == 1 || i2c - i2r == 1))
+                    val = a.ax.sh[max(i2r, i2c)] * (a.ax.inv_s[i1r] * ish3[k]);
+            }
+        }
+        for (int ch = 0; ch < 2; ++ch) {
+            if (cc[ch] < 0) continue;
+            const int cr = a.inv[nd.inv_off[ch] + pr.c];
+            if (cr >= 0) val = val + ccast<double>(U[ch][cr * L + pr.k]);
+        }
+        out[r] = ccast<T>(val);
+    }
 }
 
-// factor block [F_II^-1 | F_II^-1 F_IB] = the first ipad rows of the front
+// factor block [F_II^-1 | F_II^-1 F_IB] = the first ipad rows of the front;
+// one workgroup per front column
 template <typename T>
 __global__ __launch_bounds__(NT) void nd_copyout_kernel(const NdFront* fr, const void* F, void* fac) {
     const NdFront f = fr[blockIdx.y];
-    const long long idx = (long long)blockIdx.x * NT + threadIdx.x;
-    if (idx >= (long long)f.ipad * f.f) return;
-    const int r = (int)(idx % f.ipad), c = (int)(idx / f.ipad);
-    static_cast<cplx<T>*>(fac)[f.moff + idx] =
-        static_cast<const cplx<T>*>(F)[f.foff + (long long)c * f.f + r];
+    const int c = blockIdx.x;
+    if (c >= f.f) return;
+    const cplx<T>* src = static_cast<const cplx<T>*>(F) + f.foff + (long long)c * f.f;
+    cplx<T>* dst = static_cast<cplx<T>*>(fac) + f.moff + (long long)c * f.ipad;
+    for (int r = threadIdx.x; r < f.ipad; r += NT) dst[r] = src[r];
 }
 
 struct SolveNdArgs {
@@ -407,7 +426,7 @@ hipError_t launch_nd_assemble(const asp_plan* P, const NdLevel& lv, int s0, int 
     a.n = P->n;
     a.S = P->S;
     const long long nfr = (long long)(s1 - s0) * lv.nn;
-    const unsigned gx = (unsigned)(((long long)fmax * fmax + NT - 1) / NT);
+    const unsigned gx = (unsigned)fmax;
     for (long long y0 = 0; y0 < nfr; y0 += YMAX) {
         a.fbase = lv.front0 + (long long)s0 * lv.nn + y0;
         dim3 grid(gx, (unsigned)std::min<long long>(YMAX, nfr - y0));
@@ -421,7 +440,7 @@ hipError_t launch_nd_assemble(const asp_plan* P, const NdLevel& lv, int s0, int 
 
 hipError_t launch_nd_copyout(const asp_plan* P, const NdFront* fr, int nfr, const void* Flevel,
                              int fmax, hipStream_t st) {
-    const unsigned gx = (unsigned)(((long long)fmax * fmax + NT - 1) / NT);
+    const unsigned gx = (unsigned)fmax;
     for (int y0 = 0; y0 < nfr; y0 += YMAX) {
         dim3 grid(gx, (unsigned)std::min(YMAX, nfr - y0));
         if (P->prec != ASP_PREC_FP64)
