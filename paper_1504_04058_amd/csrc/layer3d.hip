@@ -387,6 +387,10 @@ __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
         return;
     }
     if (ti == a.jp) return;
+    // a front's boundary rows in already eliminated separator columns hold
+    // -F_BI F_II^-1, which nothing reads again (the solves use its transpose
+    // K^T from the separator rows): not updated
+    if (a.fr && ti >= gm.npiv && tj < a.jp) return;
     const cplx<T>* R = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff;
     load_tile(sP, A, Bp, ti * TB, J0);
     load_tile(sQ, R, TB, 0, tj * TB);
@@ -461,6 +465,10 @@ __global__ __launch_bounds__(NT) void gj_update_bf16x3_kernel(GjArgs a) {
         return;
     }
     if (ti == a.jp) return;
+    // a front's boundary rows in already eliminated separator columns hold
+    // -F_BI F_II^-1, which nothing reads again (the solves use its transpose
+    // K^T from the separator rows): not updated
+    if (a.fr && ti >= gm.npiv && tj < a.jp) return;
     const zf* R = static_cast<const zf*>(a.Rbuf) + gm.roff;
     {
         // P(r, k) = A(ti*64 + r, J0 + k): reads coalesced over r
