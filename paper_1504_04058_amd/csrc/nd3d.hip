@@ -9,6 +9,8 @@
 // (column i1 + n i2) L + (sweep line - lo), 16 right-hand sides per entry.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "asp_internal.h"
 #include "mfma.h"
 
@@ -234,6 +236,11 @@ __global__ __launch_bounds__(NT) void nd_prod_kernel(SolveNdArgs a) {
     CTile<T> acc[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc[t].zero();
+    f32x4 p1[RT], p2[RT], p3[RT];   // FP32: the three products of each row tile
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) p1[t][e] = p2[t][e] = p3[t][e] = 0.f;
     // operands of one batch: A(row, c) for the RT row tiles, the vector at c
     auto load = [&](int c0, cplx<T> (&m)[RT][4], cplx<T> (&t)[4]) {
 #pragma unroll
@@ -263,10 +270,25 @@ __global__ __launch_bounds__(NT) void nd_prod_kernel(SolveNdArgs a) {
         for (;;) {
             const int bn = b + NW;
             if (bn < nb) load(16 * bn, mn, tn);
+            if constexpr (std::is_same<T, float>::value) {
+                // three-product form: p1 += (m_r + m_i) t_r, p2 += m_r (t_i - t_r),
+                // p3 += m_i (t_r + t_i); re = p1 - p3, im = p1 + p2
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 4; ++u) {
+                    const float td = tc[u].y - tc[u].x, ts = tc[u].x + tc[u].y;
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) cmac(acc[rt], mc[rt][u], tc[u]);
+                    for (int rt = 0; rt < RT; ++rt) {
+                        p1[rt] = Mfma<float>::mac(mc[rt][u].x + mc[rt][u].y, tc[u].x, p1[rt]);
+                        p2[rt] = Mfma<float>::mac(mc[rt][u].x, td, p2[rt]);
+                        p3[rt] = Mfma<float>::mac(mc[rt][u].y, ts, p3[rt]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) cmac(acc[rt], mc[rt][u], tc[u]);
+            }
             if (bn >= nb) break;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -276,6 +298,15 @@ __global__ __launch_bounds__(NT) void nd_prod_kernel(SolveNdArgs a) {
             }
             b = bn;
         }
+    }
+    if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc[rt].re[e] = p1[rt][e] - p3[rt][e];
+                acc[rt].im[e] = p1[rt][e] + p2[rt][e];
+            }
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
