@@ -290,7 +290,7 @@ __global__ __launch_bounds__(NT) void nd_prod_kernel(SolveNdArgs a) {
                     for (int rt = 0; rt < RT; ++rt) cmac(acc[rt], mc[rt][u], tc[u]);
             }
             if (bn >= nb) break;
-#pragma unroll
+            // the next batch becomes the current one (register renames)
             for (int u = 0; u < 4; ++u) {
                 tc[u] = tn[u];
 #pragma unroll
