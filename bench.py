@@ -300,9 +300,11 @@ def serving_run(count, prec_name):
 def paper_tables(prec_name, sizes, dim=2, widths=None, nd3d=True):
     """The paper's experiments (Tables 1-3 of Section 3.2 in 2D, Tables 4-6 of
     Section 4.2 in 3D) on this path: per field and grid, the factorization
-    time, the GMRES(40) iterations to 1e-3 for force (a) point source and (b)
-    wave packet (solved as one batch of two right-hand sides) and the solve
-    time, beside the printed iteration counts.  widths = (narrow, wide): every
+    time (a second factorization of the plan; the first, which also allocates
+    the factor memory, is reported beside it), the GMRES(40) iterations to 1e-3
+    for force (a) point source and (b) wave packet (solved as one batch of two
+    right-hand sides) and the solve time (again the second solve), beside the
+    printed iteration counts.  widths = (narrow, wide): every
     problem once more with unequal layer widths from workloads.variation_widths."""
     import json as _json
 
@@ -330,6 +332,9 @@ def paper_tables(prec_name, sizes, dim=2, widths=None, nd3d=True):
                 with asp.Plan(dim, w["c"], w["omega"], n, lb, w["gamma"], C=w["C"], prec=prec,
                               pml_aux=w.get("gamma_aux", 0), nd3d=nd3d and dim == 3) as plan:
                     torch.cuda.synchronize()
+                    a0 = time.perf_counter()
+                    plan.factor()   # first: includes allocating the factor and work memory
+                    torch.cuda.synchronize()
                     a = time.perf_counter()
                     plan.factor()
                     torch.cuda.synchronize()
@@ -347,7 +352,8 @@ def paper_tables(prec_name, sizes, dim=2, widths=None, nd3d=True):
                 rows.append({"n": n, "omega_over_2pi": (n + 1) / 8, "field": field,
                              "layers": "equal" if isinstance(lb, int) else
                              f"variation {widths[0]}/{widths[1]}", "m": m,
-                             "setup_ms": (b - a) * 1e3, "first_solve_ms": (c0 - b) * 1e3,
+                             "setup_ms": (b - a) * 1e3, "first_setup_ms": (a - a0) * 1e3,
+                             "first_solve_ms": (c0 - b) * 1e3,
                              "solve_ms": (c - c0) * 1e3,
                              "iters": [int(i) for i in iters], "max_relres": float(max(relres)),
                              "status": asp.STATUS_NAMES.get(st, st),

@@ -106,7 +106,9 @@ typedef struct {
     int max_lines;            /* largest number of sweep lines of one auxiliary problem */
     size_t factor_bytes;      /* device bytes the factors (and sweep maps) occupy once
                                  asp_factor has run; known right after asp_setup */
-    size_t workspace_bytes;   /* device bytes of the apply/GMRES workspaces now allocated */
+    size_t workspace_bytes;   /* device bytes of the apply/GMRES workspaces now allocated,
+                                 and of the 3D nested-dissection factorization's work
+                                 buffers, which stay between factorizations */
     int factored;             /* nonzero once asp_factor has succeeded */
 } asp_plan_info;
 
@@ -225,8 +227,9 @@ asp_status asp_timing_read(asp_plan* plan, int cls, int* launches, double* ms, d
 /* asp_workspace_estimate -- device bytes of the workspaces asp_gmres allocates
  * for nrhs right-hand sides and the given restart length (apply scratch,
  * sweep data, Krylov basis); host only.
- * asp_release_workspace -- free those workspaces now, keeping the factors
- * (a factor cache keeps idle plans this way); the next call allocates again.
+ * asp_release_workspace -- free those workspaces (and the factorization's
+ * kept work buffers) now, keeping the factors (a factor cache keeps idle plans
+ * this way); the next call allocates again.
  * Synchronizes the plan's stream. */
 asp_status asp_workspace_estimate(const asp_plan* plan, int nrhs, int restart, size_t* bytes);
 asp_status asp_release_workspace(asp_plan* plan);

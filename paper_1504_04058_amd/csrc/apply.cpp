@@ -428,8 +428,13 @@ extern "C" asp_status asp_release_workspace(asp_plan* P) {
     if (P->host_only) return ASP_OK;
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     void* bufs[] = {P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_V, P->d_Z, P->d_b, P->d_red,
-                    P->d_small, P->d_act, P->d_y3, P->d_g3, P->d_w3};
+                    P->d_small, P->d_act, P->d_y3, P->d_g3, P->d_w3, P->d_nd_v, P->d_nd_x,
+                    P->d_nd_lb[0], P->d_nd_lb[1], P->d_nd_rb, P->d_nd_db};
     for (void* b : bufs) dev_free(b);
+    P->d_nd_v = P->d_nd_x = nullptr;
+    P->d_nd_lb[0] = P->d_nd_lb[1] = nullptr;
+    P->d_nd_rb = P->d_nd_db = nullptr;
+    P->nd_work_bytes = 0;
     P->d_y3 = P->d_g3 = nullptr;
     P->d_w3 = nullptr;
     P->y3_elems = P->w3_elems = 0;

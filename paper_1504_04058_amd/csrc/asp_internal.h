@@ -252,6 +252,12 @@ struct asp_plan {
     NdFront* d_nd_fronts = nullptr;
     void* d_nd_v = nullptr;                   // front vectors [chunk][vtot]
     void* d_nd_x = nullptr;                   // slab vectors [chunk][xtot]
+    // the factorization's level, panel and pivot-tile buffers, kept between
+    // factorizations until asp_release_workspace
+    void* d_nd_lb[2] = {nullptr, nullptr};
+    void* d_nd_rb = nullptr;
+    void* d_nd_db = nullptr;
+    size_t nd_work_bytes = 0;
 
     // GMRES workspaces
     int kr_rhs = 0, kr_restart = 0;

@@ -311,22 +311,30 @@ asp_status nd_upload(asp_plan* P) {
 // Algorithm 3 by nested dissection: every problem of a group, level by level.
 asp_status nd_factor(asp_plan* P) {
     hipStream_t st = P->stream;
-    char* lb[2] = {nullptr, nullptr};
-    char* rb = nullptr;
-    char* db = nullptr;
     const size_t e = esz(P);
     asp_status s = ASP_OK;
-    if ((s = nd_alloc(P, &lb[0], (size_t)P->nd_lvlbuf * e)) != ASP_OK) return s;
-    if ((s = nd_alloc(P, &lb[1], (size_t)P->nd_lvlbuf * e)) != ASP_OK) {
-        (void)hipFree(lb[0]);
-        return s;
+    if (!P->d_nd_lb[0]) {
+        char* lb0 = nullptr;
+        char* lb1 = nullptr;
+        char* rb0 = nullptr;
+        char* db0 = nullptr;
+        if ((s = nd_alloc(P, &lb0, (size_t)P->nd_lvlbuf * e)) != ASP_OK ||
+            (s = nd_alloc(P, &lb1, (size_t)P->nd_lvlbuf * e)) != ASP_OK ||
+            (s = nd_alloc(P, &rb0, (size_t)P->nd_rbuf * e)) != ASP_OK ||
+            (s = nd_alloc(P, &db0, (size_t)P->nd_dbuf * NDT * NDT * e)) != ASP_OK) {
+            for (void* b : {(void*)lb0, (void*)lb1, (void*)rb0})
+                if (b) (void)hipFree(b);
+            return s;
+        }
+        P->d_nd_lb[0] = lb0;
+        P->d_nd_lb[1] = lb1;
+        P->d_nd_rb = rb0;
+        P->d_nd_db = db0;
+        P->nd_work_bytes = (2 * (size_t)P->nd_lvlbuf + (size_t)P->nd_rbuf + (size_t)P->nd_dbuf * NDT * NDT) * e;
     }
-    if ((s = nd_alloc(P, &rb, (size_t)P->nd_rbuf * e)) != ASP_OK ||
-        (s = nd_alloc(P, &db, (size_t)P->nd_dbuf * NDT * NDT * e)) != ASP_OK) {
-        for (void* b : {(void*)lb[0], (void*)lb[1], (void*)rb})
-            if (b) (void)hipFree(b);
-        return s;
-    }
+    char* lb[2] = {static_cast<char*>(P->d_nd_lb[0]), static_cast<char*>(P->d_nd_lb[1])};
+    char* rb = static_cast<char*>(P->d_nd_rb);
+    char* db = static_cast<char*>(P->d_nd_db);
     double fb = 0, fl = 0;
     int launches = 0;
     for (const auto& F : P->nd_fronts) {
@@ -363,9 +371,6 @@ asp_status nd_factor(asp_plan* P) {
         }
         t.end();
     }
-    (void)hipStreamSynchronize(st);
-    for (void* b : {(void*)lb[0], (void*)lb[1], (void*)rb, (void*)db})
-        if (b) (void)hipFree(b);
     return s;
 }
 

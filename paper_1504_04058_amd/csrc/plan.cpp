@@ -369,7 +369,7 @@ extern "C" void asp_destroy(asp_plan* P) {
                     P->d_T, P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_y, P->d_V, P->d_Z, P->d_b,
                     P->d_red, P->d_small, P->d_act, P->d_e3, P->d_gv3, P->d_y3,
                     P->d_g3, P->d_w3, P->d_nd_nodes, P->d_nd_cols, P->d_nd_inv, P->d_nd_fronts,
-                    P->d_nd_v, P->d_nd_x};
+                    P->d_nd_v, P->d_nd_x, P->d_nd_lb[0], P->d_nd_lb[1], P->d_nd_rb, P->d_nd_db};
     (void)hipStreamSynchronize(P->stream);
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -396,7 +396,7 @@ extern "C" asp_status asp_info(const asp_plan* P, asp_plan_info* info) {
     info->n_sub = (int)P->subs.size();
     info->max_lines = P->max_L;
     info->factor_bytes = P->fac_bytes + P->t_bytes;
-    info->workspace_bytes = P->ws_bytes + P->kr_bytes;
+    info->workspace_bytes = P->ws_bytes + P->kr_bytes + P->nd_work_bytes;
     info->factored = P->factored ? 1 : 0;
     return ASP_OK;
 }
