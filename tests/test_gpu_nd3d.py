@@ -138,3 +138,24 @@ def test_nd_paper_gmres(field):
         assert abs(int(it[k]) - refs[k]) <= 1
         bvec = f[k] / P.scale()
         assert np.linalg.norm(bvec - A @ u[k]) / np.linalg.norm(bvec) <= w["tol"] * (1 + 1e-9)
+
+
+def test_nd_factorization_groups_match_block_recurrence():
+    """3D n = 63 (gamma = 8, b = 4) in FP64: the nested-dissection fronts do
+    not fit one factorization group (the problems are factored in two groups
+    that share the level buffers), and the apply still equals the
+    block-recurrence apply to rounding."""
+    print("nd two groups vs block recurrence n=63 fp64", flush=True)
+    n = 63
+    c = workloads.velocity_lens3d(n)
+    P = Problem(3, n, 2 * math.pi * (n + 1) / 8, 8, 25.0, 4, c)
+    rng = np.random.default_rng(23)
+    r = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
+    with _plan(P, asp.ASP_PREC_FP64, nd=True) as plan:
+        plan.factor()
+        z_nd = host(plan.apply(dev(r)))
+    with _plan(P, asp.ASP_PREC_FP64, nd=False) as plan:
+        plan.factor()
+        z_bl = host(plan.apply(dev(r)))
+    for k in range(2):
+        assert rel(z_nd[k], z_bl[k]) < 1e-11, k
