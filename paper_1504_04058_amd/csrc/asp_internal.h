@@ -438,9 +438,14 @@ struct NdLevel {
 // children's Schur complements (from Fchild); F in Flevel
 hipError_t launch_nd_assemble(const asp_plan* P, const NdLevel& lv, int s0, int s1, void* Flevel,
                               const void* Fchild, int fmax, hipStream_t st);
-// Gauss-Jordan panel jp of the separator part of nfr fronts
+// Gauss-Jordan panel jp of the separator part of nfr fronts.  mode 0: the
+// whole trailing update; panels in pairs (look-ahead), Rbuf holding three
+// slots of f x 64 per front: mode 1 for the first of a pair (its rows and
+// columns kept, only the second panel's tiles updated; the whole update for a
+// front without a second panel), mode 2 for the second (both panels' updates
+// applied to the rest in one pass)
 hipError_t launch_gj_fronts(const asp_plan* P, const NdFront* fr, int nfr, void* Flevel, int jp,
-                            int ntmax, void* Rbuf, void* Dbuf, hipStream_t st);
+                            int ntmax, void* Rbuf, void* Dbuf, int mode, hipStream_t st);
 // [F_II^-1 | F_II^-1 F_IB] of each front into the factor buffer
 hipError_t launch_nd_copyout(const asp_plan* P, const NdFront* fr, int nfr, const void* Flevel,
                              int fmax, hipStream_t st);

@@ -227,7 +227,14 @@ struct GjArgs {
     int* flag;
     long long rstride;
     int k, jp, ntmax;
+    // fronts, two panels per pass (look-ahead): the panel rows of panel J1 in
+    // R slot 0 and of J2 in slot 1 (rsel), its columns kept in slot 2 (save_c);
+    // the update after J1 covers only what panel J2 needs (GJ_NARROW), the one
+    // after J2 applies both panels to the rest (GJ_COMBINED)
+    int mode, rsel, save_c;
 };
+
+enum { GJ_FULL = 0, GJ_NARROW = 1, GJ_COMBINED = 2 };
 
 // the matrix of job js: block k of a problem (all panels pivot), or a front
 // whose first ipad / 64 panels pivot
@@ -341,15 +348,20 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j].zero();
+    // panel buffers of a front: slots of Bp x 64 entries (rows of J1, rows of
+    // J2, columns of J1), column-major with leading dimension 64 / Bp
+    const long long slot = (long long)Bp * TB;
     if (rowt) {
         load_tile(sA, A, Bp, t * TB, J0);
         __syncthreads();
         tile_product(sA, sD, acc);
         store_acc(A, Bp, t * TB, J0, acc, T(-1));
+        if (a.save_c)
+            store_acc(static_cast<cplx<T>*>(a.Rbuf) + gm.roff + 2 * slot, Bp, t * TB, 0, acc, T(-1));
     } else {
         load_tile(sA, A, Bp, J0, t * TB);
         __syncthreads();
-        cplx<T>* R = static_cast<cplx<T>*>(a.Rbuf) + gm.roff;
+        cplx<T>* R = static_cast<cplx<T>*>(a.Rbuf) + gm.roff + a.rsel * slot;
 #pragma unroll 4
         for (int e = 0; e < 16; ++e) {
             const int c = cg + 4 * e;
@@ -387,17 +399,32 @@ __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
         return;
     }
     if (ti == a.jp) return;
+    // GJ_NARROW (a front with a next panel): only the next panel's row and
+    // column tiles now, the rest with the next panel's update
+    const bool narrow = a.mode == GJ_NARROW && a.jp + 1 < gm.npiv;
+    if (narrow && ti != a.jp + 1 && tj != a.jp + 1) return;
     // a front's boundary rows in already eliminated separator columns hold
     // -F_BI F_II^-1, which nothing reads again (the solves use its transpose
     // K^T from the separator rows): not updated
-    if (a.fr && ti >= gm.npiv && tj < a.jp) return;
-    const cplx<T>* R = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff;
+    if (!narrow && a.fr && ti >= gm.npiv && tj < a.jp) return;
+    const long long slot = (long long)Bp * TB;
+    const cplx<T>* R = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff + a.rsel * slot;
     load_tile(sP, A, Bp, ti * TB, J0);
     load_tile(sQ, R, TB, 0, tj * TB);
     CTile<T> acc[2][2];
     load_acc(acc, A, Bp, ti * TB, tj * TB);
     __syncthreads();
     tile_product(sP, sQ, acc);
+    if (a.mode == GJ_COMBINED && ti != a.jp - 1 && tj != a.jp - 1) {
+        // the deferred update of panel J1 = jp - 1: its columns (slot 2) times
+        // its rows (slot 0)
+        const cplx<T>* R1 = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff;
+        __syncthreads();
+        load_tile(sP, R1 + 2 * slot, Bp, ti * TB, 0);
+        load_tile(sQ, R1, TB, 0, tj * TB);
+        __syncthreads();
+        tile_product(sP, sQ, acc);
+    }
     store_acc(A, Bp, ti * TB, tj * TB, acc, T(1));
 }
 
@@ -832,7 +859,7 @@ void launch_gj(const asp_plan* P, const GjArgs& a, int njobs, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_gj_fronts(const asp_plan* P, const NdFront* fr, int nfr, void* Flevel, int jp,
-                            int ntmax, void* Rbuf, void* Dbuf, hipStream_t st) {
+                            int ntmax, void* Rbuf, void* Dbuf, int mode, hipStream_t st) {
     const size_t esz = P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd);
     constexpr int YMAX = 65535;
     for (int y0 = 0; y0 < nfr; y0 += YMAX) {
@@ -844,6 +871,9 @@ hipError_t launch_gj_fronts(const asp_plan* P, const NdFront* fr, int nfr, void*
         a.flag = P->d_flag;
         a.jp = jp;
         a.ntmax = ntmax;
+        a.mode = mode;
+        a.rsel = mode == GJ_COMBINED ? 1 : 0;
+        a.save_c = mode == GJ_NARROW ? 1 : 0;
         launch_gj(P, a, std::min(YMAX, nfr - y0), st);
     }
     return hipGetLastError();
@@ -855,6 +885,9 @@ hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int
     a.desc = P->d_desc;
     a.jobs = jobs;
     a.fr = nullptr;
+    a.mode = GJ_FULL;
+    a.rsel = 0;
+    a.save_c = 0;
     a.fac = P->d_fac;
     a.Rbuf = Rbuf;
     a.Dbuf = Dbuf;

@@ -37,6 +37,10 @@ long long pad64(long long x) { return (x + NDT - 1) / NDT * NDT; }
 
 size_t esz(const asp_plan* P) { return P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd); }
 
+// separator panels eliminated two at a time (one pass of the trailing update
+// over the front per pair); the bf16-split updates keep one pass per panel
+bool look_ahead(const asp_plan* P) { return P->prec != ASP_PREC_BF16X3; }
+
 struct TNode {
     int depth = 0;
     int ch[2] = {-1, -1};
@@ -290,7 +294,7 @@ asp_status nd_setup(asp_plan* P) {
                 F.foff = fo;
                 F.roff = ro;
                 fo += (long long)F.f * F.f;
-                ro += (long long)F.f * NDT;
+                ro += (long long)F.f * NDT * (look_ahead(P) ? 3 : 1);
             }
             P->nd_lvlbuf = std::max(P->nd_lvlbuf, fo);
             P->nd_rbuf = std::max(P->nd_rbuf, ro);
@@ -361,8 +365,16 @@ asp_status nd_factor(asp_plan* P) {
                 for (long long i = lv.front0 + (long long)gr[0] * lv.nn; i < lv.front0 + (long long)gr[1] * lv.nn; ++i)
                     np = std::max(np, P->nd_fronts[i].ipad / NDT);
                 hipError_t err = launch_nd_assemble(P, lv, gr[0], gr[1], lb[d & 1], lb[(d + 1) & 1], fmax, st);
-                for (int jp = 0; jp < np && err == hipSuccess; ++jp)
-                    err = launch_gj_fronts(P, fr, nfr, lb[d & 1], jp, fmax / NDT, rb, db, st);
+                if (look_ahead(P)) {
+                    for (int jp = 0; jp < np && err == hipSuccess; jp += 2) {
+                        err = launch_gj_fronts(P, fr, nfr, lb[d & 1], jp, fmax / NDT, rb, db, 1, st);
+                        if (err == hipSuccess && jp + 1 < np)
+                            err = launch_gj_fronts(P, fr, nfr, lb[d & 1], jp + 1, fmax / NDT, rb, db, 2, st);
+                    }
+                } else {
+                    for (int jp = 0; jp < np && err == hipSuccess; ++jp)
+                        err = launch_gj_fronts(P, fr, nfr, lb[d & 1], jp, fmax / NDT, rb, db, 0, st);
+                }
                 if (err == hipSuccess) err = launch_nd_copyout(P, fr, nfr, lb[d & 1], fmax, st);
                 if (err != hipSuccess)
                     s = plan_fail(P, ASP_ERR_DEVICE, std::string("nested dissection factor launch: ") +
