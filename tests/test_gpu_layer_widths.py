@@ -119,3 +119,22 @@ def test_unequal_width_gmres_iterations():
         assert abs(int(it[k]) - refs[k]) <= 1
         bvec = f[k] / P.scale()
         assert np.linalg.norm(bvec - A @ u[k]) / np.linalg.norm(bvec) <= w["tol"] * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("d,n,gamma,aux,w", [(2, 63, 12, 4, (1, 1, 9, 2, 4, 8, 8, 8)),
+                                             (3, 31, 8, 4, (1, 4, 2, 3, 7))])
+def test_unequal_widths_with_thin_auxiliary_pml(d, n, gamma, aux, w):
+    """Both options of the Section 3.1 remarks together: unequal layers and
+    thinner auxiliary pads; the apply against the oracle in FP64."""
+    print(f"layer widths + thin pml d={d} n={n} aux={aux} w={w}", flush=True)
+    c = workloads.velocity_random(n, d, seed=4, width=3.0 if d == 3 else 8.0)
+    P = Problem(d, n, 2 * math.pi * (n + 1) / 8, gamma, 25.0, list(w), c, gamma_aux=aux)
+    M = Preconditioner(P)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
+    with asp.Plan(d, P.c, P.omega, n, list(w), gamma, C=P.C, prec=asp.ASP_PREC_FP64,
+                  pml_aux=aux) as plan:
+        plan.factor()
+        z = host(plan.apply(dev(r)))
+    for k in range(2):
+        assert rel(z[k], M.apply(r[k])) < 1e-11
