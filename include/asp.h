@@ -144,13 +144,14 @@ asp_status asp_factor(asp_plan* plan);
 
 /* asp_apply -- z = M^-1 r, Algorithm 2 (2D) / 4 (3D): the m M-solves, the
  * right-going and left-going sweeps over the boundary values, and the sum.
+ *   nrhs >= 1 right-hand sides.
  *   r  device, nrhs * N complex128, symmetric-form residuals; read only.
  *   z  device, nrhs * N complex128, written; must not alias r.
  * Errors: ASP_ERR_STATE (not factored), ASP_ERR_ARG, ASP_ERR_OOM, ASP_ERR_DEVICE. */
 asp_status asp_apply(asp_plan* plan, const void* r, void* z, int nrhs);
 
 /* asp_matvec -- y = A x with the symmetric-form 5-point (2D) / 7-point (3D)
- * PML operator of eq. (2D) / (3D), complex double.
+ * PML operator of eq. (2D) / (3D), complex double, for nrhs >= 1 vectors.
  *   x  device, nrhs * N complex128;  y  device, nrhs * N complex128, no alias.
  * Errors: ASP_ERR_ARG, ASP_ERR_DEVICE. */
 asp_status asp_matvec(asp_plan* plan, const void* x, void* y, int nrhs);
@@ -162,7 +163,8 @@ asp_status asp_matvec(asp_plan* plan, const void* x, void* y, int nrhs);
  * ||f/prod s - A u|| / ||f/prod s|| is <= tol.
  *   f       device, nrhs * N complex128, the PHYSICAL right-hand side f.
  *   u       device, nrhs * N complex128, written with the solution.
- *   tol     > 0;  restart >= 1;  maxit >= 1 (total Arnoldi steps per RHS).
+ *   nrhs    >= 1.
+ *   tol     > 0;  1 <= restart <= 64;  maxit >= 1 (total Arnoldi steps per RHS).
  *   iters   HOST, [nrhs]: Arnoldi steps (= preconditioner applies) per RHS.
  *   relres  HOST, [nrhs]: final true relative residual per RHS.
  * Factors the plan first if needed.  Workspaces ((2 restart + 3) * nrhs * N
@@ -178,7 +180,7 @@ asp_status asp_gmres(asp_plan* plan, const void* f, void* u, int nrhs, double to
  *   in   device; M: nrhs * (N_p) values y on X_p (column-major restriction);
  *        R/L: nrhs * n^(dim-1) boundary values w.  complex128.
  *   out  device; nrhs * N_p complex128: the solution restricted to X_p.
- * N_p = n^(dim-1) * |X_p|.  Requires a factored plan.
+ * N_p = n^(dim-1) * |X_p|; nrhs >= 1.  Requires a factored plan.
  * Errors: ASP_ERR_ARG, ASP_ERR_STATE, ASP_ERR_OOM, ASP_ERR_DEVICE. */
 asp_status asp_subsolve(asp_plan* plan, int kind, int p, const void* in, void* out, int nrhs);
 

@@ -196,6 +196,35 @@ def test_host_only_plan_refuses_device_calls(L):
         asp.asp_destroy(plan)
 
 
+def test_empty_and_bad_solve_arguments_rejected(L):
+    """Zero or negative right-hand-side counts, bad GMRES controls and
+    out-of-range auxiliary problems are argument errors, caught before the
+    plan's state or the device is looked at (a host-only plan)."""
+    plan = _host_plan(2, 63, 4, 12)
+    a, b = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    it = (ctypes.c_int * 2)()
+    rr = (ctypes.c_double * 2)()
+    try:
+        for nrhs in (0, -1):
+            assert L.asp_apply(plan, a, b, nrhs) == asp.ASP_ERR_ARG
+            assert L.asp_matvec(plan, a, b, nrhs) == asp.ASP_ERR_ARG
+            assert L.asp_subsolve(plan, asp.ASP_SUB_M, 1, a, b, nrhs) == asp.ASP_ERR_ARG
+            assert L.asp_gmres(plan, a, b, nrhs, 1e-6, 20, 100, it, rr) == asp.ASP_ERR_ARG
+        assert L.asp_apply(plan, a, a, 1) == asp.ASP_ERR_ARG                # aliasing
+        assert L.asp_gmres(plan, a, a, 1, 1e-6, 20, 100, it, rr) == asp.ASP_ERR_ARG
+        for tol, restart, maxit in ((0.0, 20, 100), (-1e-6, 20, 100), (float("nan"), 20, 100),
+                                    (1e-6, 0, 100), (1e-6, 65, 100), (1e-6, 20, 0)):
+            assert L.asp_gmres(plan, a, b, 1, tol, restart, maxit, it, rr) == asp.ASP_ERR_ARG
+        assert L.asp_gmres(plan, a, b, 1, 1e-6, 20, 100, None, rr) == asp.ASP_ERR_ARG
+        m = asp.asp_info(plan)["m"]
+        # G~^M_p for p = 1..m, G~^R_p for p = 2..m, G~^L_p for p = 1..m-1
+        for kind, p in ((asp.ASP_SUB_M, 0), (asp.ASP_SUB_M, m + 1), (asp.ASP_SUB_R, 1),
+                        (asp.ASP_SUB_L, m), (7, 1)):
+            assert L.asp_subsolve(plan, kind, p, a, b, 1) == asp.ASP_ERR_ARG
+    finally:
+        asp.asp_destroy(plan)
+
+
 @pytest.mark.parametrize("dim,n,b,gamma,prec", [(2, 1023, 4, 12, 1), (2, 63, 4, 12, 0),
                                                 (3, 63, 4, 8, 1), (3, 31, 4, 8, 0)])
 def test_planned_factor_bytes(dim, n, b, gamma, prec):
