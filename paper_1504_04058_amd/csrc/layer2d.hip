@@ -687,10 +687,15 @@ constexpr int SW_W = 8;        // wavefronts per block, splitting the columns of
 
 // W_out = T W_in for 16 outputs i1 and 32 right-hand sides: a complex product
 // on the matrix cores.  Each wavefront takes a contiguous eighth of the
-// columns of T, four k-steps of operands in flight at a time; the partial
-// tiles meet in LDS and are added in wavefront order (fixed, so a result does
-// not depend on the other right-hand sides or on scheduling).  The two blocks
-// of a row tile are 64 block ids apart and so share an XCD and its L2 copy of T.
+// columns of T in batches of 16 (four k-steps); two batches sit in two fixed
+// register slots, and a slot is refilled right after its products, so one
+// batch is in flight while the other is multiplied.  Every load is issued
+// (columns past the wavefront's range read its last column again) and the
+// columns past the range are zeroed where used: a value selected at the load
+// makes the compiler wait for that load at once.  The partial tiles meet in
+// LDS and are added in wavefront order (fixed, so a result does not depend on
+// the other right-hand sides or on scheduling).  The two blocks of a row tile
+// are 64 block ids apart and so share an XCD and its L2 copy of T.
 template <typename T>
 __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
     __shared__ cplx<T> red[SW_W][2][64][4];
@@ -708,7 +713,16 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
     // past n are padding, their outputs are not stored)
     const cplx<T>* __restrict__ Tt = Tm + (long long)blockIdx.x * n * 16 + li;
     const int per = (n + 16 * SW_W - 1) / (16 * SW_W) * 16;
-    const int cb = wv * per;
+    const int cb = wv * per, ce = min(cb + per, n);
+    // one output per thread (tile t2o, lane l2, element v_); its u~ value is
+    // read now, ahead of the products
+    const int tid = threadIdx.x;
+    const int v_ = tid & 3, l2 = (tid >> 2) & 63, t2o = tid >> 8;
+    const int ko = k0 + Mfma<T>::row(l2, v_);
+    const int slot = s0 + 16 * t2o + (l2 & 15);
+    const bool okout = ko < n && slot < a.nact;
+    const int id = okout ? (a.act ? a.act[slot] : slot) : 0;
+    const zd uval = a.Ugrid[(long long)id * a.N + (long long)n * (a.line[side] - 1) + (okout ? ko : 0)];
     // FP32: three real products per complex one (p1 = (ar + ai) br,
     // p2 = ar (bi - br), p3 = ai (br + bi); re = p1 - p3, im = p1 + p2), the
     // matrix-core work of the step down by a quarter; FP64: the four products
@@ -718,36 +732,48 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
     acc[1].zero();
     kacc[0].zero();
     kacc[1].zero();
-    // operands of 4 k-steps (16 columns); the next batch is loaded before the
-    // current batch's products
     struct Batch {
         cplx<T> av[4], bv[4][2];
+        bool ok[4];
     };
     auto load = [&](Batch& B, int c0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = c0 + 4 * u + lk;
-            const int cc = min(c, n - 1);
+            const int cc = min(c, ce - 1);
             B.av[u] = Tt[(long long)cc * 16];
 #pragma unroll
             for (int t2 = 0; t2 < 2; ++t2) B.bv[u][t2] = Wi[(long long)cc * ws + s0 + 16 * t2 + li];
-            if (c >= n) B.av[u] = mk<T>(T(0), T(0));
+            B.ok[u] = c < ce;
         }
     };
-    Batch cur, nxt;
-    load(cur, cb);
-    for (int c0 = cb; c0 < cb + per; c0 += 16) {
-        if (c0 + 16 < cb + per) load(nxt, c0 + 16);
+    auto multiply = [&](const Batch& B) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u) {
+            const cplx<T> av = csel(B.ok[u], B.av[u], mk<T>(T(0), T(0)));
 #pragma unroll
             for (int t2 = 0; t2 < 2; ++t2) {
                 if constexpr (sizeof(T) == 4)
-                    kmac3(kacc[t2], cur.av[u], cur.bv[u][t2]);
+                    kmac3(kacc[t2], av, B.bv[u][t2]);
                 else
-                    cmac(acc[t2], cur.av[u], cur.bv[u][t2]);
+                    cmac(acc[t2], av, B.bv[u][t2]);
             }
-        cur = nxt;
+        }
+    };
+    Batch b0, b1;
+    load(b0, cb);
+    load(b1, cb + 16);
+    // nothing outstanding on entry: the waits in the loop count its own loads
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int c0 = cb; c0 < cb + per; c0 += 32) {
+        multiply(b0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(b0, c0 + 32);
+        __builtin_amdgcn_sched_barrier(0);
+        multiply(b1);
+        __builtin_amdgcn_sched_barrier(0);
+        load(b1, c0 + 48);
+        __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (sizeof(T) == 4) {
 #pragma unroll
@@ -763,18 +789,11 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) red[wv][t2][l][v] = mk<T>(acc[t2].re[v], acc[t2].im[v]);
     __syncthreads();
-    // one output per thread: tile t2, lane l2, element v
-    const int tid = threadIdx.x;
-    const int v = tid & 3, l2 = (tid >> 2) & 63, t2 = tid >> 8;
-    const int ko = k0 + Mfma<T>::row(l2, v);
-    const int slot = s0 + 16 * t2 + (l2 & 15);
-    if (ko >= n || slot >= a.nact) return;
-    cplx<T> sum = red[0][t2][l2][v];
+    if (!okout) return;
+    cplx<T> sum = red[0][t2o][l2][v_];
 #pragma unroll
-    for (int q = 1; q < SW_W; ++q) sum = sum + red[q][t2][l2][v];
-    const int id = a.act ? a.act[slot] : slot;
-    const zd val = ccast<double>(sum) +
-                   a.Ugrid[(long long)id * a.N + (long long)n * (a.line[side] - 1) + ko];
+    for (int q = 1; q < SW_W; ++q) sum = sum + red[q][t2o][l2][v_];
+    const zd val = ccast<double>(sum) + uval;
     a.W[a.w_out[side] + (long long)id * n + ko] = val;
     reinterpret_cast<cplx<T>*>(a.Wt_out[side])[(long long)ko * ws + slot] = ccast<T>(val);
 }
