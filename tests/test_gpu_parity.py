@@ -124,6 +124,26 @@ def test_apply(n, gamma, b, prec, tol):
         assert rel(z[k], M.apply(r[k])) < tol
 
 
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
+def test_apply_odd_batch_count_per_sweep_wavefront(prec, tol):
+    """n = 300: each of the eight wavefronts of a sweep step takes 48 columns
+    of the boundary map, three batches of 16, so the second register slot's
+    last batch lies wholly past the wavefront's range and must add nothing;
+    the seventh wavefront's range ends past n and the eighth lies wholly past
+    it."""
+    n, gamma, b = 300, 12, 4
+    assert (n + 127) // 128 * 16 == 48 and 6 * 48 < n < 7 * 48
+    P = _problem(n, gamma, b)
+    M = Preconditioner(P)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
+    with _plan(P, prec) as plan:
+        plan.factor()
+        z = host(plan.apply(dev(r)))
+    for k in range(2):
+        assert rel(z[k], M.apply(r[k])) < tol
+
+
 def test_single_and_two_layers():
     for n, gamma, b in [(16, 5, 8), (17, 5, 8)]:     # m = 1 and m = 2
         P = _problem(n, gamma, b, velocity="constant", freq=2)
