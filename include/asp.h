@@ -110,6 +110,11 @@ typedef struct {
                                  and of the 3D nested-dissection factorization's work
                                  buffers, which stay between factorizations */
     int factored;             /* nonzero once asp_factor has succeeded */
+    size_t factor_work_bytes; /* device bytes of the work buffers asp_factor allocates besides
+                                 the factors: the forward-substitution scratch of the 2D
+                                 boundary-map solves, the 3D level, panel and pivot buffers.
+                                 They stay allocated (and are counted in workspace_bytes)
+                                 until asp_release_workspace; known right after asp_setup */
 } asp_plan_info;
 
 /* Fill *opts with the defaults (C = 25, FP64, null stream, device plan). */

@@ -42,7 +42,7 @@ class asp_plan_info(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("m", ctypes.c_int),
                 ("n_sub", ctypes.c_int), ("max_lines", ctypes.c_int),
                 ("factor_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
-                ("factored", ctypes.c_int)]
+                ("factored", ctypes.c_int), ("factor_work_bytes", ctypes.c_size_t)]
 
 
 _lib = None

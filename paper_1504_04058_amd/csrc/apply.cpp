@@ -73,6 +73,22 @@ void solve_cost(const asp_plan* P, int sub0, int nsub, int nact, double io_vecto
 
 }  // namespace
 
+size_t solve_scratch_bytes(const asp_plan* P) {
+    return (size_t)P->y_waves * solve_scratch_per_block(P) * elem_bytes(P);
+}
+
+// workgroups of one boundary-map launch: all the unit-data solves, at most
+// TRANSFER_GROUPS at a time
+static long long transfer_groups(const asp_plan* P) {
+    return std::min<long long>(TRANSFER_GROUPS,
+                               (long long)std::max(2 * P->m - 4, 1) * groups_of(P->n, P->LR_RL));
+}
+
+size_t factor_work_estimate(const asp_plan* P) {
+    if (P->dim == 3) return P->nd ? nd_factor_work_estimate(P) : factor3d_work_estimate(P);
+    return (size_t)transfer_groups(P) * solve_scratch_per_block(P) * elem_bytes(P);
+}
+
 double factor_bytes_of(const asp_plan* P, const SubDesc& d) {
     const double B = (P->dim == 2) ? d.L : (double)P->n * d.L;
     return (double)P->n * B * B * elem_bytes(P);
@@ -170,8 +186,7 @@ asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
     asp_status s = ensure_y(P, apply_groups(P, nrhs));
     if (s != ASP_OK) return s;
     P->ws_rhs = nrhs;
-    P->ws_bytes = (2 * vec + wlen) * sizeof(zd) +
-                  (size_t)P->y_waves * solve_scratch_per_block(P) * elem_bytes(P);
+    P->ws_bytes = (2 * vec + wlen) * sizeof(zd) + (size_t)P->wt_elems * elem_bytes(P);
     return ASP_OK;
 }
 
@@ -306,9 +321,7 @@ extern "C" asp_status asp_factor(asp_plan* P) {
         if (dev_alloc(P, &t, P->t_bytes) != ASP_OK) return ASP_ERR_OOM;
         P->d_T = t;
     }
-    asp_status s = ensure_y(
-        P, std::min<long long>(TRANSFER_GROUPS, (long long)std::max(2 * P->m - 4, 1) *
-                                                    groups_of(P->n, P->LR_RL)));
+    asp_status s = ensure_y(P, transfer_groups(P));
     if (s != ASP_OK) return s;
     ASP_HIP(P, hipMemsetAsync(P->d_flag, 0, sizeof(int), P->stream));
     {
@@ -447,11 +460,9 @@ extern "C" asp_status asp_release_workspace(asp_plan* P) {
     P->wt_elems = 0;
     P->kr_rhs = P->kr_restart = 0;
     P->kr_bytes = 0;
-    // the solve scratch is shared with asp_factor; keep it only if small
-    if ((double)P->y_waves * solve_scratch_per_block(P) * elem_bytes(P) > 256.0 * (1 << 20)) {
-        dev_free(P->d_y);
-        P->d_y = nullptr;
-        P->y_waves = 0;
-    }
+    // the layer solves' scratch (shared by asp_factor and the applies)
+    dev_free(P->d_y);
+    P->d_y = nullptr;
+    P->y_waves = 0;
     return ASP_OK;
 }

@@ -95,6 +95,11 @@ size_t workspace_estimate3(const asp_plan* P, int nrhs) {
     return (size_t)(2.0 * vec + 2.0 * ye + we);
 }
 
+size_t factor3d_work_estimate(const asp_plan* P) {
+    const size_t nsub = P->subs.size();
+    return nsub * ((size_t)P->Bmax * TB3 + (size_t)TB3 * TB3) * esz(P);
+}
+
 // Algorithm 3: every auxiliary problem at once, block k after block k-1; each
 // block inverse is a sequence of 64-wide Gauss-Jordan panels.
 asp_status factor3d(asp_plan* P) {

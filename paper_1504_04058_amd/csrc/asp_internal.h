@@ -407,6 +407,12 @@ hipError_t launch_scale_vec(const zd* w, zd* v, const zd* scal, long long N, con
 // host-side pieces shared by the entry points
 asp_status ensure_apply_ws(asp_plan* P, int nrhs);
 asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
+// device bytes of the 2D layer solves' forward-substitution scratch now allocated
+size_t solve_scratch_bytes(const asp_plan* P);
+// device bytes of the work buffers asp_factor allocates besides the factors
+size_t factor_work_estimate(const asp_plan* P);
+size_t nd_factor_work_estimate(const asp_plan* P);
+size_t factor3d_work_estimate(const asp_plan* P);
 // algorithmic bytes of one auxiliary problem's factor (n dense L x L blocks in
 // 2D, n dense nL x nL blocks in 3D)
 double factor_bytes_of(const asp_plan* P, const SubDesc& d);

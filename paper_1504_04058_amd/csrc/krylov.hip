@@ -171,13 +171,25 @@ __global__ __launch_bounds__(BS) void axpy_multi_kernel(const zd* __restrict__ V
         cf[k] = (k < ni) ? coef[(long long)rhs * coef_stride + i0 + k] : mk(0.0, 0.0);
     zd* wr = w + (long long)rhs * N;
     double nrm = 0.0;
+    // a zero coefficient skips its vector (it may be unset, even NaN): every
+    // vector is loaded (index clamped to a valid one) and the skip is a select,
+    // so that the CHUNK loads of an element are in flight together instead of
+    // each waiting under its own branch
+    bool use[CHUNK];
+    const zd* vp[CHUNK];
+#pragma unroll
+    for (int k = 0; k < CHUNK; ++k) {
+        use[k] = k < ni && (cf[k].x != 0.0 || cf[k].y != 0.0);
+        vp[k] = V + (long long)(i0 + (k < ni ? k : 0)) * vstride + (long long)rhs * N;
+    }
     for (long long idx = (long long)blockIdx.x * BS + threadIdx.x; idx < N;
          idx += (long long)nblk * BS) {
+        zd x[CHUNK];
+#pragma unroll
+        for (int k = 0; k < CHUNK; ++k) x[k] = vp[k][idx];
         zd v = wr[idx];
 #pragma unroll
-        for (int k = 0; k < CHUNK; ++k)   // a zero coefficient skips its vector (it may be unset)
-            if (k < ni && (cf[k].x != 0.0 || cf[k].y != 0.0))
-                v = v - cf[k] * V[(long long)(i0 + k) * vstride + (long long)rhs * N + idx];
+        for (int k = 0; k < CHUNK; ++k) v = csel(use[k], v - cf[k] * x[k], v);
         wr[idx] = v;
         nrm += abs2(v);
     }

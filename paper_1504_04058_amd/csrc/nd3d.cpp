@@ -133,7 +133,9 @@ void solve_cost_nd(const asp_plan* P, int sub, int nact, double* bytes, double* 
         const int nn = P->nd_lvl_nodes[d];
         for (int p = 0; p < nn; ++p) {
             const NdFront& F = P->nd_fronts[P->nd_lvl_front0[d] + (long long)sub * nn + p];
-            const double kb = (double)F.ipad * (F.f - F.ipad), all = (double)F.ipad * F.f;
+            const NdNode& nd = P->nd_nodes[F.node];
+            const double sI = (double)nd.nI * F.L, tB = (double)nd.nB * F.L;   // unpadded
+            const double kb = sI * tB, all = sI * (sI + tB);
             e += kb + all;
             fl += 8.0 * (kb + all);
         }
@@ -334,16 +336,23 @@ asp_status nd_factor(asp_plan* P) {
         P->d_nd_lb[1] = lb1;
         P->d_nd_rb = rb0;
         P->d_nd_db = db0;
-        P->nd_work_bytes = (2 * (size_t)P->nd_lvlbuf + (size_t)P->nd_rbuf + (size_t)P->nd_dbuf * NDT * NDT) * e;
+        P->nd_work_bytes = nd_factor_work_estimate(P);
     }
     char* lb[2] = {static_cast<char*>(P->d_nd_lb[0]), static_cast<char*>(P->d_nd_lb[1])};
     char* rb = static_cast<char*>(P->d_nd_rb);
     char* db = static_cast<char*>(P->d_nd_db);
     double fb = 0, fl = 0;
     int launches = 0;
+    // the method's work, from the unpadded separator (s) and boundary (t)
+    // unknowns of each front: LU elimination of the separator, 8 (s^3/3 +
+    // s^2 t + s t^2) real flops, and [F_II^-1 | F_II^-1 F_IB] written once.
+    // The Gauss-Jordan kernels execute more (the whole padded front, the
+    // explicit inverse), which counts as overhead, not as work.
     for (const auto& F : P->nd_fronts) {
-        fb += (double)F.ipad * F.f * e;
-        fl += 8.0 * (double)F.f * F.f * F.ipad;
+        const NdNode& nd = P->nd_nodes[F.node];
+        const double sI = (double)nd.nI * F.L, tB = (double)nd.nB * F.L;
+        fb += sI * (sI + tB) * e;
+        fl += 8.0 * (sI * sI * sI / 3.0 + sI * sI * tB + sI * tB * tB);
     }
     for (const auto& gr : P->nd_groups)
         for (int d = 0; d < P->nd_levels; ++d) {
@@ -384,6 +393,10 @@ asp_status nd_factor(asp_plan* P) {
         t.end();
     }
     return s;
+}
+
+size_t nd_factor_work_estimate(const asp_plan* P) {
+    return (2 * (size_t)P->nd_lvlbuf + (size_t)P->nd_rbuf + (size_t)P->nd_dbuf * NDT * NDT) * esz(P);
 }
 
 size_t nd_workspace_estimate(const asp_plan* P, int nrhs) {

@@ -396,8 +396,9 @@ extern "C" asp_status asp_info(const asp_plan* P, asp_plan_info* info) {
     info->n_sub = (int)P->subs.size();
     info->max_lines = P->max_L;
     info->factor_bytes = P->fac_bytes + P->t_bytes;
-    info->workspace_bytes = P->ws_bytes + P->kr_bytes + P->nd_work_bytes;
+    info->workspace_bytes = P->ws_bytes + P->kr_bytes + P->nd_work_bytes + solve_scratch_bytes(P);
     info->factored = P->factored ? 1 : 0;
+    info->factor_work_bytes = factor_work_estimate(P);
     return ASP_OK;
 }
 

@@ -89,6 +89,11 @@ class Backend:
     def factor_bytes(self, req: Request) -> int:
         raise NotImplementedError
 
+    def factor_work_bytes(self, req: Request) -> int:
+        """Device bytes the factorization needs for the time of `create`
+        (work buffers that `create` releases before it returns)."""
+        return 0
+
     def workspace_bytes(self, req: Request, nrhs: int) -> int:
         raise NotImplementedError
 
@@ -117,30 +122,34 @@ class AspBackend(Backend):
         self.asp, self.torch = asp, torch
         self.prec, self.tol, self.restart, self.maxit = prec, tol, restart, maxit
         self.keep_u = keep_u
-        self._sizes = {}
+        self._hosts = {}      # shape -> host-only plan (sizes only, no device state)
+        self._ws = {}         # (shape, nrhs) -> workspace bytes
+        self._lock = threading.Lock()
 
     def _host_plan(self, req):
+        """A host-only plan of the request's shape: the library's own sizes
+        (factors, factorization work buffers, workspaces) without a device."""
         k = (req.dim, req.n, req.layer_b, req.pml_eta)
-        if k not in self._sizes:
-            h = self.asp.asp_setup(req.dim, np.ones(req.n ** req.dim), req.omega, req.n,
-                                   req.layer_b, req.pml_eta, C=req.C, prec=self.prec,
-                                   host_only=True)
-            try:
-                info = self.asp.asp_info(h)
-                ws = {r: self.asp.asp_workspace_estimate(h, r, self.restart) for r in (1, 64)}
-            finally:
-                self.asp.asp_destroy(h)
-            self._sizes[k] = (info["factor_bytes"], ws)
-        return self._sizes[k]
+        with self._lock:
+            if k not in self._hosts:
+                h = self.asp.asp_setup(req.dim, np.ones(req.n ** req.dim), req.omega, req.n,
+                                       req.layer_b, req.pml_eta, C=req.C, prec=self.prec,
+                                       host_only=True)
+                self._hosts[k] = (h, self.asp.asp_info(h))
+            return k, self._hosts[k]
 
     def factor_bytes(self, req):
-        return self._host_plan(req)[0]
+        return self._host_plan(req)[1][1]["factor_bytes"]
+
+    def factor_work_bytes(self, req):
+        return self._host_plan(req)[1][1]["factor_work_bytes"]
 
     def workspace_bytes(self, req, nrhs):
-        ws = self._host_plan(req)[1]
-        # affine in nrhs between the two probes; per-rhs slope from them
-        per = (ws[64] - ws[1]) / 63.0
-        return int(ws[1] + per * (nrhs - 1)) + 1
+        k, (h, _) = self._host_plan(req)
+        with self._lock:
+            if (k, nrhs) not in self._ws:
+                self._ws[(k, nrhs)] = self.asp.asp_workspace_estimate(h, nrhs, self.restart)
+            return self._ws[(k, nrhs)]
 
     def create(self, req):
         torch = self.torch
@@ -150,7 +159,15 @@ class AspBackend(Backend):
                                  C=req.C, prec=self.prec)
             self.asp.asp_set_stream(plan.handle, stream.cuda_stream)
             plan.factor()
+            # the factorization's work buffers go back before the plan is cached
+            self.asp.asp_release_workspace(plan.handle)
         return (plan, stream)
+
+    def close(self):
+        with self._lock:
+            for h, _ in self._hosts.values():
+                self.asp.asp_destroy(h)
+            self._hosts.clear()
 
     def solve(self, handle, f):
         torch = self.torch
@@ -242,16 +259,18 @@ class Server:
             if e is None:
                 req = q[0]
                 fb = self.backend.factor_bytes(req)
-                if fb + self.backend.workspace_bytes(req, 1) > self.budget:
+                fw = self.backend.factor_work_bytes(req)
+                if max(fb + fw, fb + self.backend.workspace_bytes(req, 1)) > self.budget:
                     # can never run: fail the key's requests instead of waiting
                     self._fail(list(q), "exceeds the device memory budget")
                     q.clear()
                     continue
-                if not self._reserve(fb):
+                # the factors, and the factorization's work buffers while it runs
+                if not self._reserve(fb + fw):
                     continue
                 e = _Entry(key, fbytes=fb, creating=True)
                 self._cache[key] = e
-                return ("create", e, req)
+                return ("create", e, req, fw)
             if e.busy or e.creating:
                 continue
             batch, total = [], 0
@@ -290,7 +309,7 @@ class Server:
                     self._lock.wait(0.05)
                     work = self._pick()
             if work[0] == "create":
-                _, e, req = work
+                _, e, req, fw = work
                 try:
                     h = self.backend.create(req)
                     err = None
@@ -298,6 +317,7 @@ class Server:
                     h, err = None, ex
                 with self._lock:
                     e.creating = False
+                    self._used -= fw           # work buffers released by create
                     if h is None:
                         self._used -= e.fbytes
                         del self._cache[e.key]

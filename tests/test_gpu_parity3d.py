@@ -104,7 +104,9 @@ def test_auxiliary_operators_3d(n, gamma, b, prec, tol, nd):
                 data = rng.standard_normal((2, k_in)) + 1j * rng.standard_normal((2, k_in))
                 out = host(plan.subsolve(kinds[kind], p, dev(data), Np)).reshape(2, Np)
                 for r in range(2):
-                    assert rel(out[r], ref.G(data[r])) < tol, (kind, p)
+                    e = rel(out[r], ref.G(data[r]))
+                    print(f"3D G~{kind}_{p} n={n} prec={prec} nd={nd}: rel err {e:.2e}", flush=True)
+                    assert e < tol, (kind, p)
 
 
 @FACT
@@ -119,7 +121,9 @@ def test_apply_3d(n, gamma, b, prec, tol, nd):
         plan.factor()
         z = host(plan.apply(dev(r)))
     for k in range(2):
-        assert rel(z[k], M.apply(r[k])) < tol
+        e = rel(z[k], M.apply(r[k]))
+        print(f"3D apply n={n} gamma={gamma} b={b} prec={prec} nd={nd}: rel err {e:.2e}", flush=True)
+        assert e < tol
 
 
 @FACT
@@ -209,6 +213,9 @@ def test_gmres_3d_bf16_split():
     for k in range(2):
         b = w["f"][k] / P.scale()
         x_ref, it_ref, _, _ = oracle_gmres(lambda v: A @ v, M.apply, b, w["tol"], w["restart"], 100)
-        print(f"bf16x3 gmres rhs {k}: iters {int(it[k])} (oracle {it_ref})", flush=True)
-        assert int(it[k]) <= it_ref + 2
+        e = rel(u[k], x_ref)
+        print(f"bf16x3 gmres rhs {k}: iters {int(it[k])} (oracle {it_ref}), solution error "
+              f"{e:.2e} at tol {w['tol']}", flush=True)
+        assert abs(int(it[k]) - it_ref) <= 1
         assert np.linalg.norm(b - A @ u[k]) / np.linalg.norm(b) <= w["tol"] * (1 + 1e-9)
+        assert e < 1e-5

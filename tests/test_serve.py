@@ -204,3 +204,38 @@ def test_stream_through_fake_backend(realtime):
     assert summ["completed"] == 60
     assert summ["factorizations"] == len({d["key"] for d in s})
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
+
+
+def test_factorization_work_buffers_are_reserved_while_creating():
+    """A plan's creation needs its factors plus the factorization's work
+    buffers; the server reserves both and returns the work buffers when the
+    creation ends, so a budget that holds the factors and a batch but not the
+    work buffers next to another resident plan forces an eviction first."""
+    class Working(FakeBackend):
+        def __init__(self):
+            super().__init__(solve_s=0.002, create_s=0.01)
+            self.inflight = 0
+            self.peak_true = 0
+            self.srv = None
+
+        def factor_work_bytes(self, r):
+            return 50 * r.n * r.n
+
+        def create(self, r):
+            with self.lock:
+                # device bytes really held while this creation runs
+                self.peak_true = max(self.peak_true, self.srv._used)
+            return super().create(r)
+
+    be = Working()
+    n = 16
+    fb, fw, ws = 100 * n * n, 50 * n * n, 10 * n * n
+    budget = 2 * fb + ws + fw - 1           # two plans fit, but not while a third creates
+    reqs = [req(i, n, 0.05 * i, key_tag=i % 3) for i in range(6)]
+    srv = Server(be, budget_bytes=budget, workers=1)
+    be.srv = srv
+    res, summ = srv.run(reqs)
+    assert summ["completed"] == 6
+    assert summ["peak_bytes"] <= budget
+    assert be.peak_true >= fb + fw               # the creation held its work reservation
+    assert summ["evictions"] > 0
