@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--secondary", default="3d_n63_lens",
-                    help="second workload timed after the first (one step), '' for none")
+                    help="second workload timed after the first (same steps and warmup), '' for none")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the seeded serving stream timed after the batch runs (0: none)")
     ap.add_argument("--cpu-sample", type=int, default=64,
@@ -81,13 +81,24 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, iters_mean, sample):
+def host_threads():
+    """Threads of the host's CPU share: OMP_NUM_THREADS where the machine sets
+    it (the GPU machines set their share there), else every core."""
+    try:
+        return max(1, int(os.environ.get("OMP_NUM_THREADS", "")))
+    except ValueError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, iters_mean, sample, threads=1):
     """Time the CPU FP64 oracle on a bounded sample of the workload and scale it
     to solves/s of the whole batch: factor `sample` auxiliary problems of each
     kind (M, R, L) and apply each G~ once; the full setup and one full
     preconditioner apply are the per-kind means times the counts; one solve of
     one right-hand side is then iters x (apply + stencil + Arnoldi), with the
-    setup shared by the batch."""
+    setup shared by the batch.  `threads`: BLAS/LAPACK threads (the oracle is
+    one Python process; its banded LU and sparse matrix-vector products run in
+    those libraries)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -95,7 +106,7 @@ def cpu_baseline(w, iters_mean, sample):
     from oracle.operator import Problem
     from oracle.subproblem import Subproblem
 
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         t_all = time.perf_counter()
         P = Problem.from_workload(w)
         X = partition.layers(P.n, P.b, P.gamma)
@@ -141,11 +152,12 @@ def cpu_baseline(w, iters_mean, sample):
     return {
         "value": nrhs / total,
         "unit": "solves/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"{sum(min(sample, c) for _, _, c in per_kind.values())} of "
                    f"{sum(c for _, _, c in per_kind.values())} auxiliary problems factored and "
-                   f"solved once (banded LU, 1 thread) + one stencil apply on the full grid, "
+                   f"solved once (banded LU, {threads} BLAS thread{'s' if threads > 1 else ''}) "
+                   f"+ one stencil apply on the full grid, "
                    f"{sample_s:.1f} s; scaled by the problem counts and {iters_mean:.2f} GMRES "
                    f"iterations per RHS (the GPU run's mean), setup shared by {nrhs} RHS"),
         "setup_s": setup,
@@ -189,9 +201,10 @@ def recorded_traffic(workload, prec_name, cls):
     return c["fetch_bytes"] + c["write_bytes"]
 
 
-def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=True):
+def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=True, keep_u=False):
     """Time `steps` passes of the hot path (factor + GMRES of the whole batch)
-    after `warmup` untimed passes; returns the measurements."""
+    after `warmup` untimed passes; returns the measurements (and the last
+    solution, on the device, if keep_u)."""
     import ctypes
 
     import torch
@@ -267,6 +280,7 @@ def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=Tr
         "iters": iters, "relres": relres, "status": asp.STATUS_NAMES.get(st, st),
         "pc_apply_gbps": pc_bytes / (pc_ms / 1e3) / 1e9 if pc_ms else None,
         "kernels": kstats, "roofline": roof, "factor_bytes": info["factor_bytes"],
+        "u": u if keep_u else None,
     }
 
 
@@ -383,13 +397,44 @@ def config_of(name, r, prec_name):
             "layer_precision": prec_name, "krylov_precision": "fp64"}
 
 
+def line_of(name, r, prec_name, factorization=None):
+    """The measurements of one run_workload result as a bench sub-line."""
+    cfg = config_of(name, r, prec_name)
+    if factorization is not None:
+        cfg["factorization"] = factorization
+    return {
+        "config": cfg, "value": r["value"], "unit": "solves/s", "ms_per_step": r["ms_per_step"],
+        "warm_solves_per_s": r["warm_solves_per_s"], "factor_ms": r["factor_ms"],
+        "gmres_ms": r["gmres_ms"], "iters_mean": float(r["iters"].mean()),
+        "max_relres": float(r["relres"].max()), "status": r["status"],
+        "pc_apply_gbps": r["pc_apply_gbps"], "kernels": r["kernels"], "roofline": r["roofline"],
+    }
+
+
+def compare_runs(mixed, plain):
+    """Iterations per right-hand side of a reduced-precision run against the
+    plain FP64 run of the same workload, and the relative 2-norm difference of
+    their solutions (both to the same tolerance)."""
+    import torch
+
+    d = [int(a) - int(b) for a, b in zip(mixed["iters"], plain["iters"])]
+    out = {"iter_delta": {"min": min(d), "max": max(d), "mean": sum(d) / len(d),
+                          "rhs_differing": sum(1 for x in d if x != 0)}}
+    if mixed.get("u") is not None and plain.get("u") is not None:
+        um, up = mixed["u"], plain["u"]
+        diff = torch.linalg.vector_norm(um - up, dim=1) / torch.linalg.vector_norm(up, dim=1)
+        out["solution_rel_diff_max"] = float(diff.max())
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
-    r = run_workload(args.workload, args.prec, args.steps, args.warmup, args.restart, args.tol)
+    r = run_workload(args.workload, args.prec, args.steps, args.warmup, args.restart, args.tol,
+                     keep_u=args.prec != "fp64")
     iters, relres = r["iters"], r["relres"]
     out = {
         "metric": METRIC,
@@ -416,22 +461,37 @@ def main():
         "roofline": r["roofline"],
         "cpu_baseline": None,
     }
+    if args.prec != "fp64":
+        # the plain FP64 path on the same workload, and what the mixed path
+        # changes against it: iterations per right-hand side and the solution
+        p64 = run_workload(args.workload, "fp64", args.steps, args.warmup, args.restart, args.tol,
+                           keep_u=True)
+        out["plain_fp64"] = line_of(args.workload, p64, "fp64")
+        out["plain_fp64"]["vs_mixed"] = compare_runs(r, p64)
+        del p64
+    r["u"] = None
     if args.secondary:
+        d2 = workloads_dim(args.secondary)
         for key, prec, nd in (("secondary", args.prec, True), ("secondary_bf16x3", "bf16x3", True),
-                              ("secondary_blocks", args.prec, False)):
-            if (prec == "bf16x3" or not nd) and workloads_dim(args.secondary) != 3:
+                              ("secondary_blocks", args.prec, False),
+                              ("secondary_fp64", "fp64", True)):
+            if (prec == "bf16x3" or not nd) and d2 != 3:
                 continue
-            s2 = run_workload(args.secondary, prec, 1, 1, nd3d=nd)
-            out[key] = {
-                "config": dict(config_of(args.secondary, s2, prec),
+            if key == "secondary_fp64" and args.prec == "fp64":
+                continue
+            s2 = run_workload(args.secondary, prec, args.steps, args.warmup, nd3d=nd,
+                              keep_u=key in ("secondary", "secondary_bf16x3", "secondary_fp64"))
+            out[key] = line_of(args.secondary, s2, prec,
                                factorization=("nested dissection" if nd else "block recurrence")
-                               if workloads_dim(args.secondary) == 3 else None),
-                "value": s2["value"], "unit": "solves/s", "ms_per_step": s2["ms_per_step"],
-                "warm_solves_per_s": s2["warm_solves_per_s"], "factor_ms": s2["factor_ms"],
-                "gmres_ms": s2["gmres_ms"], "iters_mean": float(s2["iters"].mean()),
-                "max_relres": float(s2["relres"].max()), "status": s2["status"],
-                "kernels": s2["kernels"], "roofline": s2["roofline"],
-            }
+                               if d2 == 3 else None)
+            out[key]["_run"] = s2
+        base = out.get("secondary_fp64", {}).get("_run")
+        for key in ("secondary", "secondary_bf16x3"):
+            if base is not None and key in out:
+                out[key]["vs_fp64"] = compare_runs(out[key]["_run"], base)
+        for key in list(out):
+            if isinstance(out[key], dict):
+                out[key].pop("_run", None)
     if args.serve_requests > 0:
         out["serving"] = serving_run(args.serve_requests, args.prec)
     if args.paper_tables:
@@ -442,7 +502,11 @@ def main():
         out["paper_tables3d"] = paper_tables(args.prec, [int(x) for x in args.paper_tables3d.split(",")],
                                              dim=3, nd3d=not args.paper_blocks3d)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(r["w"], float(iters.mean()), args.cpu_sample)
+        nt = host_threads()
+        out["cpu_baseline"] = cpu_baseline(r["w"], float(iters.mean()), args.cpu_sample, threads=nt)
+        if nt > 1:
+            out["cpu_baseline"]["one_thread"] = cpu_baseline(r["w"], float(iters.mean()),
+                                                             args.cpu_sample, threads=1)
     print(json.dumps(out), flush=True)
 
 

@@ -73,6 +73,8 @@ void solve_cost(const asp_plan* P, int sub0, int nsub, int nact, double io_vecto
 
 }  // namespace
 
+long long apply_scratch_groups(const asp_plan* P, int nrhs) { return apply_groups(P, nrhs); }
+
 size_t solve_scratch_bytes(const asp_plan* P) {
     return (size_t)P->y_waves * solve_scratch_per_block(P) * elem_bytes(P);
 }

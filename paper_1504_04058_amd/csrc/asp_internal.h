@@ -407,6 +407,11 @@ hipError_t launch_scale_vec(const zd* w, zd* v, const zd* scal, long long N, con
 // host-side pieces shared by the entry points
 asp_status ensure_apply_ws(asp_plan* P, int nrhs);
 asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
+// workgroups (each with solve_scratch_per_block entries of scratch) of the
+// 2D layer solves of one apply over nrhs right-hand sides
+long long apply_scratch_groups(const asp_plan* P, int nrhs);
+// right-hand sides per chunk of the 3D nested-dissection solves
+constexpr int ND_CHUNK = 16;
 // device bytes of the 2D layer solves' forward-substitution scratch now allocated
 size_t solve_scratch_bytes(const asp_plan* P);
 // device bytes of the work buffers asp_factor allocates besides the factors

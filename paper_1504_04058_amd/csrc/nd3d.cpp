@@ -31,7 +31,7 @@ namespace {
 constexpr int NDT = 64;                 // padding of a front part: the Gauss-Jordan panel width
 constexpr int ND_LEAF = 4;              // regions of at most 4 x 4 columns are leaves
 constexpr double ND_TRANSIENT = 24e9;   // level-buffer bytes of one factorization group
-constexpr int RW = 16;                  // right-hand sides per chunk
+constexpr int RW = ND_CHUNK;            // right-hand sides per chunk
 
 long long pad64(long long x) { return (x + NDT - 1) / NDT * NDT; }
 

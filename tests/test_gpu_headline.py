@@ -85,8 +85,10 @@ def _plan2d(w, prec):
     return asp.Plan(2, w["c"], w["omega"], w["n"], w["b"], w["gamma"], C=w["C"], prec=prec)
 
 
+# FP32 bounds about ten times the measured worst case over the 64 right-hand
+# sides (relative 2-norm 1.0e-6, worst line 1.3e-6)
 @pytest.mark.parametrize("prec,tol,ltol", [(asp.ASP_PREC_FP64, 1e-11, 1e-11),
-                                           (asp.ASP_PREC_FP32, 1e-4, 1e-4)])
+                                           (asp.ASP_PREC_FP32, 1e-5, 1.5e-5)])
 def test_apply_64_rhs(prec, tol, ltol):
     """All 64 right-hand sides of the benchmark's batch shape against the
     oracle: two 32-RHS chunks per M problem, two 32-RHS sweep tiles."""

@@ -3,10 +3,13 @@
 Tolerances (relative 2-norm unless stated):
 * stencil y = A x, complex double: 1e-13;
 * one auxiliary Green's operator and the whole apply, FP64 factors: 1e-11;
-  FP32 factors: 2e-4 per operator and 1e-3 for the apply (both stated);
+  FP32 factors: 7e-6 per operator and 8e-6 for the apply (about ten times the
+  largest errors measured on these cases, 6.7e-7 and 7.5e-7);
 * GMRES to tol 1e-6: iteration count within +-1 of the oracle's; the solution
-  within 1e-6 of the oracle's (FP64) and within 1e-5 (FP32 factors); the true
-  relative residual, recomputed by the oracle's operator, <= 1e-6.
+  within 1e-6 of the oracle's (FP64) and within 1e-5 (FP32 factors: two valid
+  solutions at tol 1e-6 may differ by up to cond(A) 1e-6; the 1e-6 solution
+  gate at tol 1e-10 is in test_gpu_headline.py); the true relative residual,
+  recomputed by the oracle's operator, <= 1e-6.
 The grids span many layers, thin and thick auxiliary problems (L = 12..26), and
 a ragged last layer (n = 100: r = 2 physical lines in X_m)."""
 import math
@@ -86,7 +89,7 @@ def test_stencil_3d(n, gamma):
         assert rel(y[r], A @ x[r]) < 1e-13
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 2e-4)])
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 7e-6)])
 @pytest.mark.parametrize("n,gamma,b", CASES)
 def test_auxiliary_operators(n, gamma, b, prec, tol):
     P = _problem(n, gamma, b)
@@ -112,7 +115,7 @@ def test_auxiliary_operators(n, gamma, b, prec, tol):
                     assert e < tol, (kind, p)
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 8e-6)])
 @pytest.mark.parametrize("n,gamma,b", CASES)
 def test_apply(n, gamma, b, prec, tol):
     P = _problem(n, gamma, b)
@@ -128,7 +131,7 @@ def test_apply(n, gamma, b, prec, tol):
         assert e < tol
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-5)])
 def test_apply_odd_batch_count_per_sweep_wavefront(prec, tol):
     """n = 300: each of the eight wavefronts of a sweep step takes 48 columns
     of the boundary map, three batches of 16, so the second register slot's
@@ -145,7 +148,9 @@ def test_apply_odd_batch_count_per_sweep_wavefront(prec, tol):
         plan.factor()
         z = host(plan.apply(dev(r)))
     for k in range(2):
-        assert rel(z[k], M.apply(r[k])) < tol
+        e = rel(z[k], M.apply(r[k]))
+        print(f"2D apply n=300 prec={prec}: rel err {e:.2e}", flush=True)
+        assert e < tol
 
 
 def test_single_and_two_layers():

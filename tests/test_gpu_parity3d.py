@@ -3,8 +3,8 @@ FP64 oracle, through the C ABI.
 
 Tolerances (relative 2-norm): one auxiliary Green's operator and the whole
 apply with FP64 factors 1e-11 (both factorizations: nested dissection, the
-default, and the dense block recurrence); FP32 factors 2e-4 per operator and 1e-3 for the
-apply; GMRES to tol 1e-6: iterations within +-1 of the oracle, the true
+default, and the dense block recurrence); FP32 factors about ten times the
+largest measured error (TOL32_OP, TOL32_APPLY); GMRES to tol 1e-6: iterations within +-1 of the oracle, the true
 relative residual (recomputed by the oracle's operator) <= 1e-6, the solution
 within 1e-6 (FP64) or 1e-5 (FP32 factors) of the oracle's.  The cases span one
 to several 64-wide tiles per block (n L = 133 .. 558), a ragged last layer and
@@ -81,10 +81,18 @@ FACT = pytest.mark.parametrize("nd", [True, False], ids=["nd", "blocks"])
 CASES = [(19, 4, 4), (23, 8, 4), (26, 5, 3)]
 
 
+# FP32 bounds about ten times the largest measured errors: nested dissection
+# 1.5e-6 per operator and 3.3e-6 per apply, the block recurrence (longer
+# chains of dependent block inverses) 7.3e-6 and 1.8e-5
+TOL32_OP = {True: 1.5e-5, False: 7e-5}
+TOL32_APPLY = {True: 3e-5, False: 2e-4}
+
+
 @FACT
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 2e-4)])
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, None)])
 @pytest.mark.parametrize("n,gamma,b", CASES)
 def test_auxiliary_operators_3d(n, gamma, b, prec, tol, nd):
+    tol = tol or TOL32_OP[nd]
     print(f"3D operators n={n} gamma={gamma} b={b} prec={prec} nd={nd}", flush=True)
     P = _problem(n, gamma, b)
     X = partition.layers(n, b, gamma)
@@ -110,9 +118,10 @@ def test_auxiliary_operators_3d(n, gamma, b, prec, tol, nd):
 
 
 @FACT
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, None)])
 @pytest.mark.parametrize("n,gamma,b", CASES + [(31, 8, 4)])
 def test_apply_3d(n, gamma, b, prec, tol, nd):
+    tol = tol or TOL32_APPLY[nd]
     print(f"3D apply n={n} gamma={gamma} b={b} prec={prec} nd={nd}", flush=True)
     P, M = _oracle(n, gamma, b)
     rng = np.random.default_rng(3)
@@ -187,7 +196,7 @@ def test_apply_3d_bf16_split(n, gamma, b, nd):
     the FP32 path printed beside it.  The split keeps hi*hi + hi*lo + lo*hi of
     every real product (16 of FP32's 24 significant bits survive in each
     partial product, the sum accumulates in FP32); measured 1-2e-6 relative
-    at n = 19 and 31 (FP32: 2-4e-6).  Bound: 1e-4."""
+    at n = 19 and 31 (FP32: 2-4e-6), at most 1.4e-5.  Bound: 1e-4."""
     P, M = _oracle(n, gamma, b)
     rng = np.random.default_rng(3)
     r = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
