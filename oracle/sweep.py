@@ -18,16 +18,28 @@ class Preconditioner:
     """M^-1 for the symmetric-form system of ``prob`` (an operator.Problem).
 
     keep_factors=False factors each subproblem when it is used and drops it
-    afterwards: same arithmetic, bounded memory, for large grids."""
+    afterwards: same arithmetic, bounded memory, for large grids.
 
-    def __init__(self, prob, keep_factors=True):
+    inner=(b2, gamma_aux2), 3D only: every auxiliary problem is solved by the
+    additive sweeping preconditioner along x2 (inner layers of b2 lines, inner
+    auxiliary PML of gamma_aux2 lines) instead of exactly (Section 5;
+    recursive.RecursiveSubproblem)."""
+
+    def __init__(self, prob, keep_factors=True, inner=None):
         self.prob = prob
         self.X = partition.layers(prob.n, prob.b, prob.gamma)
         self.m = len(self.X)
         subs = partition.subproblems(prob.n, prob.b, prob.gamma, prob.gamma_aux)
         self.keep = keep_factors
         # Algorithm 1 / 3: factor H^M_q (q=1..m), H^R_p (p=2..m), H^L_p (p=1..m-1).
-        mk = lambda s: Subproblem(prob, s, self.X[s.p - 1], factor=keep_factors)
+        if inner is None:
+            mk = lambda s: Subproblem(prob, s, self.X[s.p - 1], factor=keep_factors)
+        else:
+            from .recursive import RecursiveSubproblem
+
+            if prob.d != 3:
+                raise ValueError("the recursive sweep applies to 3D problems")
+            mk = lambda s: RecursiveSubproblem(prob, s, self.X[s.p - 1], *inner, factor=keep_factors)
         self.M = {s.p: mk(s) for s in subs["M"]}
         self.R = {s.p: mk(s) for s in subs["R"]}
         self.L = {s.p: mk(s) for s in subs["L"]}
