@@ -2,8 +2,8 @@
 not have the same width) against the CPU FP64 oracle, through the C ABI
 (opts.n_layers / opts.layer_widths): one auxiliary Green's operator of each
 kind, including a layer of a single line, and the whole apply, 2D and 3D, FP64
-factors 1e-11 and FP32 factors 2e-4 / 1e-3 (the bars of the equal-width
-tests); GMRES at the paper's 2D settings with wider layers across the lens,
+factors 1e-11 and FP32 factors 4e-5 / 3e-5 (about ten times the measured
+errors); GMRES at the paper's 2D settings with wider layers across the lens,
 with the oracle's iteration count."""
 import math
 
@@ -51,7 +51,8 @@ def _plan(P, prec):
     return asp.Plan(P.d, P.c, P.omega, P.n, list(P.b), P.gamma, C=P.C, prec=prec)
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 2e-4)])
+# FP32: about ten times the largest measured error (3.7e-6 per operator)
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 4e-5)])
 @pytest.mark.parametrize("d,n,gamma,w", CASES)
 def test_unequal_width_operators(d, n, gamma, w, prec, tol):
     print(f"layer widths operators d={d} n={n} gamma={gamma} w={w} prec={prec}", flush=True)
@@ -80,7 +81,8 @@ def test_unequal_width_operators(d, n, gamma, w, prec, tol):
                     assert e < tol, (kind, p)
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
+# FP32: about ten times the largest measured error (3.1e-6 per apply)
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 3e-5)])
 @pytest.mark.parametrize("d,n,gamma,w", CASES)
 def test_unequal_width_apply(d, n, gamma, w, prec, tol):
     print(f"layer widths apply d={d} n={n} w={w} prec={prec}", flush=True)

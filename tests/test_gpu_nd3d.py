@@ -2,7 +2,7 @@
 (Section 4.1: columns along the sweep axis, ordered by nested dissection;
 opts.nd3d) against the CPU FP64 oracle, through the C ABI: one auxiliary
 Green's operator of each kind and the whole apply at FP64 (1e-11) and FP32
-(2e-4 / 1e-3) factors, agreement with the dense block-recurrence path, more
+(1e-5 / 1e-5, about ten times the measured errors) factors, agreement with the dense block-recurrence path, more
 than one chunk of 16 right-hand sides, and GMRES at the paper's 3D settings
 with the oracle's iteration count."""
 import math
@@ -52,7 +52,8 @@ def _plan(P, prec, nd=True):
                     pml_aux=P.gamma_aux, nd3d=nd)
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 2e-4)])
+# FP32: about ten times the largest measured error (1.0e-6 per operator)
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-5)])
 @pytest.mark.parametrize("n,gamma,b,aux", CASES)
 def test_nd_operators(n, gamma, b, aux, prec, tol):
     print(f"nd operators n={n} gamma={gamma} b={b} aux={aux} prec={prec}", flush=True)
@@ -79,7 +80,8 @@ def test_nd_operators(n, gamma, b, aux, prec, tol):
                     assert e < tol, (kind, p)
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
+# FP32: about ten times the largest measured error (9.4e-7 per apply)
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-5)])
 @pytest.mark.parametrize("n,gamma,b,aux", CASES)
 def test_nd_apply(n, gamma, b, aux, prec, tol):
     print(f"nd apply n={n} gamma={gamma} b={b} aux={aux} prec={prec}", flush=True)

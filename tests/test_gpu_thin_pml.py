@@ -2,7 +2,7 @@
 neighbouring layer with eta_aux < eta, pads at the domain boundary keep the
 boundary PML) against the CPU FP64 oracle, through the C ABI: one auxiliary
 Green's operator of each kind and the whole apply, 2D and 3D, FP64 factors
-1e-11 and FP32 factors 2e-4 / 1e-3 (the bars of the full-width tests), and
+1e-11 and FP32 factors 1.2e-5 / 1.2e-5 (about ten times the measured errors), and
 GMRES at the paper's 3D choice eta = 9h, eta_aux = 5h with the oracle's
 iteration count."""
 import math
@@ -50,7 +50,8 @@ def _plan(P, prec):
 CASES = [(2, 127, 9, 5, 8), (2, 63, 12, 4, 4), (3, 23, 8, 4, 4), (3, 26, 9, 5, 3)]
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 2e-4)])
+# FP32: about ten times the largest measured error (1.1e-6 per operator)
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1.2e-5)])
 @pytest.mark.parametrize("d,n,gamma,aux,b", CASES)
 def test_thin_auxiliary_operators(d, n, gamma, aux, b, prec, tol):
     print(f"thin pml operators d={d} n={n} gamma={gamma} aux={aux} b={b} prec={prec}", flush=True)
@@ -77,7 +78,8 @@ def test_thin_auxiliary_operators(d, n, gamma, aux, b, prec, tol):
                     assert e < tol, (kind, p)
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-3)])
+# FP32: about ten times the largest measured error (1.1e-6 per apply)
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1.2e-5)])
 @pytest.mark.parametrize("d,n,gamma,aux,b", CASES)
 def test_thin_apply(d, n, gamma, aux, b, prec, tol):
     print(f"thin pml apply d={d} n={n} aux={aux} prec={prec}", flush=True)
