@@ -155,6 +155,33 @@ asp_status asp_factor(asp_plan* plan);
  * Errors: ASP_ERR_STATE (not factored), ASP_ERR_ARG, ASP_ERR_OOM, ASP_ERR_DEVICE. */
 asp_status asp_apply(asp_plan* plan, const void* r, void* z, int nrhs);
 
+/* Size of the fixed device array asp_apply_noalloc works in.  Each device the
+ * library runs on holds one such array from the library's load until the
+ * process ends. */
+#define ASP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* asp_apply_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): z = M^-1 r exactly as asp_apply computes it (the same kernels,
+ * bitwise the same result), but the apply's work buffers are carved from the
+ * fixed array of ASP_NOALLOC_SCRATCH_BYTES bytes instead of the plan's
+ * workspaces, and the call allocates and frees nothing (nor does it record
+ * timing events: asp_timing_read does not see it).
+ *   r, z, nrhs as for asp_apply.  The plan must be factored (asp_factor
+ *   allocates the factors; this call only reads them).  2D plans and 3D plans
+ *   factored by nested dissection.  The work buffers grow with n, the layer
+ *   count and nrhs: 2D n = 127 fits with up to 16 right-hand sides in either
+ *   precision, 3D n = 31 with 16.
+ * Every call on one device uses that device's array and leaves the last
+ * call's contents in it (nothing in it has to start at zero): calls that
+ * overlap on one device (other streams, other plans, other host threads) race
+ * and give wrong results.
+ * Errors: ASP_ERR_ARG (bad arguments; a 3D plan factored by the block
+ * recurrence; work buffers for nrhs right-hand sides larger than
+ * ASP_NOALLOC_SCRATCH_BYTES, the message giving both sizes), ASP_ERR_STATE
+ * (not factored), ASP_ERR_DEVICE. */
+asp_status asp_apply_noalloc(asp_plan* plan, const void* r, void* z, int nrhs);
+
 /* asp_matvec -- y = A x with the symmetric-form 5-point (2D) / 7-point (3D)
  * PML operator of eq. (2D) / (3D), complex double, for nrhs >= 1 vectors.
  *   x  device, nrhs * N complex128;  y  device, nrhs * N complex128, no alias.

@@ -69,6 +69,7 @@ def lib():
             "asp_setup": (I, [ctypes.POINTER(P), I, P, D, I, I, I, ctypes.POINTER(asp_opts)]),
             "asp_factor": (I, [P]),
             "asp_apply": (I, [P, P, P, I]),
+            "asp_apply_noalloc": (I, [P, P, P, I]),
             "asp_matvec": (I, [P, P, P, I]),
             "asp_gmres": (I, [P, P, P, I, D, I, I, P, P]),
             "asp_subsolve": (I, [P, I, I, P, P, I]),
@@ -151,6 +152,10 @@ def asp_factor(plan):
 
 def asp_apply(plan, r, z, nrhs):
     _check(plan, lib().asp_apply(plan, _ptr(r), _ptr(z), nrhs))
+
+
+def asp_apply_noalloc(plan, r, z, nrhs):
+    _check(plan, lib().asp_apply_noalloc(plan, _ptr(r), _ptr(z), nrhs))
 
 
 def asp_matvec(plan, x, y, nrhs):
@@ -270,6 +275,11 @@ class Plan:
         r = r.contiguous()
         z = torch.empty_like(r)
         asp_apply(self.handle, r, z, r.numel() // self.N)
+        return z
+
+    def apply_noalloc(self, r, z):
+        """z = M^-1 r into the caller's z (same shape as r), allocating nothing."""
+        asp_apply_noalloc(self.handle, r, z, r.numel() // self.N)
         return z
 
     def matvec(self, x):
