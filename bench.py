@@ -60,6 +60,11 @@ def parse():
     ap.add_argument("--restart", type=int, default=None)
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain-fp64", action="store_true",
+                    help="skip the plain FP64 lines beside a reduced-precision run")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy a device buffer of BYTES bytes once and exit: the "
+                         "reference a hardware traffic counter is scaled by")
     ap.add_argument("--secondary", default="3d_n63_lens",
                     help="second workload timed after the first (same steps and warmup), '' for none")
     ap.add_argument("--serve-requests", type=int, default=48,
@@ -429,6 +434,16 @@ def compare_runs(mixed, plain):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        import torch
+
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
@@ -461,7 +476,7 @@ def main():
         "roofline": r["roofline"],
         "cpu_baseline": None,
     }
-    if args.prec != "fp64":
+    if args.prec != "fp64" and not args.no_plain_fp64:
         # the plain FP64 path on the same workload, and what the mixed path
         # changes against it: iterations per right-hand side and the solution
         p64 = run_workload(args.workload, "fp64", args.steps, args.warmup, args.restart, args.tol,
@@ -477,7 +492,7 @@ def main():
                               ("secondary_fp64", "fp64", True)):
             if (prec == "bf16x3" or not nd) and d2 != 3:
                 continue
-            if key == "secondary_fp64" and args.prec == "fp64":
+            if key == "secondary_fp64" and (args.prec == "fp64" or args.no_plain_fp64):
                 continue
             s2 = run_workload(args.secondary, prec, args.steps, args.warmup, nd3d=nd,
                               keep_u=key in ("secondary", "secondary_bf16x3", "secondary_fp64"))
