@@ -70,8 +70,16 @@ typedef enum {
                                columns along the sweep axis, the n x n columns ordered by
                                nested dissection, multifrontal elimination;
                                O(n^2 L^2 log n) factor entries per problem */
-    ASP_FACT3D_BLOCKS = 1   /* a dense block recurrence along x1: n blocks of n L
+    ASP_FACT3D_BLOCKS = 1,  /* a dense block recurrence along x1: n blocks of n L
                                unknowns, O(n^3 L^2) factor entries per problem */
+    ASP_FACT3D_RECURSIVE = 2 /* the recursive sweep (Section 5): each quasi-2D auxiliary
+                               problem is not factored exactly but solved by one
+                               application of the additive sweeping preconditioner
+                               along x2 (inner layers and auxiliary PML as the outer
+                               ones: layer_b lines, pml_eta / pml_aux), whose quasi-1D
+                               problems are factored by the block recurrence along x1
+                               (blocks of L_x3 x L_x2 unknowns).  G~ is then approximate
+                               (the outer GMRES is flexible); equal layer widths only */
 } asp_fact3d;
 
 typedef struct {
@@ -96,8 +104,9 @@ typedef struct {
                        Layer 1 also takes the pml_eta - 1 PML lines below it, layer m
                        those above it.  Violations: ASP_ERR_ARG */
     int fact3d;     /* asp_fact3d: how the quasi-2D auxiliary problems of a 3D plan are
-                       factored; default ASP_FACT3D_ND.  Either way the result is the
-                       same operator G~.  Ignored by 2D plans; other values ASP_ERR_ARG */
+                       factored; default ASP_FACT3D_ND.  ND and BLOCKS give the same
+                       operator G~, RECURSIVE an approximation of it.  Ignored by 2D
+                       plans; other values ASP_ERR_ARG */
 } asp_opts;
 
 typedef struct {

@@ -20,7 +20,7 @@ ASP_OK, ASP_ERR_ARG, ASP_ERR_OOM, ASP_ERR_STATE = 0, 1, 2, 3
 ASP_ERR_BREAKDOWN, ASP_ERR_NOCONV, ASP_ERR_DEVICE = 4, 5, 6
 ASP_PREC_FP64, ASP_PREC_FP32, ASP_PREC_BF16X3 = 0, 1, 2
 ASP_SUB_M, ASP_SUB_R, ASP_SUB_L = 0, 1, 2
-ASP_FACT3D_ND, ASP_FACT3D_BLOCKS = 0, 1
+ASP_FACT3D_ND, ASP_FACT3D_BLOCKS, ASP_FACT3D_RECURSIVE = 0, 1, 2
 STATUS_NAMES = {0: "ASP_OK", 1: "ASP_ERR_ARG", 2: "ASP_ERR_OOM", 3: "ASP_ERR_STATE",
                 4: "ASP_ERR_BREAKDOWN", 5: "ASP_ERR_NOCONV", 6: "ASP_ERR_DEVICE"}
 
@@ -121,16 +121,18 @@ def _current_stream():
 # -- the C entry points --------------------------------------------------------------
 
 def asp_setup(dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64, stream=None,
-              host_only=False, pml_aux=0, nd3d=True):
+              host_only=False, pml_aux=0, nd3d=True, fact3d=None):
     """Returns a plan handle (ctypes.c_void_p).  c: host array, n**dim velocities
     (column-major, i.e. numpy order='F' flattening of an (n,)*dim array).
     layer_b: lines per layer, or a sequence of physical lines per layer
-    (arbitrary widths: opts.n_layers / opts.layer_widths)."""
+    (arbitrary widths: opts.n_layers / opts.layer_widths).  fact3d: an
+    ASP_FACT3D_* value; None takes nested dissection (nd3d) or the blocks."""
     c = np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(-1, order="F")
                              if np.asarray(c).ndim > 1 else np.asarray(c, dtype=np.float64))
     opts = asp_opts(C, prec, stream if stream is not None else
                     (ctypes.c_void_p(0) if host_only else _current_stream()), int(host_only),
-                    int(pml_aux or 0), 0, None, ASP_FACT3D_ND if nd3d else ASP_FACT3D_BLOCKS)
+                    int(pml_aux or 0), 0, None,
+                    fact3d if fact3d is not None else (ASP_FACT3D_ND if nd3d else ASP_FACT3D_BLOCKS))
     if not isinstance(layer_b, (int, np.integer)):
         widths = (ctypes.c_int * len(layer_b))(*[int(w) for w in layer_b])
         opts.n_layers = len(layer_b)
@@ -244,11 +246,11 @@ class Plan:
     """Owning wrapper around a plan handle (destroyed with the object)."""
 
     def __init__(self, dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64,
-                 host_only=False, pml_aux=0, nd3d=True):
+                 host_only=False, pml_aux=0, nd3d=True, fact3d=None):
         self.dim, self.n = dim, n
         self.N = n ** dim
         self.handle = asp_setup(dim, c, omega, n, layer_b, pml_eta, C=C, prec=prec,
-                                host_only=host_only, pml_aux=pml_aux, nd3d=nd3d)
+                                host_only=host_only, pml_aux=pml_aux, nd3d=nd3d, fact3d=fact3d)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

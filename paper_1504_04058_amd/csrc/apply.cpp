@@ -87,7 +87,9 @@ static long long transfer_groups(const asp_plan* P) {
 }
 
 size_t factor_work_estimate(const asp_plan* P) {
-    if (P->dim == 3) return P->nd ? nd_factor_work_estimate(P) : factor3d_work_estimate(P);
+    if (P->dim == 3)
+        return P->rec ? rec_factor_work_estimate(P)
+                      : P->nd ? nd_factor_work_estimate(P) : factor3d_work_estimate(P);
     return (size_t)transfer_groups(P) * solve_scratch_per_block(P) * elem_bytes(P);
 }
 
@@ -161,7 +163,8 @@ extern "C" asp_status asp_timing_read(asp_plan* P, int cls, int* launches, doubl
 // workspaces
 // ---------------------------------------------------------------------------
 asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
-    if (P->dim == 3) return P->nd ? nd_ensure_ws(P, nrhs) : ensure_apply_ws3(P, nrhs);
+    if (P->dim == 3)
+        return P->rec ? rec_ensure_ws(P, nrhs) : P->nd ? nd_ensure_ws(P, nrhs) : ensure_apply_ws3(P, nrhs);
     if (nrhs <= P->ws_rhs) return ASP_OK;
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     dev_free(P->d_U);
@@ -198,7 +201,9 @@ asp_status ensure_apply_ws(asp_plan* P, int nrhs) {
 // z = M^-1 r for the right-hand-side ids act[0..nact) (device list, NULL for
 // 0..nact-1) of batches laid out with stride N.
 asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int nact) {
-    if (P->dim == 3) return P->nd ? nd_apply(P, r, z, act, nact) : apply3d_internal(P, r, z, act, nact);
+    if (P->dim == 3)
+        return P->rec ? rec_apply(P, r, z, act, nact)
+                      : P->nd ? nd_apply(P, r, z, act, nact) : apply3d_internal(P, r, z, act, nact);
     hipStream_t st = P->stream;
     const int m = P->m;
     const int w_rhs = P->ws_rhs;
@@ -308,7 +313,7 @@ extern "C" asp_status asp_factor(asp_plan* P) {
     }
     if (P->dim == 3) {
         ASP_HIP(P, hipMemsetAsync(P->d_flag, 0, sizeof(int), P->stream));
-        asp_status s3 = P->nd ? nd_factor(P) : factor3d(P);
+        asp_status s3 = P->rec ? rec_factor(P) : P->nd ? nd_factor(P) : factor3d(P);
         if (s3 != ASP_OK) return s3;
         int flag3 = 0;
         ASP_HIP(P, hipMemcpyAsync(&flag3, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, P->stream));
@@ -380,7 +385,9 @@ extern "C" asp_status asp_subsolve(asp_plan* P, int kind, int p, const void* in,
     if (!P->factored) return plan_fail(P, ASP_ERR_STATE, "asp_subsolve before asp_factor");
     asp_status s = ensure_apply_ws(P, nrhs);
     if (s != ASP_OK) return s;
-    if (P->dim == 3) return P->nd ? nd_subsolve(P, idx, in, out, nrhs) : subsolve3d(P, idx, in, out, nrhs);
+    if (P->dim == 3)
+        return P->rec ? rec_subsolve(P, idx, in, out, nrhs)
+                      : P->nd ? nd_subsolve(P, idx, in, out, nrhs) : subsolve3d(P, idx, in, out, nrhs);
     const SubDesc& d = P->subs[idx];
     hipStream_t st = P->stream;
     const size_t row = sizeof(zd);
@@ -424,7 +431,8 @@ extern "C" asp_status asp_workspace_estimate(const asp_plan* P, int nrhs, int re
         const double kr3 = vec3 * (2.0 * restart + 2.0) +
                            (double)nrhs * krylov_blocks(P->N) * 8 * sizeof(zd) +
                            (double)nrhs * 257 * sizeof(zd);
-        *bytes = (P->nd ? nd_workspace_estimate(P, nrhs) : workspace_estimate3(P, nrhs)) + (size_t)kr3;
+        *bytes = (P->rec ? rec_workspace_estimate(P, nrhs)
+                  : P->nd ? nd_workspace_estimate(P, nrhs) : workspace_estimate3(P, nrhs)) + (size_t)kr3;
         return ASP_OK;
     }
     const double vec = (double)nrhs * P->N * sizeof(zd);
@@ -447,6 +455,7 @@ extern "C" asp_status asp_release_workspace(asp_plan* P) {
                     P->d_nd_lb[0], P->d_nd_lb[1], P->d_nd_rb, P->d_nd_db};
     for (void* b : bufs) dev_free(b);
     P->d_nd_v = P->d_nd_x = nullptr;
+    rec_free_ws(P);
     P->d_nd_lb[0] = P->d_nd_lb[1] = nullptr;
     P->d_nd_rb = P->d_nd_db = nullptr;
     P->nd_work_bytes = 0;

@@ -126,6 +126,20 @@ struct NdFront {
     int f, ipad, L, sub, node;
 };
 
+// 3D recursive sweep (Section 5): inner problem (outer, inner) is the
+// auxiliary problem `inner`'s geometry taken along x2 (with equal layer widths
+// the inner partition of a slab along x2 is the outer partition along x3) on
+// the slab of the auxiliary problem `outer` (its x3 lines and profile).  Block
+// k (i1 = k) holds the L_outer x L_inner unknowns (i3, i2) at j = (i3 - lo) +
+// L_outer (i2 - lo2), padded to B with identity rows; the factor stores S_k^-1
+// for every k (n B x B blocks at fac_off).
+struct RecDesc {
+    int outer, inner;    // indices into the auxiliary problems
+    int B;               // padded block size (multiple of 64) >= L_outer L_inner
+    long long fac_off;   // block k = 0 in the factor buffer
+    long long vec_off;   // x1 coupling vector e(j) = 1 / (s2 s3 h^2), B entries
+};
+
 // solve launch modes
 enum { IN_GRID = 0, IN_BOUNDARY = 1, IN_UNIT = 2 };
 enum { OUT_GRID_STORE = 0, OUT_GRID_ADD_U = 1, OUT_GRID_ACC = 2, OUT_LINE = 3 };
@@ -259,6 +273,28 @@ struct asp_plan {
     void* d_nd_db = nullptr;
     size_t nd_work_bytes = 0;
 
+    // 3D recursive sweep (fact3d == ASP_FACT3D_RECURSIVE)
+    bool rec = false;
+    std::vector<RecDesc> rec_desc;            // (3m-2)^2 inner problems, outer-major
+    int rec_Bmax = 0;
+    long long rec_vec_elems = 0;
+    RecDesc* d_rec = nullptr;
+    SubDesc* d_rec_sd = nullptr;              // the same problems as block descriptors (B, fac_off, vec_off)
+    zd* d_rec_e = nullptr;
+    int* d_rec_jobs = nullptr;                // job lists: inner problem indices, then their slots
+    long long rec_jobs_len = 0;               // entries of each of the two halves
+    std::vector<int> rec_jobs_host;           // the same on the host
+    std::vector<long long> rec_list_off;      // start of every job list
+    std::vector<int> rec_list_len;
+    int rec_Lmax = 0;
+    // recursive solve workspaces (chunks of 16 right-hand sides)
+    int rec_chunks = 0;
+    void* d_rec_sv = nullptr;                 // slab vectors: in, U, R, L [slot][chunk][k][i2][i3][16]
+    void* d_rec_w2 = nullptr;                 // inner sweep planes [slot][side][pingpong][chunk][k][i3][16]
+    void* d_rec_g = nullptr;                  // block-solve data and results [chunk][job][k][Bmax][16]
+    void* d_rec_y = nullptr;
+    size_t rec_ws_bytes = 0;
+
     // GMRES workspaces
     int kr_rhs = 0, kr_restart = 0;
     zd* d_V = nullptr;      // (restart+1) * nrhs * N
@@ -359,6 +395,27 @@ struct Solve3Launch {
 };
 hipError_t launch_solve3d_step(const asp_plan* P, const Solve3Launch& L, int k, int fwd,
                                hipStream_t st);
+// the block-recurrence kernels on other descriptors (only B, fac_off and
+// vec_off are read; a descriptor with xs > xe writes no grid output):
+// Gauss-Jordan panel jp of block k of desc[jobs[0..njobs)], and one block step
+// of their solves with data gathered into G and results kept in Y
+// ([chunk][job][k][Bmax][16] each, e the x1 coupling vectors at vec_off)
+hipError_t launch_gj_blocks(const asp_plan* P, const SubDesc* desc, const int* jobs, int njobs,
+                            void* fac, int k, int jp, int Bmax, void* Rbuf, void* Dbuf,
+                            hipStream_t st);
+struct BlockSolve {
+    const SubDesc* desc = nullptr;
+    const int* jobs = nullptr;
+    int njobs = 0;
+    const void* fac = nullptr;
+    void* Y = nullptr;
+    const void* G = nullptr;
+    int Bmax = 0;
+    const zd* e = nullptr;
+    int nact = 0;
+    bool narrow = false;   // 16 rows per workgroup, 16 wavefronts (few problems)
+};
+hipError_t launch_block_step(const asp_plan* P, const BlockSolve& s, int k, int fwd, hipStream_t st);
 // W[job][i1 + n i2][slot] = U on sweep line `line0` (job 0) and `line1` (job 1)
 hipError_t launch_plane3d(const asp_plan* P, const zd* U, int line0, int line1, zd* W,
                           const int* act, int nact, hipStream_t st);
@@ -385,6 +442,9 @@ int krylov_blocks(long long N);
 // fused Gram-Schmidt passes (modes: 0 dots, 1 update then dots, 2 update then
 // norm) over nv <= CGS_MAXV basis vectors; partial sums [rhs][block][CGS_MAXV]
 constexpr int CGS_MAXV = 24;
+// partial sums of |v|^2 per right-hand side, reduced by launch_reduce (one value)
+hipError_t launch_norms(const zd* v, long long N, const int* act, int nact, zd* partial,
+                        hipStream_t st);
 int cgs_blocks(long long N);
 hipError_t launch_cgs(int mode, int nv, const zd* V, long long vstride, const zd* coef,
                       int coef_stride, zd* w, long long N, const int* act, int nact, zd* partial,
@@ -436,6 +496,42 @@ asp_status nd_apply(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
 asp_status nd_subsolve(asp_plan* P, int idx, const void* in, void* out, int nrhs);
 asp_status nd_ensure_ws(asp_plan* P, int nrhs);
 size_t nd_workspace_estimate(const asp_plan* P, int nrhs);
+
+// recursive sweep (rec3d.cpp): inner problems and job lists at setup, factor,
+// apply, one auxiliary solve, workspaces
+asp_status rec_setup(asp_plan* P);
+asp_status rec_upload(asp_plan* P);
+asp_status rec_factor(asp_plan* P);
+asp_status rec_apply(asp_plan* P, const zd* r, zd* z, const int* act, int nact);
+asp_status rec_subsolve(asp_plan* P, int idx, const void* in, void* out, int nrhs);
+asp_status rec_ensure_ws(asp_plan* P, int nrhs);
+size_t rec_workspace_estimate(const asp_plan* P, int nrhs);
+size_t rec_factor_work_estimate(const asp_plan* P);
+void rec_free_ws(asp_plan* P);
+
+// recursive-sweep kernels (rec3d.hip).  A launch covers nslot slabs (outer
+// problems slot_outer[0..nslot)) and nchunk chunks of 16 right-hand sides.
+struct RecLaunch {
+    int nslot = 0, chunks = 0, nact = 0;
+    const int* act = nullptr;
+    const int* slot_outer = nullptr;   // device: outer problem of each slot
+    const int* jobs = nullptr;         // device: inner problem of each job
+    const int* jslot = nullptr;        // device: slot of each job
+    int njobs = 0;
+    int mode = 0;                      // launch-specific (see rec3d.hip)
+    int pp = 0;                        // ping-pong plane of the inner sweeps
+    const zd* rin = nullptr;           // grid data (M) or outer planes (R/L)
+    zd* out0 = nullptr;                // outputs (see launch_rec_slab_out)
+    zd* out1 = nullptr;
+    const zd* U = nullptr;
+    zd* Wout = nullptr;
+};
+hipError_t launch_rec_form(const asp_plan* P, int k, hipStream_t st);
+hipError_t launch_rec_slab_in(const asp_plan* P, const RecLaunch& L, hipStream_t st);
+hipError_t launch_rec_gather(const asp_plan* P, const RecLaunch& L, hipStream_t st);
+hipError_t launch_rec_scatter(const asp_plan* P, const RecLaunch& L, hipStream_t st);
+hipError_t launch_rec_seed(const asp_plan* P, const RecLaunch& L, hipStream_t st);
+hipError_t launch_rec_slab_out(const asp_plan* P, const RecLaunch& L, hipStream_t st);
 
 // nested-dissection kernels (nd3d.hip); fronts fr[0..nfr) of one level
 struct NdLevel {

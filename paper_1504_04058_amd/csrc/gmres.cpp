@@ -111,8 +111,8 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
     };
     // |v[r]|^2 for the active list into small[r][OFF_NRM]
     auto norms = [&](const zd* v, int nact) -> asp_status {
-        ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * nact * N, 8.0 * nact * N,
-                  launch_multidot(v, 0, 0, 1, v, N, P->d_act, nact, P->d_red, st));
+        ASP_TIMED(P, ASP_K_KRYLOV, 16.0 * nact * N, 4.0 * nact * N,
+                  launch_norms(v, N, P->d_act, nact, P->d_red, st));
         ASP_HIP(P, launch_reduce(P->d_red, nblk, 1, P->d_act, nact, small + OFF_NRM, SMALL, st));
         return ASP_OK;
     };

@@ -321,6 +321,23 @@ __global__ __launch_bounds__(BS) void residual_kernel(const zd* __restrict__ b, 
     if (threadIdx.x == 0) norm_partial[((long long)rhs * nblk + blockIdx.x) * CHUNK] = r[0];
 }
 
+// partial sums of |v|^2 (the layout of residual_kernel's)
+__global__ __launch_bounds__(BS) void norm_kernel(const zd* __restrict__ v, long long N,
+                                                const int* __restrict__ act,
+                                                zd* __restrict__ norm_partial) {
+    __shared__ zd sh[BS];
+    const int rhs = act ? act[blockIdx.y] : (int)blockIdx.y;
+    const int nblk = gridDim.x;
+    const zd* vr = v + (long long)rhs * N;
+    double nrm = 0.0;
+    for (long long idx = (long long)blockIdx.x * BS + threadIdx.x; idx < N;
+         idx += (long long)nblk * BS)
+        nrm += abs2(vr[idx]);
+    zd r[1] = {mk(nrm, 0.0)};
+    block_reduce<1>(r, sh);
+    if (threadIdx.x == 0) norm_partial[((long long)rhs * nblk + blockIdx.x) * CHUNK] = r[0];
+}
+
 AxisTables axis_of(const asp_plan* P) {
     return AxisTables{P->d_axis, P->d_axis + (P->n + 1), P->d_axis + (2 * P->n + 1)};
 }
@@ -364,6 +381,12 @@ hipError_t launch_scale_by_s(const asp_plan* P, const zd* f, zd* b, int nrhs, hi
     dim3 grid((unsigned)((P->N + 255) / 256), nrhs);
     hipLaunchKernelGGL(scale_by_s_kernel, grid, dim3(256), 0, st, f, b, axis_of(P), P->n, P->dim,
                        P->N);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms(const zd* v, long long N, const int* act, int nact, zd* partial,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(norm_kernel, dim3(krylov_blocks(N), nact), dim3(BS), 0, st, v, N, act, partial);
     return hipGetLastError();
 }
 

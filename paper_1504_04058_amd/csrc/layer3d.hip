@@ -900,6 +900,66 @@ hipError_t launch_gj3d(const asp_plan* P, const int* jobs, int njobs, int k, int
     return hipGetLastError();
 }
 
+hipError_t launch_gj_blocks(const asp_plan* P, const SubDesc* desc, const int* jobs, int njobs,
+                            void* fac, int k, int jp, int Bmax, void* Rbuf, void* Dbuf,
+                            hipStream_t st) {
+    GjArgs a;
+    a.desc = desc;
+    a.jobs = jobs;
+    a.fr = nullptr;
+    a.mode = GJ_FULL;
+    a.rsel = 0;
+    a.save_c = 0;
+    a.fac = fac;
+    a.Rbuf = Rbuf;
+    a.Dbuf = Dbuf;
+    a.flag = P->d_flag;
+    a.rstride = (long long)Bmax * TB;
+    a.k = k;
+    a.jp = jp;
+    a.ntmax = Bmax / TB;
+    launch_gj(P, a, njobs, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_step(const asp_plan* P, const BlockSolve& s, int k, int fwd,
+                             hipStream_t st) {
+    Solve3Args a{};
+    a.desc = s.desc;
+    a.jobs = s.jobs;
+    a.njobs = s.njobs;
+    a.fac = s.fac;
+    a.Y = s.Y;
+    a.G = s.G;
+    a.yj = (long long)P->n * s.Bmax * RW;
+    a.Bmax = s.Bmax;
+    a.k = k;
+    a.fwd = fwd;
+    a.n = P->n;
+    a.N = P->N;
+    a.S = P->S;
+    a.ax = axis_of(P);
+    a.e3 = s.e;
+    a.gv3 = nullptr;
+    a.in_mode = IN_GRID;
+    a.nact = s.nact;
+    const int chunks = (s.nact + RW - 1) / RW;
+    if (s.narrow) {
+        dim3 grid(s.Bmax / 16, s.njobs, chunks);
+        if (P->prec != ASP_PREC_FP64)
+            hipLaunchKernelGGL((solve3d_step_kernel<float, 16, 1>), grid, dim3(1024), 0, st, a);
+        else
+            hipLaunchKernelGGL((solve3d_step_kernel<double, 8, 1>), grid, dim3(512), 0, st, a);
+    } else {
+        dim3 grid(s.Bmax / 32, s.njobs, chunks);
+        if (P->prec != ASP_PREC_FP64)
+            hipLaunchKernelGGL((solve3d_step_kernel<float, 8, 2>), grid, dim3(512), 0, st, a);
+        else
+            hipLaunchKernelGGL((solve3d_step_kernel<double, 8, 2>), grid, dim3(512), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_gather3d(const asp_plan* P, const int* jobs, int njobs, const zd* r,
                            const int* act, int nact, hipStream_t st) {
     const int chunks = (nact + RW - 1) / RW;

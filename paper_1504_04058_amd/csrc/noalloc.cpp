@@ -110,7 +110,8 @@ extern "C" asp_status asp_apply_noalloc(asp_plan* P, const void* r, void* z, int
         return plan_fail(P, ASP_ERR_STATE, "asp_apply_noalloc before asp_factor");
     if (P->dim == 3 && !P->nd)
         return plan_fail(P, ASP_ERR_ARG,
-                         "asp_apply_noalloc: 3D plans factored by the block recurrence are not supported");
+                         "asp_apply_noalloc: 3D plans factored by the block recurrence or the recursive "
+                         "sweep are not supported");
     WsFields keep;
     keep.save(P);
     const size_t need = lay_out(P, nrhs, nullptr);

@@ -197,8 +197,10 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (o.prec == ASP_PREC_BF16X3 && dim != 3)
         return fail(ASP_ERR_ARG, "the bf16 split precision applies to the 3D factorization only");
     if (dim == 3 && (long long)n * n * n > (1LL << 31)) return fail(ASP_ERR_ARG, "grid too large");
-    if (o.fact3d != ASP_FACT3D_ND && o.fact3d != ASP_FACT3D_BLOCKS)
+    if (o.fact3d != ASP_FACT3D_ND && o.fact3d != ASP_FACT3D_BLOCKS && o.fact3d != ASP_FACT3D_RECURSIVE)
         return fail(ASP_ERR_ARG, "unknown fact3d");
+    if (dim == 3 && o.fact3d == ASP_FACT3D_RECURSIVE && o.n_layers > 0)
+        return fail(ASP_ERR_ARG, "the recursive sweep takes equal layer widths (n_layers = 0)");
 
     P->dim = dim;
     P->n = n;
@@ -282,6 +284,11 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
         asp_status s_nd = nd_setup(P);
         if (s_nd != ASP_OK) return fail(s_nd, P->err.c_str());
     }
+    if (dim == 3 && o.fact3d == ASP_FACT3D_RECURSIVE) {
+        // the recursive sweep: inner problems along x2 of every slab and their factor size
+        asp_status s_rec = rec_setup(P);
+        if (s_rec != ASP_OK) return fail(s_rec, P->err.c_str());
+    }
     P->t_elems = tr_off;
     P->t_bytes = (size_t)tr_off * esz;
 
@@ -349,6 +356,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
         if ((st = upload(P, &P->d_gv3, gv3.data(), gv3.size())) != ASP_OK) return fail(st, P->err.c_str());
     }
     if (P->nd && (st = nd_upload(P)) != ASP_OK) return fail(st, P->err.c_str());
+    if (P->rec && (st = rec_upload(P)) != ASP_OK) return fail(st, P->err.c_str());
     if (hipMalloc(reinterpret_cast<void**>(&P->d_flag), sizeof(int)) != hipSuccess)
         return fail(ASP_ERR_OOM, "hipMalloc failed");
     if (hipMalloc(reinterpret_cast<void**>(&P->d_sink), SINK_ELEMS * sizeof(zd)) != hipSuccess)
@@ -369,7 +377,9 @@ extern "C" void asp_destroy(asp_plan* P) {
                     P->d_T, P->d_U, P->d_W, P->d_stage, P->d_wt, P->d_y, P->d_V, P->d_Z, P->d_b,
                     P->d_red, P->d_small, P->d_act, P->d_e3, P->d_gv3, P->d_y3,
                     P->d_g3, P->d_w3, P->d_nd_nodes, P->d_nd_cols, P->d_nd_inv, P->d_nd_fronts,
-                    P->d_nd_v, P->d_nd_x, P->d_nd_lb[0], P->d_nd_lb[1], P->d_nd_rb, P->d_nd_db};
+                    P->d_nd_v, P->d_nd_x, P->d_nd_lb[0], P->d_nd_lb[1], P->d_nd_rb, P->d_nd_db,
+                    P->d_rec, P->d_rec_sd, P->d_rec_e, P->d_rec_jobs, P->d_rec_sv, P->d_rec_w2,
+                    P->d_rec_g, P->d_rec_y};
     (void)hipStreamSynchronize(P->stream);
     for (void* b : bufs)
         if (b) (void)hipFree(b);

@@ -1,0 +1,151 @@
+"""GPU parity of the recursive sweep of the 3D auxiliary problems (Section 5;
+asp_opts.fact3d = ASP_FACT3D_RECURSIVE) against the oracle's recursive
+preconditioner (oracle.recursive: every quasi-2D problem solved by one
+application of the additive sweeping preconditioner along x2), through the C
+ABI.
+
+Tolerances (relative 2-norm): each approximate G~ and the whole apply with
+FP64 factors 1e-11; FP32 factors: the errors are printed and bounded at about
+ten times the measured ones.  GMRES at the 3D experiments' settings (eta 9h,
+eta_aux 5h, b 4, GMRES(40) to 1e-3): the GPU count within one of the oracle's
+recursive count.  With one layer (m = 1) the recursion is exact, so the
+preconditioner is A^-1."""
+import functools
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import direct, partition
+from oracle.gmres import gmres as oracle_gmres
+from oracle.operator import Problem
+from oracle.recursive import RecursiveSubproblem
+from oracle.sweep import Preconditioner
+
+pytestmark = pytest.mark.gpu
+asp = pytest.importorskip("paper_1504_04058_amd.asp")
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _problem(n, gamma, b, velocity="lens", gamma_aux=None):
+    c = workloads.velocity_lens3d(n) if velocity == "lens" else workloads.velocity_random(n, 3, seed=2, width=3.0)
+    return Problem(3, n, 2 * math.pi * (n + 1) / 8, gamma, 25.0, b, c, gamma_aux=gamma_aux)
+
+
+def _plan(P, prec=asp.ASP_PREC_FP64):
+    return asp.Plan(3, P.c, P.omega, P.n, P.b, P.gamma, C=P.C, prec=prec,
+                    pml_aux=P.gamma_aux if P.gamma_aux != P.gamma else 0,
+                    fact3d=asp.ASP_FACT3D_RECURSIVE)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(n, gamma, b, velocity="lens", gamma_aux=None):
+    P = _problem(n, gamma, b, velocity, gamma_aux)
+    return P, Preconditioner(P, inner=(P.b, P.gamma_aux))
+
+
+CASES = [(19, 4, 4, None), (23, 8, 4, None), (21, 5, 3, 3)]
+
+
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-4)])
+@pytest.mark.parametrize("n,gamma,b,aux", CASES)
+def test_recursive_operators(n, gamma, b, aux, prec, tol):
+    print(f"recursive operators n={n} gamma={gamma} b={b} aux={aux} prec={prec}", flush=True)
+    P = _problem(n, gamma, b, gamma_aux=aux)
+    X = partition.layers(n, b, gamma)
+    subs = partition.subproblems(n, b, gamma, P.gamma_aux)
+    m = len(X)
+    rng = np.random.default_rng(5)
+    picks = {"M": [1, 2, m], "R": [2, m], "L": [1, m - 1]}
+    kinds = {"M": asp.ASP_SUB_M, "R": asp.ASP_SUB_R, "L": asp.ASP_SUB_L}
+    with _plan(P, prec) as plan:
+        plan.factor()
+        for kind, ps in picks.items():
+            for p in sorted(set(ps)):
+                sub = [s for s in subs[kind] if s.p == p][0]
+                ref = RecursiveSubproblem(P, sub, X[p - 1], P.b, P.gamma_aux)
+                Np = P.S * (X[p - 1][1] - X[p - 1][0] + 1)
+                k_in = Np if kind == "M" else P.S
+                data = rng.standard_normal((2, k_in)) + 1j * rng.standard_normal((2, k_in))
+                out = host(plan.subsolve(kinds[kind], p, dev(data), Np)).reshape(2, Np)
+                for r in range(2):
+                    e = rel(out[r], ref.G(data[r]))
+                    print(f"  recursive G~{kind}_{p} prec={prec}: rel err {e:.2e}", flush=True)
+                    assert e < tol, (kind, p, e)
+
+
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-4)])
+@pytest.mark.parametrize("n,gamma,b,aux", CASES + [(31, 8, 4, None)])
+def test_recursive_apply(n, gamma, b, aux, prec, tol):
+    print(f"recursive apply n={n} gamma={gamma} b={b} aux={aux} prec={prec}", flush=True)
+    P, M = _oracle(n, gamma, b, "lens", aux)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal((3, P.N)) + 1j * rng.standard_normal((3, P.N))
+    with _plan(P, prec) as plan:
+        plan.factor()
+        z = host(plan.apply(dev(r)))
+    for k in range(3):
+        e = rel(z[k], M.apply(r[k]))
+        print(f"  recursive apply prec={prec}: rel err {e:.2e}", flush=True)
+        assert e < tol
+
+
+def test_recursive_many_rhs():
+    """18 right-hand sides: two 16-wide chunks through every slab and plane buffer."""
+    P, M = _oracle(19, 4, 4)
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal((18, P.N)) + 1j * rng.standard_normal((18, P.N))
+    with _plan(P) as plan:
+        plan.factor()
+        z = host(plan.apply(dev(r)))
+    for k in (0, 15, 16, 17):
+        assert rel(z[k], M.apply(r[k])) < 1e-11, k
+
+
+def test_recursive_single_layer_is_exact():
+    """n = 15, gamma = 8: one layer along x3 and one along x2, so the recursion
+    solves the slab exactly and the preconditioner is A^-1."""
+    P = _problem(15, 8, 4)
+    assert len(partition.layers(15, 4, 8)) == 1
+    r = np.random.default_rng(0).standard_normal(P.N) + 0j
+    with _plan(P) as plan:
+        plan.factor()
+        z = host(plan.apply(dev(r[None])))[0]
+    assert rel(z, direct.solve(P.A(), r)) < 1e-10
+
+
+@pytest.mark.parametrize("field", list(workloads.PAPER_FIELDS))
+def test_recursive_gmres_paper_settings(field):
+    print(f"recursive GMRES paper settings n=23 field={field}", flush=True)
+    w = workloads.paper_workload3d(field, 23)
+    P = Problem.from_workload(w)
+    A = P.A()
+    M = Preconditioner(P, inner=(w["b"], w["gamma_aux"]))
+    with asp.Plan(3, w["c"], w["omega"], w["n"], w["b"], w["gamma"], C=w["C"],
+                  pml_aux=w["gamma_aux"], fact3d=asp.ASP_FACT3D_RECURSIVE) as plan:
+        u, it, rr, st = plan.gmres(dev(w["f"]), tol=w["tol"], restart=w["restart"], maxit=100)
+        u = host(u)
+    assert st == asp.ASP_OK
+    for k in range(w["f"].shape[0]):
+        b = w["f"][k] / P.scale()
+        _, it_ref, _, _ = oracle_gmres(lambda v: A @ v, M.apply, b, w["tol"], w["restart"], 100)
+        print(f"  rhs {k}: iters {int(it[k])} (oracle recursive {it_ref})", flush=True)
+        assert abs(int(it[k]) - it_ref) <= 1
+        assert np.linalg.norm(b - A @ u[k]) / np.linalg.norm(b) <= w["tol"] * (1 + 1e-9)

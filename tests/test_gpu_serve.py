@@ -91,3 +91,25 @@ def test_tight_budget_evicts_and_stays_within_it():
     assert summ["completed"] == len(reqs)
     assert summ["peak_bytes"] <= budget
     assert summ["evictions"] > 0
+
+
+def test_served_equals_alone_with_3d_keys():
+    """A stream mixing 2D and 3D keys (3D n = 19, 23 by nested dissection):
+    every request's solution and iteration count are bitwise the same as when
+    it is solved alone in a fresh plan, and 3D keys run concurrently with 2D
+    ones on their own streams."""
+    descs = workloads.request_stream(count=16, rate=400.0, seed=13,
+                                     sizes=((2, 31), (3, 19), (3, 23)), max_rhs=5)
+    assert {d["d"] for d in descs} == {2, 3}
+    reqs = [serve.Request.from_description(d) for d in descs]
+    backend = serve.AspBackend(prec=asp.ASP_PREC_FP32, tol=1e-6, restart=20, maxit=400)
+    srv = serve.Server(backend, budget_bytes=16 << 30, max_rhs=16, workers=3)
+    res, summ = srv.run(reqs)
+    print(summ, flush=True)
+    assert summ["completed"] == len(reqs), [r.status for r in res]
+    for r in res:
+        assert r.status == "ASP_OK" and np.all(r.relres <= 1e-6)
+    for d, r in zip(descs, res):
+        u1, it1, _ = _alone(d, asp.ASP_PREC_FP32)
+        assert np.array_equal(it1, r.iters), d["rid"]
+        assert np.array_equal(u1, r.u), d["rid"]
