@@ -69,6 +69,14 @@ def parse():
                     help="second workload timed after the first (same steps and warmup), '' for none")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the seeded serving stream timed after the batch runs (0: none)")
+    ap.add_argument("--serve-spec", type=int, default=0, metavar="COUNT",
+                    help="only run the full serving mix (2D n = 127..1023, 3D n = 31, 63, 1-32 "
+                         "right-hand sides, half the requests repeating a key) of COUNT requests: "
+                         "at saturation, then at fractions of the saturated request rate")
+    ap.add_argument("--serve-fractions", default="0.5,0.8",
+                    help="offered loads of --serve-spec as fractions of the saturated rate")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0,
+                    help="device memory the served factors and workspaces may hold")
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="auxiliary problems of each kind the oracle factors and solves")
     ap.add_argument("--paper-tables", default="",
@@ -206,7 +214,8 @@ def recorded_traffic(workload, prec_name, cls):
     return c["fetch_bytes"] + c["write_bytes"]
 
 
-def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=True, keep_u=False):
+def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=True, keep_u=False,
+                 fact3d=None):
     """Time `steps` passes of the hot path (factor + GMRES of the whole batch)
     after `warmup` untimed passes; returns the measurements (and the last
     solution, on the device, if keep_u)."""
@@ -227,7 +236,7 @@ def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=Tr
     f = torch.from_numpy(w["f"]).to(dev)
     u = torch.empty_like(f)
     plan = asp.Plan(w["d"], w["c"], w["omega"], w["n"], w["b"], w["gamma"], C=w["C"], prec=prec,
-                    nd3d=nd3d)
+                    nd3d=nd3d, fact3d=fact3d)
     h = plan.handle
     L = asp.lib()
     for _ in range(warmup):
@@ -314,6 +323,46 @@ def serving_run(count, prec_name):
     summ["mean_batch_rhs"] = (sum(sum(reqs[i].nrhs for i in ids) for _, ids in srv.batches) /
                               max(len(srv.batches), 1))
     return summ
+
+
+def serving_spec(prec_name, count, fractions, budget_gb):
+    """The full serving mix: a seeded Poisson stream of `count` requests (2D
+    n = 127, 255, 511, 1023 and 3D n = 31, 63 with omega = 2 pi n / 8; constant,
+    lens and random velocities; 1-32 right-hand sides; each request repeats an
+    earlier key with probability 1/2).  First all requests arrive at once (the
+    saturated throughput and request rate), then the same stream arrives in
+    real time at each fraction of the saturated request rate.  Requests build
+    their inputs when they are served."""
+    import workloads
+    from paper_1504_04058_amd import asp, serve
+
+    prec = asp.ASP_PREC_FP32 if prec_name == "fp32" else asp.ASP_PREC_FP64
+    budget = int(budget_gb * (1 << 30))
+
+    def one(rate, realtime):
+        descs = workloads.request_stream(count=count, rate=rate, seed=5, max_rhs=32)
+        reqs = [serve.Request.from_description(d) for d in descs]
+        backend = serve.AspBackend(prec=prec, keep_u=False)
+        srv = serve.Server(backend, budget_bytes=budget, max_rhs=64, workers=4, realtime=realtime,
+                           progress_every=max(1, count // 10))
+        res, summ = srv.run(reqs)
+        backend.close()
+        summ["offered_rate_per_s"] = rate if realtime else None
+        summ["keys"] = len({d["key"] for d in descs})
+        summ["batches"] = len(srv.batches)
+        return summ
+
+    print(f"serve-spec: {count} requests, saturation run", flush=True)
+    sat = one(1.0, False)
+    sat_rate = sat["completed"] / sat["wall_s"]
+    out = {"stream": {"requests": count, "seed": 5, "sizes": "2D n = 127, 255, 511, 1023; 3D n = 31, 63",
+                      "rhs_per_request": "1-32", "repeat": 0.5, "budget_gb": budget_gb,
+                      "layer_precision": prec_name},
+           "saturation": dict(sat, request_rate_per_s=sat_rate), "loads": []}
+    for f in fractions:
+        print(f"serve-spec: offered load {f:.2f} x {sat_rate:.2f} requests/s", flush=True)
+        out["loads"].append(dict(one(f * sat_rate, True), fraction=f))
+    return out
 
 
 def paper_tables(prec_name, sizes, dim=2, widths=None, nd3d=True):
@@ -444,6 +493,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 4}), flush=True)
         return
+    if args.serve_spec:
+        spec = serving_spec(args.prec, args.serve_spec,
+                            [float(x) for x in args.serve_fractions.split(",")], args.serve_budget_gb)
+        print(json.dumps({"serving_spec": spec}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
@@ -487,21 +541,26 @@ def main():
     r["u"] = None
     if args.secondary:
         d2 = workloads_dim(args.secondary)
-        for key, prec, nd in (("secondary", args.prec, True), ("secondary_bf16x3", "bf16x3", True),
-                              ("secondary_blocks", args.prec, False),
-                              ("secondary_fp64", "fp64", True)):
-            if (prec == "bf16x3" or not nd) and d2 != 3:
+        from paper_1504_04058_amd import asp
+
+        names = {asp.ASP_FACT3D_ND: "nested dissection", asp.ASP_FACT3D_BLOCKS: "block recurrence",
+                 asp.ASP_FACT3D_RECURSIVE: "recursive sweep along x2"}
+        for key, prec, f3 in (("secondary", args.prec, asp.ASP_FACT3D_ND),
+                              ("secondary_bf16x3", "bf16x3", asp.ASP_FACT3D_ND),
+                              ("secondary_blocks", args.prec, asp.ASP_FACT3D_BLOCKS),
+                              ("secondary_recursive", args.prec, asp.ASP_FACT3D_RECURSIVE),
+                              ("secondary_fp64", "fp64", asp.ASP_FACT3D_ND)):
+            if (prec == "bf16x3" or f3 != asp.ASP_FACT3D_ND) and d2 != 3:
                 continue
             if key == "secondary_fp64" and (args.prec == "fp64" or args.no_plain_fp64):
                 continue
-            s2 = run_workload(args.secondary, prec, args.steps, args.warmup, nd3d=nd,
-                              keep_u=key in ("secondary", "secondary_bf16x3", "secondary_fp64"))
-            out[key] = line_of(args.secondary, s2, prec,
-                               factorization=("nested dissection" if nd else "block recurrence")
-                               if d2 == 3 else None)
+            s2 = run_workload(args.secondary, prec, args.steps, args.warmup, fact3d=f3 if d2 == 3 else None,
+                              keep_u=key in ("secondary", "secondary_bf16x3", "secondary_fp64",
+                                             "secondary_recursive"))
+            out[key] = line_of(args.secondary, s2, prec, factorization=names[f3] if d2 == 3 else None)
             out[key]["_run"] = s2
         base = out.get("secondary_fp64", {}).get("_run")
-        for key in ("secondary", "secondary_bf16x3"):
+        for key in ("secondary", "secondary_bf16x3", "secondary_recursive"):
             if base is not None and key in out:
                 out[key]["vs_fp64"] = compare_runs(out[key]["_run"], base)
         for key in list(out):

@@ -82,6 +82,17 @@ typedef enum {
                                (the outer GMRES is flexible); equal layer widths only */
 } asp_fact3d;
 
+typedef enum {
+    ASP_SWEEP2D_MAPS = 0,      /* the factorization also computes, for every R_p and L_p with
+                                  1 < p < m, the dense n x n map from the boundary data it
+                                  receives to the boundary line it hands on; a sweep step is
+                                  then one map product, and all R/L solves run at once after
+                                  the sweeps.  O(n^3 / b) map entries and setup O(n^3 L^2 / b) */
+    ASP_SWEEP2D_SEQUENTIAL = 1 /* Algorithm 2 as stated: the sweeps solve R_2 .. R_m and
+                                  L_{m-1} .. L_1 one after another (each R/L pair in one launch),
+                                  each handing its boundary line to the next; no maps */
+} asp_sweep2d;
+
 typedef struct {
     double C;       /* PML strength (Section 2, "an appropriate positive constant"); default 25 */
     int prec;       /* asp_prec; default ASP_PREC_FP64 */
@@ -107,6 +118,9 @@ typedef struct {
                        factored; default ASP_FACT3D_ND.  ND and BLOCKS give the same
                        operator G~, RECURSIVE an approximation of it.  Ignored by 2D
                        plans; other values ASP_ERR_ARG */
+    int sweep2d;    /* asp_sweep2d: how a 2D apply moves boundary values between layers;
+                       default ASP_SWEEP2D_MAPS.  Both give the same operator.  Ignored by
+                       3D plans; other values ASP_ERR_ARG */
 } asp_opts;
 
 typedef struct {

@@ -21,6 +21,7 @@ ASP_ERR_BREAKDOWN, ASP_ERR_NOCONV, ASP_ERR_DEVICE = 4, 5, 6
 ASP_PREC_FP64, ASP_PREC_FP32, ASP_PREC_BF16X3 = 0, 1, 2
 ASP_SUB_M, ASP_SUB_R, ASP_SUB_L = 0, 1, 2
 ASP_FACT3D_ND, ASP_FACT3D_BLOCKS, ASP_FACT3D_RECURSIVE = 0, 1, 2
+ASP_SWEEP2D_MAPS, ASP_SWEEP2D_SEQUENTIAL = 0, 1
 STATUS_NAMES = {0: "ASP_OK", 1: "ASP_ERR_ARG", 2: "ASP_ERR_OOM", 3: "ASP_ERR_STATE",
                 4: "ASP_ERR_BREAKDOWN", 5: "ASP_ERR_NOCONV", 6: "ASP_ERR_DEVICE"}
 
@@ -35,7 +36,7 @@ class asp_opts(ctypes.Structure):
     _fields_ = [("C", ctypes.c_double), ("prec", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("host_only", ctypes.c_int), ("pml_aux", ctypes.c_int),
                 ("n_layers", ctypes.c_int), ("layer_widths", ctypes.POINTER(ctypes.c_int)),
-                ("fact3d", ctypes.c_int)]
+                ("fact3d", ctypes.c_int), ("sweep2d", ctypes.c_int)]
 
 
 class asp_plan_info(ctypes.Structure):
@@ -121,7 +122,7 @@ def _current_stream():
 # -- the C entry points --------------------------------------------------------------
 
 def asp_setup(dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64, stream=None,
-              host_only=False, pml_aux=0, nd3d=True, fact3d=None):
+              host_only=False, pml_aux=0, nd3d=True, fact3d=None, sweep2d=ASP_SWEEP2D_MAPS):
     """Returns a plan handle (ctypes.c_void_p).  c: host array, n**dim velocities
     (column-major, i.e. numpy order='F' flattening of an (n,)*dim array).
     layer_b: lines per layer, or a sequence of physical lines per layer
@@ -132,7 +133,8 @@ def asp_setup(dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64, st
     opts = asp_opts(C, prec, stream if stream is not None else
                     (ctypes.c_void_p(0) if host_only else _current_stream()), int(host_only),
                     int(pml_aux or 0), 0, None,
-                    fact3d if fact3d is not None else (ASP_FACT3D_ND if nd3d else ASP_FACT3D_BLOCKS))
+                    fact3d if fact3d is not None else (ASP_FACT3D_ND if nd3d else ASP_FACT3D_BLOCKS),
+                    int(sweep2d))
     if not isinstance(layer_b, (int, np.integer)):
         widths = (ctypes.c_int * len(layer_b))(*[int(w) for w in layer_b])
         opts.n_layers = len(layer_b)
@@ -246,11 +248,12 @@ class Plan:
     """Owning wrapper around a plan handle (destroyed with the object)."""
 
     def __init__(self, dim, c, omega, n, layer_b, pml_eta, C=25.0, prec=ASP_PREC_FP64,
-                 host_only=False, pml_aux=0, nd3d=True, fact3d=None):
+                 host_only=False, pml_aux=0, nd3d=True, fact3d=None, sweep2d=ASP_SWEEP2D_MAPS):
         self.dim, self.n = dim, n
         self.N = n ** dim
         self.handle = asp_setup(dim, c, omega, n, layer_b, pml_eta, C=C, prec=prec,
-                                host_only=host_only, pml_aux=pml_aux, nd3d=nd3d, fact3d=fact3d)
+                                host_only=host_only, pml_aux=pml_aux, nd3d=nd3d, fact3d=fact3d,
+                                sweep2d=sweep2d)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -225,6 +225,55 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
         t.end();
     }
     if (m == 1) return ASP_OK;
+    if (P->sweep_seq) {
+        // Algorithm 2 as stated: R_{t+1} and L_{m-t} solved in step t (one launch),
+        // each handing its outgoing boundary line (plus u~) to the next problem of
+        // its sweep; R outputs a_p in z, L outputs c_p in the staging grid
+        double sb = 0, sf = 0;
+        for (int t = 1; t <= m - 1; ++t) {
+            double b1, f1;
+            solve_cost(P, P->idx_R(t + 1), 1, nact, 2.0, &b1, &f1);
+            sb += b1;
+            sf += f1;
+            solve_cost(P, P->idx_L(m - t), 1, nact, 2.0, &b1, &f1);
+            sb += b1;
+            sf += f1;
+        }
+        KTimer t(P, ASP_K_SWEEP, sb, sf, 1 + (m - 1) + (m - 2));
+        const long long rowR = (long long)P->wrow(P->idx_R(2)) * w_rhs * P->n;
+        const long long rowL = (long long)P->wrow(P->idx_L(m - 1)) * w_rhs * P->n;
+        ASP_HIP(P, launch_sweep_seed(P, P->d_W, rowR, rowL, act, nact, st));
+        const int nsub = (int)P->subs.size();
+        for (int s = 1; s <= m - 1; ++s) {
+            SolveLaunch L;
+            L.job0 = nsub + 2 * (s - 1);
+            L.njobs = 2;
+            L.rl = true;
+            L.act = act;
+            L.nact = nact;
+            L.in_mode = IN_BOUNDARY;
+            L.out_mode = OUT_GRID_STORE;
+            L.out = z;
+            L.out_mode_L = OUT_GRID_STORE;
+            L.out_L = P->d_stage;
+            L.W = P->d_W;
+            L.w_rhs = w_rhs;
+            L.Ugrid = P->d_U;
+            ASP_HIP(P, launch_solve2d(P, L, st));
+            if (s < m - 1)
+                ASP_HIP(P, launch_sweep_hand(
+                               P, z, P->d_stage, P->d_W,
+                               (long long)P->wrow(P->idx_R(s + 2)) * w_rhs * P->n, P->X[s][1],
+                               (long long)P->wrow(P->idx_L(m - s - 1)) * w_rhs * P->n,
+                               P->X[m - s - 1][0], act, nact, st));
+        }
+        t.end();
+        KTimer tc(P, ASP_K_COMBINE, 5.0 * nact * (double)P->N * sizeof(zd), 0.0);
+        ASP_HIP(P, launch_combine3d(P, z, P->d_U, P->d_stage, P->X[0][1], P->X[m - 2][1], true,
+                                    act, nact, st));
+        tc.end();
+        return ASP_OK;
+    }
     // the two sweeps: the boundary values u~^R_{p,1:p} and u~^L_{p,p:m}
     // accumulated layer by layer (W rows hold the data entering R_p / L_p); the
     // seed and the m-2 steps are timed as one span of m-1 launches
@@ -345,7 +394,7 @@ extern "C" asp_status asp_factor(asp_plan* P) {
     ASP_HIP(P, hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, P->stream));
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     if (flag) return plan_fail(P, ASP_ERR_BREAKDOWN, "zero or non-finite pivot in a layer factorization");
-    if ((s = compute_transfer(P)) != ASP_OK) return s;
+    if (!P->sweep_seq && (s = compute_transfer(P)) != ASP_OK) return s;
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     P->factored = true;
     return ASP_OK;

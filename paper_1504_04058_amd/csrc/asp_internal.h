@@ -171,6 +171,7 @@ struct asp_plan {
     int gamma_aux = 0;                // PML width of the pads facing another layer
     double omega = 0, h = 0, C = 25.0;
     int prec = ASP_PREC_FP64;
+    bool sweep_seq = false;           // 2D: the sweeps as sequential R/L solves (no maps)
     hipStream_t stream = nullptr;
     bool host_only = false;  // partition and tables only, no device state
     long long N = 0, S = 0;  // unknowns, unknowns per line
@@ -362,6 +363,12 @@ long long solve_scratch_per_block(const asp_plan* P);
 // the W rows that start the two sweeps (from u~_{1,1} and u~_{m,m} in U)
 hipError_t launch_sweep_seed(const asp_plan* P, zd* W, long long outR, long long outL,
                              const int* act, int nact, hipStream_t st);
+// the boundary lines the R_{t+1} / L_{m-t} solves of a sequential sweep step hand
+// on: W rows rowR / rowL (R outputs in z, L outputs in stage, both without U)
+// get the output plus U on line lineR / lineL
+hipError_t launch_sweep_hand(const asp_plan* P, const zd* z, const zd* stage, zd* W,
+                             long long rowR, int lineR, long long rowL, int lineL, const int* act,
+                             int nact, hipStream_t st);
 // sweep step t = 1..m-2 (both directions); workspace sizes for nrhs right-hand sides
 int sweep_wt_len(const asp_plan* P, int nrhs);
 hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const int* act, int nact,

@@ -825,7 +825,38 @@ __global__ void sweep_seed_kernel(const zd* __restrict__ Ugrid, zd* __restrict__
     WtL[(long long)k * ws + slot] = ccast<T>(vL);
 }
 
+// Sequential sweep step: the boundary line R_{t+1} hands to R_{t+2} (its
+// output a plus u~ on the last line of its layer) and the one L_{m-t} hands to
+// L_{m-t-1} (c plus u~ on the first line of its layer) into their W rows
+__global__ void sweep_hand_kernel(const zd* __restrict__ z, const zd* __restrict__ stage,
+                                  const zd* __restrict__ Ugrid, zd* __restrict__ W,
+                                  long long rowR, int lineR, long long rowL, int lineL,
+                                  const int* __restrict__ act, int n, long long N) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int id = act ? act[blockIdx.y] : (int)blockIdx.y;
+    const long long u = (long long)id * N + k;
+    if (rowR >= 0) {
+        const long long g = u + (long long)n * (lineR - 1);
+        W[rowR + (long long)id * n + k] = z[g] + Ugrid[g];
+    }
+    if (rowL >= 0) {
+        const long long g = u + (long long)n * (lineL - 1);
+        W[rowL + (long long)id * n + k] = stage[g] + Ugrid[g];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_sweep_hand(const asp_plan* P, const zd* z, const zd* stage, zd* W,
+                             long long rowR, int lineR, long long rowL, int lineL, const int* act,
+                             int nact, hipStream_t st) {
+    if (nact <= 0) return hipSuccess;
+    dim3 grid((P->n + 255) / 256, nact);
+    hipLaunchKernelGGL(sweep_hand_kernel, grid, dim3(256), 0, st, z, stage, P->d_U, W, rowR, lineR,
+                       rowL, lineL, act, P->n, P->N);
+    return hipGetLastError();
+}
 
 hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
     const int nsub = (int)P->subs.size();

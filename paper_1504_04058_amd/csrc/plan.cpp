@@ -148,6 +148,7 @@ extern "C" void asp_default_opts(asp_opts* o) {
     o->n_layers = 0;
     o->layer_widths = nullptr;
     o->fact3d = ASP_FACT3D_ND;
+    o->sweep2d = ASP_SWEEP2D_MAPS;
 }
 
 extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double omega, int n,
@@ -199,6 +200,8 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (dim == 3 && (long long)n * n * n > (1LL << 31)) return fail(ASP_ERR_ARG, "grid too large");
     if (o.fact3d != ASP_FACT3D_ND && o.fact3d != ASP_FACT3D_BLOCKS && o.fact3d != ASP_FACT3D_RECURSIVE)
         return fail(ASP_ERR_ARG, "unknown fact3d");
+    if (o.sweep2d != ASP_SWEEP2D_MAPS && o.sweep2d != ASP_SWEEP2D_SEQUENTIAL)
+        return fail(ASP_ERR_ARG, "unknown sweep2d");
     if (dim == 3 && o.fact3d == ASP_FACT3D_RECURSIVE && o.n_layers > 0)
         return fail(ASP_ERR_ARG, "the recursive sweep takes equal layer widths (n_layers = 0)");
 
@@ -212,6 +215,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     P->h = 1.0 / (n + 1);
     P->C = o.C;
     P->prec = o.prec;
+    P->sweep_seq = dim == 2 && o.sweep2d == ASP_SWEEP2D_SEQUENTIAL;
     P->stream = reinterpret_cast<hipStream_t>(o.stream);
     P->S = (dim == 2) ? n : (long long)n * n;
     P->N = P->S * n;
@@ -260,7 +264,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
             fac_off += (long long)n * d.L * d.LR;
             // the sweeps step through R_p and L_p for 1 < p < m with their dense
             // maps, stored in row tiles of 16 (rows padded to a multiple of 16)
-            if (d.kind != ASP_SUB_M && d.p > 1 && d.p < P->m) {
+            if (!P->sweep_seq && d.kind != ASP_SUB_M && d.p > 1 && d.p < P->m) {
                 d.tr_off = tr_off;
                 tr_off += (long long)((n + 15) / 16 * 16) * n;
             }
@@ -338,12 +342,11 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     // a launch takes a contiguous range of it
     std::vector<int> jobs(P->subs.size());
     for (size_t s = 0; s < P->subs.size(); ++s) jobs[s] = (int)s;
-    // 3D: sweep step t = 1..m-1 runs R_{t+1} and L_{m-t} together (two entries each)
-    if (dim == 3)
-        for (int t = 1; t <= P->m - 1; ++t) {
-            jobs.push_back(P->idx_R(t + 1));
-            jobs.push_back(P->idx_L(P->m - t));
-        }
+    // sweep step t = 1..m-1 runs R_{t+1} and L_{m-t} together (two entries each)
+    for (int t = 1; t <= P->m - 1; ++t) {
+        jobs.push_back(P->idx_R(t + 1));
+        jobs.push_back(P->idx_L(P->m - t));
+    }
 
     asp_status st;
     if ((st = upload(P, &P->d_axis, axis.data(), axis.size())) != ASP_OK) return fail(st, P->err.c_str());

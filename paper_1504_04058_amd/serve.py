@@ -203,7 +203,7 @@ class Server:
     (sorted by arrival) and returns the results and summary statistics."""
 
     def __init__(self, backend: Backend, budget_bytes: int, max_rhs: int = 64, workers: int = 4,
-                 realtime: bool = True):
+                 realtime: bool = True, progress_every: int = 0):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_rhs = max_rhs
@@ -219,6 +219,8 @@ class Server:
         self.evictions = 0
         self.factorizations = 0
         self.batches = []           # (key, request ids) of every solve launched
+        self.progress_every = progress_every   # print a line every so many completed requests
+        self._completed = 0
 
     # -- memory ------------------------------------------------------------------------
     def _reserve(self, nbytes):
@@ -355,6 +357,13 @@ class Server:
                 e.busy = False
                 e.last_used = time.perf_counter()
                 self._used -= ws
+                if self.progress_every:
+                    before = self._completed // self.progress_every
+                    self._completed += len(batch)
+                    if self._completed // self.progress_every > before:
+                        print(f"serve: {self._completed} requests done at {done:.1f} s, "
+                              f"{self.factorizations} factorizations, {self.evictions} evictions",
+                              flush=True)
                 self._lock.notify_all()
 
     def run(self, requests: List[Request]):

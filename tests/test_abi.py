@@ -303,3 +303,53 @@ def test_bf16_split_precision_is_3d_only(L):
             asp.asp_destroy(fp32)
     finally:
         asp.asp_destroy(plan)
+
+
+def test_sequential_sweep_plan(L):
+    """opts.sweep2d (Algorithm 2 as stated): the same partition and layer
+    factors as the default, without the n x n boundary maps; 3D plans ignore
+    the field; unknown values are rejected."""
+    n, b, gamma = 255, 4, 12
+    c = np.ones(n * n)
+    maps = asp.asp_setup(2, c, 10.0, n, b, gamma, host_only=True, prec=asp.ASP_PREC_FP32)
+    seq = asp.asp_setup(2, c, 10.0, n, b, gamma, host_only=True, prec=asp.ASP_PREC_FP32,
+                        sweep2d=asp.ASP_SWEEP2D_SEQUENTIAL)
+    try:
+        a, s_ = asp.asp_info(maps), asp.asp_info(seq)
+        m = a["m"]
+        assert s_["m"] == m and s_["n_sub"] == a["n_sub"]
+        assert a["factor_bytes"] - s_["factor_bytes"] == 2 * (m - 2) * (-(-n // 16) * 16) * n * 8
+    finally:
+        asp.asp_destroy(maps)
+        asp.asp_destroy(seq)
+    p3 = asp.asp_setup(3, np.ones(23 ** 3), 10.0, 23, 4, 8, host_only=True,
+                       sweep2d=asp.ASP_SWEEP2D_SEQUENTIAL)
+    asp.asp_destroy(p3)
+    opts = asp.asp_opts(25.0, asp.ASP_PREC_FP64, None, 1, 0, 0, None, 0, 5)
+    plan = ctypes.c_void_p()
+    st = L.asp_setup(ctypes.byref(plan), 2, c.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(10.0),
+                     n, b, gamma, ctypes.byref(opts))
+    assert st == asp.ASP_ERR_ARG and "sweep2d" in asp.asp_last_error(plan)
+    asp.asp_destroy(plan)
+
+
+def test_recursive_plan(L):
+    """opts.fact3d = ASP_FACT3D_RECURSIVE (Section 5): (3m-2)^2 inner problems,
+    inner problem (outer o, inner i) factored as n blocks of B x B with B =
+    L_o L_i rounded up to a multiple of 64; unequal layer widths are refused."""
+    n, b, gamma = 31, 4, 8
+    c = np.ones(n ** 3)
+    plan = asp.asp_setup(3, c, 10.0, n, b, gamma, host_only=True, prec=asp.ASP_PREC_FP32,
+                         fact3d=asp.ASP_FACT3D_RECURSIVE)
+    try:
+        info = asp.asp_info(plan)
+    finally:
+        asp.asp_destroy(plan)
+    subs = partition.subproblems(n, b, gamma)
+    Ls = [s.L for k in ("M", "R", "L") for s in subs[k]]
+    want = sum(n * (-(-lo * li // 64) * 64) ** 2 for lo in Ls for li in Ls)
+    assert info["factor_bytes"] == want * 8 and info["n_sub"] == len(Ls)
+    with pytest.raises(asp.AspError) as e:
+        asp.asp_setup(3, c, 10.0, n, [5, 5, 7], gamma, host_only=True,
+                      fact3d=asp.ASP_FACT3D_RECURSIVE)
+    assert e.value.status == asp.ASP_ERR_ARG and "equal layer widths" in str(e.value)

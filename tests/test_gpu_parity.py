@@ -221,3 +221,45 @@ def test_alone_equals_in_batch():
             u1, it1, _, _ = plan.gmres(dev(w["f"][k:k + 1]), tol=1e-6, restart=20, maxit=100)
             assert int(it1[0]) == int(it_all[k])
             assert np.array_equal(host(u1)[0], u_all[k])
+
+
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 8e-6)])
+@pytest.mark.parametrize("n,gamma,b", [(63, 12, 4), (100, 12, 4), (127, 9, 8)])
+def test_apply_sequential_sweep(n, gamma, b, prec, tol):
+    """opts.sweep2d = ASP_SWEEP2D_SEQUENTIAL (Algorithm 2 as stated, no boundary
+    maps): the apply against the oracle, and against the default path with
+    the maps (the same operator, rounding apart)."""
+    P = _problem(n, gamma, b)
+    M = Preconditioner(P)
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal((3, P.N)) + 1j * rng.standard_normal((3, P.N))
+    with asp.Plan(2, P.c, P.omega, n, b, gamma, C=P.C, prec=prec,
+                  sweep2d=asp.ASP_SWEEP2D_SEQUENTIAL) as plan:
+        plan.factor()
+        z = host(plan.apply(dev(r)))
+    with _plan(P, prec) as plan:
+        plan.factor()
+        zm = host(plan.apply(dev(r)))
+    for k in range(3):
+        e = rel(z[k], M.apply(r[k]))
+        print(f"2D sequential-sweep apply n={n} prec={prec}: rel err {e:.2e}, vs maps "
+              f"{rel(z[k], zm[k]):.2e}", flush=True)
+        assert e < tol
+        assert rel(z[k], zm[k]) < (1e-12 if prec == asp.ASP_PREC_FP64 else 2 * tol)
+
+
+def test_gmres_sequential_sweep_counts():
+    """GMRES with the sequential sweeps takes the oracle's iteration counts."""
+    w = workloads.workload("2d_n511_lens", n=127, nrhs=3)
+    P = Problem.from_workload(w)
+    with asp.Plan(2, w["c"], w["omega"], w["n"], w["b"], w["gamma"], C=w["C"],
+                  sweep2d=asp.ASP_SWEEP2D_SEQUENTIAL) as plan:
+        u, it, rr, st = plan.gmres(dev(w["f"]), tol=1e-6, restart=20, maxit=200)
+        u = host(u)
+    assert st == asp.ASP_OK
+    A, M = P.A(), Preconditioner(P)
+    for k in range(3):
+        b = w["f"][k] / P.scale()
+        x_ref, it_ref, _, _ = oracle_gmres(lambda v: A @ v, M.apply, b, 1e-6, 20, 200)
+        assert abs(int(it[k]) - it_ref) <= 1
+        assert rel(u[k], x_ref) < 1e-6

@@ -5,8 +5,8 @@ application of the additive sweeping preconditioner along x2), through the C
 ABI.
 
 Tolerances (relative 2-norm): each approximate G~ and the whole apply with
-FP64 factors 1e-11; FP32 factors: the errors are printed and bounded at about
-ten times the measured ones.  GMRES at the 3D experiments' settings (eta 9h,
+FP64 factors 1e-11; FP32 factors 5e-5 per operator and 8e-5 per apply, about
+ten times the largest measured errors (4.2e-6 and 7.3e-6).  GMRES at the 3D experiments' settings (eta 9h,
 eta_aux 5h, b 4, GMRES(40) to 1e-3): the GPU count within one of the oracle's
 recursive count.  With one layer (m = 1) the recursion is exact, so the
 preconditioner is A^-1."""
@@ -64,7 +64,7 @@ def _oracle(n, gamma, b, velocity="lens", gamma_aux=None):
 CASES = [(19, 4, 4, None), (23, 8, 4, None), (21, 5, 3, 3)]
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-4)])
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 5e-5)])
 @pytest.mark.parametrize("n,gamma,b,aux", CASES)
 def test_recursive_operators(n, gamma, b, aux, prec, tol):
     print(f"recursive operators n={n} gamma={gamma} b={b} aux={aux} prec={prec}", flush=True)
@@ -91,7 +91,7 @@ def test_recursive_operators(n, gamma, b, aux, prec, tol):
                     assert e < tol, (kind, p, e)
 
 
-@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 1e-4)])
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 8e-5)])
 @pytest.mark.parametrize("n,gamma,b,aux", CASES + [(31, 8, 4, None)])
 def test_recursive_apply(n, gamma, b, aux, prec, tol):
     print(f"recursive apply n={n} gamma={gamma} b={b} aux={aux} prec={prec}", flush=True)
