@@ -87,6 +87,9 @@ def parse():
     ap.add_argument("--paper-blocks3d", action="store_true",
                     help="factor the 3D paper tables by the dense block recurrence instead of "
                          "nested dissection")
+    ap.add_argument("--sweep-compare", default="",
+                    help="comma-separated 2D grid sizes: time the boundary-map sweeps against the "
+                         "sequential R/L sweeps of Algorithm 2 (setup, one GMRES solve); '' for none")
     ap.add_argument("--paper-widths", default="",
                     help="NARROW:WIDE: run the 2D paper tables also with unequal layers of NARROW "
                          "or WIDE lines, wide where the velocity varies along the sweep axis "
@@ -365,6 +368,50 @@ def serving_spec(prec_name, count, fractions, budget_gb):
     return out
 
 
+def sweep_compare(prec_name, sizes, nrhs=16):
+    """The two 2D sweep forms side by side at each grid size (the
+    2d_n1023_random recipe, 8 points per wavelength, nrhs right-hand sides,
+    GMRES(20) to 1e-6): setup (a second factorization of the plan; the maps
+    form computes its boundary maps there) and one GMRES solve (the second
+    one), with the factor bytes of each form."""
+    import torch
+
+    import workloads
+    from paper_1504_04058_amd import asp
+
+    prec = asp.ASP_PREC_FP32 if prec_name == "fp32" else asp.ASP_PREC_FP64
+    rows = []
+    for n in sizes:
+        w = workloads.workload("2d_n1023_random", n=n, nrhs=nrhs)
+        f = torch.from_numpy(w["f"]).cuda()
+        u = torch.empty_like(f)
+        for form, sw in (("maps", asp.ASP_SWEEP2D_MAPS), ("sequential", asp.ASP_SWEEP2D_SEQUENTIAL)):
+            with asp.Plan(2, w["c"], w["omega"], n, w["b"], w["gamma"], C=w["C"], prec=prec,
+                          sweep2d=sw) as plan:
+                plan.factor()
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                plan.factor()
+                torch.cuda.synchronize()
+                b = time.perf_counter()
+                asp.asp_gmres(plan.handle, f, u, nrhs, 1e-6, 20, 200)
+                torch.cuda.synchronize()
+                c0 = time.perf_counter()
+                st, iters, relres = asp.asp_gmres(plan.handle, f, u, nrhs, 1e-6, 20, 200)
+                torch.cuda.synchronize()
+                c = time.perf_counter()
+                info = asp.asp_info(plan.handle)
+            rows.append({"n": n, "form": form, "m": info["m"], "factor_bytes": info["factor_bytes"],
+                         "setup_ms": (b - a) * 1e3, "solve_ms": (c - c0) * 1e3,
+                         "iters_mean": float(iters.mean()), "max_relres": float(relres.max())})
+            print(f"sweep-compare n={n} {form}: setup {rows[-1]['setup_ms']:.1f} ms, solve "
+                  f"{rows[-1]['solve_ms']:.1f} ms", flush=True)
+        del f, u
+        torch.cuda.empty_cache()
+    return {"workload": "2d_n1023_random recipe", "nrhs": nrhs, "layer_precision": prec_name,
+            "rows": rows}
+
+
 def paper_tables(prec_name, sizes, dim=2, widths=None, nd3d=True):
     """The paper's experiments (Tables 1-3 of Section 3.2 in 2D, Tables 4-6 of
     Section 4.2 in 3D) on this path: per field and grid, the factorization
@@ -572,6 +619,8 @@ def main():
         out["paper_tables"] = paper_tables(args.prec, [int(x) for x in args.paper_tables.split(",")],
                                            widths=[int(x) for x in args.paper_widths.split(":")]
                                            if args.paper_widths else None)
+    if args.sweep_compare:
+        out["sweep_compare"] = sweep_compare(args.prec, [int(x) for x in args.sweep_compare.split(",")])
     if args.paper_tables3d:
         out["paper_tables3d"] = paper_tables(args.prec, [int(x) for x in args.paper_tables3d.split(",")],
                                              dim=3, nd3d=not args.paper_blocks3d)
