@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d_n1023_random")
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--prec", choices=["fp32", "fp64", "bf16x3"], default="fp32")
     ap.add_argument("--restart", type=int, default=None)
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -95,6 +95,13 @@ def parse():
                          "or WIDE lines, wide where the velocity varies along the sweep axis "
                          "(workloads.variation_widths); '' for equal widths only")
     return ap.parse_args()
+
+
+def prec_code(name):
+    """The library's precision constant for a --prec name."""
+    from paper_1504_04058_amd import asp
+
+    return {"fp32": asp.ASP_PREC_FP32, "fp64": asp.ASP_PREC_FP64, "bf16x3": asp.ASP_PREC_BF16X3}[name]
 
 
 def host_threads():
@@ -232,8 +239,7 @@ def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=Tr
     w = workloads.workload(name)
     restart = restart or w["restart"]
     tol = tol or w["tol"]
-    prec = {"fp32": asp.ASP_PREC_FP32, "fp64": asp.ASP_PREC_FP64,
-            "bf16x3": asp.ASP_PREC_BF16X3}[prec_name]
+    prec = prec_code(prec_name)
     nrhs = w["f"].shape[0]
     dev = torch.device("cuda:0")
     f = torch.from_numpy(w["f"]).to(dev)
@@ -315,7 +321,7 @@ def serving_run(count, prec_name):
         c, f = workloads.materialize(d)
         reqs.append(serve.Request(d["rid"], d["key"], d["arrival"], d["d"], d["n"], d["omega"],
                                   d["nrhs"], c, f, layer_b=d["b"], pml_eta=d["gamma"]))
-    prec = asp.ASP_PREC_FP32 if prec_name == "fp32" else asp.ASP_PREC_FP64
+    prec = prec_code(prec_name)
     srv = serve.Server(serve.AspBackend(prec=prec, keep_u=False), budget_bytes=64 << 30,
                        max_rhs=64, workers=4)
     res, summ = srv.run(reqs)
@@ -339,7 +345,7 @@ def serving_spec(prec_name, count, fractions, budget_gb):
     import workloads
     from paper_1504_04058_amd import asp, serve
 
-    prec = asp.ASP_PREC_FP32 if prec_name == "fp32" else asp.ASP_PREC_FP64
+    prec = prec_code(prec_name)
     budget = int(budget_gb * (1 << 30))
 
     def one(rate, realtime):
@@ -379,7 +385,7 @@ def sweep_compare(prec_name, sizes, nrhs=16):
     import workloads
     from paper_1504_04058_amd import asp
 
-    prec = asp.ASP_PREC_FP32 if prec_name == "fp32" else asp.ASP_PREC_FP64
+    prec = prec_code(prec_name)
     rows = []
     for n in sizes:
         w = workloads.workload("2d_n1023_random", n=n, nrhs=nrhs)
@@ -431,8 +437,7 @@ def paper_tables(prec_name, sizes, dim=2, widths=None, nd3d=True):
     golden = "paper_iterations.json" if dim == 2 else "paper_iterations_3d.json"
     with open(os.path.join(ROOT, "tests", "golden", golden)) as fh:
         printed = _json.load(fh)
-    prec = {"fp32": asp.ASP_PREC_FP32, "fp64": asp.ASP_PREC_FP64,
-            "bf16x3": asp.ASP_PREC_BF16X3}[prec_name]
+    prec = prec_code(prec_name)
     rows = []
     for n in sizes:
         col = printed["n"].index(n) if n in printed["n"] else None
@@ -584,6 +589,14 @@ def main():
                            keep_u=True)
         out["plain_fp64"] = line_of(args.workload, p64, "fp64")
         out["plain_fp64"]["vs_mixed"] = compare_runs(r, p64)
+        if args.prec != "bf16x3":
+            # the same workload with real-split bf16 products in the layer
+            # solves, boundary maps and sweeps (FP32 factors and accumulation)
+            b16 = run_workload(args.workload, "bf16x3", args.steps, args.warmup, args.restart, args.tol,
+                               keep_u=True)
+            out["mixed_bf16x3"] = line_of(args.workload, b16, "bf16x3")
+            out["mixed_bf16x3"]["vs_fp64"] = compare_runs(b16, p64)
+            del b16
         del p64
     r["u"] = None
     if args.secondary:

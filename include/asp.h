@@ -55,12 +55,14 @@ typedef enum {
     ASP_PREC_FP64 = 0,     /* layer factors and layer solves in complex double */
     ASP_PREC_FP32 = 1,     /* layer factors and layer solves in complex float;
                               GMRES, stencil and all grid vectors stay complex double */
-    ASP_PREC_BF16X3 = 2    /* 3D only: as ASP_PREC_FP32, but the Schur-complement (trailing)
-                              updates of the block inversions are real-split products on
-                              bf16 matrix cores: each FP32 operand x = hi + lo with
+    ASP_PREC_BF16X3 = 2    /* FP32 factors as ASP_PREC_FP32, with matrix products as real-split
+                              products on bf16 matrix cores: each FP32 operand x = hi + lo with
                               hi = bf16(x), lo = bf16(x - hi), and x*y ~ hi*hi + hi*lo + lo*hi
-                              accumulated in FP32 (about 16 significant bits per product);
-                              a 2D plan rejects it with ASP_ERR_ARG */
+                              accumulated in FP32 (about 16 significant bits per product).
+                              3D: the Schur-complement (trailing) updates of the block
+                              inversions; 2D: the layer solves (each block step S_k^-1 times
+                              the step vectors), the boundary maps they produce and the
+                              sweep-map products */
 } asp_prec;
 
 typedef enum { ASP_SUB_M = 0, ASP_SUB_R = 1, ASP_SUB_L = 2 } asp_sub_kind;

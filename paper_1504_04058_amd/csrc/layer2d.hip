@@ -244,8 +244,11 @@ struct SolveArgs {
 
 constexpr int SB = 256;        // threads per solve workgroup: four wavefronts, one tile each
 
-template <typename T, int LR, int INM>
+// SPL (ASP_PREC_BF16X3, T = float): every block product as real-split bf16
+// products with FP32 accumulation (cmac_split), one 16x16x32 step over K <= 32
+template <typename T, int LR, int INM, bool SPL = false>
 __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
+    static_assert(!SPL || std::is_same<T, float>::value, "the split products take FP32 operands");
     static_assert(INM == IN_GRID || INM == IN_BOUNDARY || INM == IN_UNIT, "input mode");
     constexpr int SRB = 1024 / LR;          // right-hand sides per workgroup
     constexpr int NCT = SRB / 16;           // right-hand-side tiles
@@ -310,7 +313,25 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // this wavefront's tile of S^-1 (ring slot fb) times the step vectors tb[buf]
     auto product = [&](int fb, int buf) {
         CTile<T> acc;
-        if constexpr (std::is_same<T, float>::value) {
+        if constexpr (SPL) {
+            // lane l takes k = 8 (l / 16) .. + 7; columns past L are zero in the
+            // factor ring, rows past LR of the step vectors are masked
+            acc.zero();
+            const int lq = l >> 4;
+            float ar[8], ai[8], br[8], bi[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = 8 * lq + j;
+                const cplx<T> av = Fs[fb][c * LR + 16 * rt + li];
+                const cplx<T> bv = tb[buf][min(c, LR - 1)][rloc];
+                const bool in = c < LR;
+                ar[j] = av.x;
+                ai[j] = av.y;
+                br[j] = in ? bv.x : 0.f;
+                bi[j] = in ? bv.y : 0.f;
+            }
+            cmac_split(acc, ar, ai, br, bi);
+        } else if constexpr (std::is_same<T, float>::value) {
             KTile3 k3;
             k3.zero();
             for (int c0 = 0; c0 < LP; c0 += 4) {
@@ -696,7 +717,7 @@ constexpr int SW_W = 8;        // wavefronts per block, splitting the columns of
 // LDS and are added in wavefront order (fixed, so a result does not depend on
 // the other right-hand sides or on scheduling).  The two blocks of a row tile
 // are 64 block ids apart and so share an XCD and its L2 copy of T.
-template <typename T>
+template <typename T, bool SPL = false>
 __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
     __shared__ cplx<T> red[SW_W][2][64][4];
     const int side = blockIdx.z;
@@ -760,22 +781,51 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
             }
         }
     };
+    // SPL: the two batches (32 columns) as the k range of one split product;
+    // slot j < 4 of a lane holds batch 0's column 4 j + lk, slot j >= 4 batch 1's
+    auto multiply_split = [&](const Batch& B0, const Batch& B1) {
+        if constexpr (SPL) {
+#pragma unroll
+            for (int t2 = 0; t2 < 2; ++t2) {
+                float ar[8], ai[8], br[8], bi[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const Batch& B = j < 4 ? B0 : B1;
+                    const int u = j & 3;
+                    const cplx<T> av = csel(B.ok[u], B.av[u], mk<T>(T(0), T(0)));
+                    ar[j] = av.x;
+                    ai[j] = av.y;
+                    br[j] = B.bv[u][t2].x;
+                    bi[j] = B.bv[u][t2].y;
+                }
+                cmac_split(acc[t2], ar, ai, br, bi);
+            }
+        }
+    };
     Batch b0, b1;
     load(b0, cb);
     load(b1, cb + 16);
     // nothing outstanding on entry: the waits in the loop count its own loads
     __builtin_amdgcn_s_waitcnt(0);
     for (int c0 = cb; c0 < cb + per; c0 += 32) {
-        multiply(b0);
-        __builtin_amdgcn_sched_barrier(0);
-        load(b0, c0 + 32);
-        __builtin_amdgcn_sched_barrier(0);
-        multiply(b1);
-        __builtin_amdgcn_sched_barrier(0);
-        load(b1, c0 + 48);
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (SPL) {
+            multiply_split(b0, b1);
+            __builtin_amdgcn_sched_barrier(0);
+            load(b0, c0 + 32);
+            load(b1, c0 + 48);
+            __builtin_amdgcn_sched_barrier(0);
+        } else {
+            multiply(b0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(b0, c0 + 32);
+            __builtin_amdgcn_sched_barrier(0);
+            multiply(b1);
+            __builtin_amdgcn_sched_barrier(0);
+            load(b1, c0 + 48);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && !SPL) {
 #pragma unroll
         for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
@@ -876,7 +926,9 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
 // solves and the transfer-map solves are separate kernels
 template <int LR, int INM>
 static hipError_t launch_solve_lr(const asp_plan* P, const SolveArgs& a, int blocks, hipStream_t st) {
-    if (P->prec != ASP_PREC_FP64)
+    if (P->prec == ASP_PREC_BF16X3)
+        hipLaunchKernelGGL((solve2d_kernel<float, LR, INM, true>), dim3(blocks), dim3(SB), 0, st, a);
+    else if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL((solve2d_kernel<float, LR, INM>), dim3(blocks), dim3(SB), 0, st, a);
     else
         hipLaunchKernelGGL((solve2d_kernel<double, LR, INM>), dim3(blocks), dim3(SB), 0, st, a);
@@ -997,7 +1049,9 @@ hipError_t launch_sweep_step(const asp_plan* P, int t, zd* W, int w_rhs, const i
     a.n = P->n;
     a.N = P->N;
     dim3 grid((P->n + SW_ROWS - 1) / SW_ROWS, ws / SW_RT, 2);
-    if (P->prec != ASP_PREC_FP64)
+    if (P->prec == ASP_PREC_BF16X3)
+        hipLaunchKernelGGL((sweep_step_kernel<float, true>), grid, dim3(64 * SW_W), 0, st, a);
+    else if (P->prec != ASP_PREC_FP64)
         hipLaunchKernelGGL(sweep_step_kernel<float>, grid, dim3(64 * SW_W), 0, st, a);
     else
         hipLaunchKernelGGL(sweep_step_kernel<double>, grid, dim3(64 * SW_W), 0, st, a);

@@ -433,8 +433,6 @@ __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
 // bf16 hi/lo planes in LDS (k contiguous), and every real product is
 // hi*hi + hi*lo + lo*hi on the 16x16x32 bf16 matrix-core instruction with FP32
 // accumulation onto the FP32 tile of A.
-typedef short s16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int LDB = TB + 8;   // padded k stride of a bf16 plane
 
 struct SplitPlanes {          // one 64 x 64 complex tile: [row][k] planes
@@ -451,23 +449,6 @@ __device__ __forceinline__ void split_store(SplitPlanes& S, int i, int k, zf v) 
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
-__device__ __forceinline__ bf16x8 neg8(bf16x8 x) {
-    s16x8 b = __builtin_bit_cast(s16x8, x);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) b[j] = (short)(b[j] ^ (short)0x8000);
-    return __builtin_bit_cast(bf16x8, b);
-}
-
-__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// c += x*y with x = xh + xl, y = yh + yl, dropping xl*yl
-__device__ __forceinline__ f32x4 split_mac(bf16x8 xh, bf16x8 xl, bf16x8 yh, bf16x8 yl, f32x4 c) {
-    c = mfma_bf16(xl, yh, c);
-    c = mfma_bf16(xh, yl, c);
-    return mfma_bf16(xh, yh, c);
-}
 
 __global__ __launch_bounds__(NT) void gj_update_bf16x3_kernel(GjArgs a) {
     __shared__ SplitPlanes sP, sQ;   // P[r][k], Q^T[c][k]

@@ -195,8 +195,6 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     if (!(o.C >= 0.0) || !std::isfinite(o.C)) return fail(ASP_ERR_ARG, "C must be finite and >= 0");
     if (o.prec != ASP_PREC_FP64 && o.prec != ASP_PREC_FP32 && o.prec != ASP_PREC_BF16X3)
         return fail(ASP_ERR_ARG, "unknown precision");
-    if (o.prec == ASP_PREC_BF16X3 && dim != 3)
-        return fail(ASP_ERR_ARG, "the bf16 split precision applies to the 3D factorization only");
     if (dim == 3 && (long long)n * n * n > (1LL << 31)) return fail(ASP_ERR_ARG, "grid too large");
     if (o.fact3d != ASP_FACT3D_ND && o.fact3d != ASP_FACT3D_BLOCKS && o.fact3d != ASP_FACT3D_RECURSIVE)
         return fail(ASP_ERR_ARG, "unknown fact3d");

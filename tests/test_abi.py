@@ -289,20 +289,20 @@ def test_nested_dissection_plan(L, n, b, gamma, aux):
     asp.asp_destroy(plan)
 
 
-def test_bf16_split_precision_is_3d_only(L):
-    with pytest.raises(asp.AspError) as e:
-        asp.asp_setup(2, np.ones(63 * 63), 10.0, 63, 4, 12, prec=asp.ASP_PREC_BF16X3, host_only=True)
-    assert e.value.status == asp.ASP_ERR_ARG and "3D" in str(e.value)
-    plan = asp.asp_setup(3, np.ones(31 ** 3), 10.0, 31, 4, 8, prec=asp.ASP_PREC_BF16X3, host_only=True)
-    try:
-        fp32 = asp.asp_setup(3, np.ones(31 ** 3), 10.0, 31, 4, 8, prec=asp.ASP_PREC_FP32,
-                             host_only=True)
-        try:   # FP32 storage
-            assert asp.asp_info(plan)["factor_bytes"] == asp.asp_info(fp32)["factor_bytes"]
+def test_bf16_split_precision_storage(L):
+    """ASP_PREC_BF16X3 keeps FP32 factors (the split happens in the products),
+    in 2D and 3D alike."""
+    for dim, n, gamma in ((2, 63, 12), (3, 31, 8)):
+        c = np.ones(n ** dim)
+        plan = asp.asp_setup(dim, c, 10.0, n, 4, gamma, prec=asp.ASP_PREC_BF16X3, host_only=True)
+        try:
+            fp32 = asp.asp_setup(dim, c, 10.0, n, 4, gamma, prec=asp.ASP_PREC_FP32, host_only=True)
+            try:
+                assert asp.asp_info(plan)["factor_bytes"] == asp.asp_info(fp32)["factor_bytes"]
+            finally:
+                asp.asp_destroy(fp32)
         finally:
-            asp.asp_destroy(fp32)
-    finally:
-        asp.asp_destroy(plan)
+            asp.asp_destroy(plan)
 
 
 def test_sequential_sweep_plan(L):

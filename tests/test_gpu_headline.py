@@ -188,10 +188,11 @@ def _gate(name, n, nrhs, prec, label, nd=True):
         assert e10 <= 1e-6
 
 
+@pytest.mark.parametrize("prec", [asp.ASP_PREC_FP32, asp.ASP_PREC_BF16X3], ids=["fp32", "bf16x3"])
 @pytest.mark.parametrize("name,n,nrhs", [("2d_n511_lens", 127, 4), ("2d_n1023_random", 255, 4)])
-def test_gate_2d_fp32(name, n, nrhs):
-    print(f"mixed-precision gate 2D {name} n={n} fp32", flush=True)
-    _gate(name, n, nrhs, asp.ASP_PREC_FP32, f"2D {name}@{n} fp32")
+def test_gate_2d(name, n, nrhs, prec):
+    print(f"mixed-precision gate 2D {name} n={n} prec={prec}", flush=True)
+    _gate(name, n, nrhs, prec, f"2D {name}@{n} prec={prec}")
 
 
 @pytest.mark.parametrize("prec", [asp.ASP_PREC_FP32, asp.ASP_PREC_BF16X3], ids=["fp32", "bf16x3"])
