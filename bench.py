@@ -308,9 +308,10 @@ def run_workload(name, prec_name, steps, warmup, restart=None, tol=None, nd3d=Tr
 
 
 def serving_run(count, prec_name):
-    """Served solves: a seeded Poisson stream of 2D (n = 127, 255, 511) and 3D
-    (n = 31) requests, 1-8 right-hand sides each, half of them repeating an
-    earlier problem, through the serving loop on a 64 GB device budget."""
+    """Served solves: a seeded stream of 2D (n = 127, 255, 511) and 3D (n = 31)
+    requests, 1-8 right-hand sides each, half of them repeating an earlier
+    problem, through the serving loop on a 64 GB device budget, all requests
+    queued at the start (the loop's throughput, not the arrival rate)."""
     import workloads
     from paper_1504_04058_amd import asp, serve
 
@@ -322,10 +323,11 @@ def serving_run(count, prec_name):
         reqs.append(serve.Request(d["rid"], d["key"], d["arrival"], d["d"], d["n"], d["omega"],
                                   d["nrhs"], c, f, layer_b=d["b"], pml_eta=d["gamma"]))
     prec = prec_code(prec_name)
-    srv = serve.Server(serve.AspBackend(prec=prec, keep_u=False), budget_bytes=64 << 30,
-                       max_rhs=64, workers=4)
+    backend = serve.AspBackend(prec=prec, keep_u=False, cache_bytes=16 << 30)
+    srv = serve.Server(backend, budget_bytes=64 << 30, max_rhs=64, workers=4, realtime=False)
     res, summ = srv.run(reqs)
-    summ["stream"] = {"requests": count, "rate_per_s": 40.0, "seed": 5,
+    backend.close()
+    summ["stream"] = {"requests": count, "arrivals": "all at the start", "seed": 5,
                       "sizes": [f"{d}d n={n}" for d, n in sizes], "rhs_per_request": "1-8",
                       "repeat": 0.5}
     summ["batches"] = len(srv.batches)
@@ -334,7 +336,7 @@ def serving_run(count, prec_name):
     return summ
 
 
-def serving_spec(prec_name, count, fractions, budget_gb):
+def serving_spec(prec_name, count, fractions, budget_gb, cache_gb=48.0):
     """The full serving mix: a seeded Poisson stream of `count` requests (2D
     n = 127, 255, 511, 1023 and 3D n = 31, 63 with omega = 2 pi n / 8; constant,
     lens and random velocities; 1-32 right-hand sides; each request repeats an
@@ -351,7 +353,7 @@ def serving_spec(prec_name, count, fractions, budget_gb):
     def one(rate, realtime):
         descs = workloads.request_stream(count=count, rate=rate, seed=5, max_rhs=32)
         reqs = [serve.Request.from_description(d) for d in descs]
-        backend = serve.AspBackend(prec=prec, keep_u=False)
+        backend = serve.AspBackend(prec=prec, keep_u=False, cache_bytes=int(cache_gb * (1 << 30)))
         srv = serve.Server(backend, budget_bytes=budget, max_rhs=64, workers=4, realtime=realtime,
                            progress_every=max(1, count // 10))
         res, summ = srv.run(reqs)
@@ -366,6 +368,7 @@ def serving_spec(prec_name, count, fractions, budget_gb):
     sat_rate = sat["completed"] / sat["wall_s"]
     out = {"stream": {"requests": count, "seed": 5, "sizes": "2D n = 127, 255, 511, 1023; 3D n = 31, 63",
                       "rhs_per_request": "1-32", "repeat": 0.5, "budget_gb": budget_gb,
+                      "reuse_cache_gb": cache_gb,
                       "layer_precision": prec_name},
            "saturation": dict(sat, request_rate_per_s=sat_rate), "loads": []}
     for f in fractions:

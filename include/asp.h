@@ -293,6 +293,22 @@ asp_status asp_timing_read(asp_plan* plan, int cls, int* launches, double* ms, d
 asp_status asp_workspace_estimate(const asp_plan* plan, int nrhs, int restart, size_t* bytes);
 asp_status asp_release_workspace(asp_plan* plan);
 
+/* asp_set_cache_limit -- device memory the library may keep for reuse, per
+ * device (serving loops that create, trim and destroy plans; no section of
+ * the paper).  Device blocks that plans give back (asp_release_workspace,
+ * asp_destroy, the factorization's work buffers, workspaces replaced by larger
+ * ones) are kept, up to `bytes` per device, and handed out again to later
+ * requests of at least their size and at most an eighth (or 2 MiB) more,
+ * instead of going back to the driver: a driver free of a large block takes
+ * milliseconds per gigabyte and waits for the whole device.  0 (the default)
+ * keeps nothing.  Lowering the limit returns the excess at once; an
+ * allocation that fails returns the whole cache and tries again.  Returns the
+ * previous limit.  Thread-safe.  Kept bytes are device memory that other
+ * allocators in the process cannot use.
+ * asp_cached_bytes -- bytes kept, over all devices. */
+size_t asp_set_cache_limit(size_t bytes);
+size_t asp_cached_bytes(void);
+
 /* asp_info -- sizes and memory of the plan.  asp_set_stream -- change the stream
  * used by later calls.  asp_destroy -- free everything (NULL is ignored).
  * asp_last_error -- description of the last failure of this plan (never NULL). */

@@ -86,6 +86,8 @@ def lib():
                                     ctypes.POINTER(ctypes.c_double)]),
             "asp_workspace_estimate": (I, [P, I, I, ctypes.POINTER(ctypes.c_size_t)]),
             "asp_release_workspace": (I, [P]),
+            "asp_set_cache_limit": (ctypes.c_size_t, [ctypes.c_size_t]),
+            "asp_cached_bytes": (ctypes.c_size_t, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -215,6 +217,16 @@ def asp_workspace_estimate(plan, nrhs, restart):
 
 def asp_release_workspace(plan):
     _check(plan, lib().asp_release_workspace(plan))
+
+
+def asp_set_cache_limit(nbytes):
+    """Device bytes the library may keep for reuse per device; returns the
+    previous limit."""
+    return int(lib().asp_set_cache_limit(int(nbytes)))
+
+
+def asp_cached_bytes():
+    return int(lib().asp_cached_bytes())
 
 
 def asp_timing_enable(plan, enable):

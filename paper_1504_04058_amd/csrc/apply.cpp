@@ -13,7 +13,7 @@ size_t elem_bytes(const asp_plan* P) { return P->prec != ASP_PREC_FP64 ? sizeof(
 
 template <typename T>
 asp_status dev_alloc(asp_plan* P, T** p, size_t count) {
-    if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+    if (devmem_alloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return plan_fail(P, ASP_ERR_OOM, "device allocation failed");
@@ -22,7 +22,7 @@ asp_status dev_alloc(asp_plan* P, T** p, size_t count) {
 }
 
 void dev_free(void* p) {
-    if (p) (void)hipFree(p);
+    devmem_free(p);
 }
 
 // workgroups of a solve launch per problem of LR rows over `nact` right-hand sides

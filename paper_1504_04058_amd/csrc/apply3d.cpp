@@ -16,7 +16,7 @@ size_t esz(const asp_plan* P) { return P->prec != ASP_PREC_FP64 ? sizeof(zf) : s
 
 template <typename T>
 asp_status alloc3(asp_plan* P, T** p, size_t bytes) {
-    if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) {
+    if (devmem_alloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return plan_fail(P, ASP_ERR_OOM, "device allocation failed");
@@ -25,7 +25,7 @@ asp_status alloc3(asp_plan* P, T** p, size_t bytes) {
 }
 
 void free3(void* p) {
-    if (p) (void)hipFree(p);
+    devmem_free(p);
 }
 
 int chunks_of(int nrhs) { return (nrhs + RW3 - 1) / RW3; }

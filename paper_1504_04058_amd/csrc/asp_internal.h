@@ -356,9 +356,20 @@ struct SolveLaunch {
     zd* out_L = nullptr;
 };
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st);
+// device memory of the library (devmem.cpp): blocks may be cached and handed
+// to another plan, so a block is freed only once no work is pending on it
+// (after a synchronization of the owning plan's stream)
+hipError_t devmem_alloc(void** p, size_t bytes);
+void devmem_free(void* p);
+
 // right-hand sides handled by one solve workgroup for problems of LR rows, and
 // the scratch entries of one workgroup (the same for every LR)
 int solve_rhs_per_block(int LR);
+// the most sweep lines a 2D auxiliary problem may have with blocks of LR rows
+// (LR = 16, 32, 64) in element type T: the solve kernels keep two blocks in
+// LDS, which at LR = 64 holds 64 lines of FP32 and 48 of FP64
+template <typename T>
+constexpr int max_lines_2d(int LR) { return LR <= 32 ? 32 : (sizeof(T) == 4 ? 64 : 48); }
 long long solve_scratch_per_block(const asp_plan* P);
 // the W rows that start the two sweeps (from u~_{1,1} and u~_{m,m} in U)
 hipError_t launch_sweep_seed(const asp_plan* P, zd* W, long long outR, long long outL,

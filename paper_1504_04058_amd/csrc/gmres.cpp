@@ -27,7 +27,7 @@ constexpr int MAX_RESTART = 64;
 
 template <typename T>
 asp_status dev_alloc(asp_plan* P, T** p, size_t count) {
-    if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+    if (devmem_alloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return plan_fail(P, ASP_ERR_OOM, "device allocation of GMRES workspace failed");
@@ -40,7 +40,7 @@ asp_status ensure_krylov_ws(asp_plan* P, int nrhs, int restart) {
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     void* old[] = {P->d_V, P->d_Z, P->d_b, P->d_red, P->d_small, P->d_act};
     for (void* b : old)
-        if (b) (void)hipFree(b);
+        devmem_free(b);
     P->d_V = P->d_Z = P->d_b = P->d_red = P->d_small = nullptr;
     P->d_act = nullptr;
     P->kr_rhs = P->kr_restart = 0;

@@ -21,7 +21,7 @@
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int MAXL = 32;
+constexpr int MAXL = 64;   // the most sweep lines of a 2D auxiliary problem
 static_assert(WAVE * 16 <= SINK_ELEMS, "sixteen discard entries per lane");
 
 // raw buffer stores: dword 3 of the resource (32-bit data format) and an
@@ -50,7 +50,8 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
 // ----------------------------------------------------------------------------
 // factorization: one 256-thread workgroup per auxiliary problem.  With LR
 // columns, thread (j, g) holds rows g RPL .. g RPL + RPL - 1 of column j of the
-// current block in registers (LR = 32: 8 row groups of 4; LR = 16: 16 of 1);
+// current block in registers (LR = 64: 4 row groups of 16; LR = 32: 8 of 4;
+// LR = 16: 16 of 1);
 // S_k is formed from S_{k-1}^-1 in place and inverted by Gauss-Jordan
 // elimination without pivoting (at a few points per wavelength the blocks are
 // close to diagonally dominant; a zero or non-finite pivot is reported as a
@@ -60,13 +61,13 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
 // ----------------------------------------------------------------------------
 constexpr int FB = 256;   // threads per factor workgroup
 
-template <typename TS, int LR>
+template <typename TS, int LR, int ML>
 __device__ __forceinline__ void factor2d_body(const SubDesc& d, AxisTables ax,
                                               const zd* __restrict__ subtab,
                                               const double* __restrict__ ksq, int n,
                                               cplx<TS>* __restrict__ fac, int* __restrict__ flag,
-                                              zd (&rowbuf)[2][MAXL], zd (&colbuf)[2][MAXL],
-                                              zd (&srow)[MAXL]) {
+                                              zd (&rowbuf)[2][ML], zd (&colbuf)[2][ML],
+                                              zd (&srow)[ML]) {
     constexpr int G = FB / LR, RPL = LR / G;
     const int L = d.L;
     const int t = threadIdx.x;
@@ -174,21 +175,26 @@ __device__ __forceinline__ void factor2d_body(const SubDesc& d, AxisTables ax,
     if (bad) *flag = 1;
 }
 
-template <typename TS>
+// ML: the largest LR of the launch (32, or 64 when a problem has more than 32
+// lines: that body's registers would halve the occupancy of the others)
+template <typename TS, int ML>
 __global__ __launch_bounds__(FB) void factor2d_kernel(const SubDesc* __restrict__ desc,
                                                      AxisTables ax,
                                                      const zd* __restrict__ subtab,
                                                      const double* __restrict__ ksq, int n,
                                                      cplx<TS>* __restrict__ fac,
                                                      int* __restrict__ flag) {
-    __shared__ zd rowbuf[2][MAXL];
-    __shared__ zd colbuf[2][MAXL];
-    __shared__ zd srow[MAXL];
+    static_assert(ML == 32 || ML == MAXL, "row counts");
+    __shared__ zd rowbuf[2][ML];
+    __shared__ zd colbuf[2][ML];
+    __shared__ zd srow[ML];
     const SubDesc d = desc[blockIdx.x];
     if (d.LR == 16)
-        factor2d_body<TS, 16>(d, ax, subtab, ksq, n, fac, flag, rowbuf, colbuf, srow);
+        factor2d_body<TS, 16, ML>(d, ax, subtab, ksq, n, fac, flag, rowbuf, colbuf, srow);
+    else if (ML == 32 || d.LR == 32)
+        factor2d_body<TS, 32, ML>(d, ax, subtab, ksq, n, fac, flag, rowbuf, colbuf, srow);
     else
-        factor2d_body<TS, 32>(d, ax, subtab, ksq, n, fac, flag, rowbuf, colbuf, srow);
+        factor2d_body<TS, ML, ML>(d, ax, subtab, ksq, n, fac, flag, rowbuf, colbuf, srow);
 }
 
 // ----------------------------------------------------------------------------
@@ -245,7 +251,7 @@ struct SolveArgs {
 constexpr int SB = 256;        // threads per solve workgroup: four wavefronts, one tile each
 
 // SPL (ASP_PREC_BF16X3, T = float): every block product as real-split bf16
-// products with FP32 accumulation (cmac_split), one 16x16x32 step over K <= 32
+// products with FP32 accumulation (cmac_split), 16x16x32 steps over the block
 template <typename T, int LR, int INM, bool SPL = false>
 __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     static_assert(!SPL || std::is_same<T, float>::value, "the split products take FP32 operands");
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     constexpr int NCT = SRB / 16;           // right-hand-side tiles
     static_assert((LR / 16) * NCT == 4, "four 16 x 16 tiles, one per wavefront");
     static_assert(SB * 4 <= SINK_ELEMS, "four discard entries per thread");
-    constexpr int FMAX = 32 * LR;           // largest block (L <= 32)
+    constexpr int FMAX = max_lines_2d<T>(LR) * LR;   // largest block
     constexpr int FPT = FMAX / SB;
     constexpr int TBS = SRB + 1;            // padded row stride of the step vectors
     __shared__ cplx<T> Fs[2][FMAX];
@@ -314,23 +320,27 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     auto product = [&](int fb, int buf) {
         CTile<T> acc;
         if constexpr (SPL) {
-            // lane l takes k = 8 (l / 16) .. + 7; columns past L are zero in the
-            // factor ring, rows past LR of the step vectors are masked
+            // lane l takes k = kh + 8 (l / 16) .. + 7 of each 32-wide k range;
+            // columns past L are zero in the factor ring, rows past LR of the
+            // step vectors are masked
             acc.zero();
             const int lq = l >> 4;
-            float ar[8], ai[8], br[8], bi[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int c = 8 * lq + j;
-                const cplx<T> av = Fs[fb][c * LR + 16 * rt + li];
-                const cplx<T> bv = tb[buf][min(c, LR - 1)][rloc];
-                const bool in = c < LR;
-                ar[j] = av.x;
-                ai[j] = av.y;
-                br[j] = in ? bv.x : 0.f;
-                bi[j] = in ? bv.y : 0.f;
+            for (int kh = 0; kh < FMAX / LR; kh += 32) {
+                float ar[8], ai[8], br[8], bi[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int c = kh + 8 * lq + j;
+                    const cplx<T> av = Fs[fb][c * LR + 16 * rt + li];
+                    const cplx<T> bv = tb[buf][min(c, LR - 1)][rloc];
+                    const bool in = c < LR;
+                    ar[j] = av.x;
+                    ai[j] = av.y;
+                    br[j] = in ? bv.x : 0.f;
+                    bi[j] = in ? bv.y : 0.f;
+                }
+                cmac_split(acc, ar, ai, br, bi);
             }
-            cmac_split(acc, ar, ai, br, bi);
         } else if constexpr (std::is_same<T, float>::value) {
             KTile3 k3;
             k3.zero();
@@ -911,14 +921,16 @@ hipError_t launch_sweep_hand(const asp_plan* P, const zd* z, const zd* stage, zd
 hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
     const int nsub = (int)P->subs.size();
     AxisTables ax{P->d_axis, P->d_axis + (P->n + 1), P->d_axis + (2 * P->n + 1)};
-    if (P->prec != ASP_PREC_FP64)
-        hipLaunchKernelGGL(factor2d_kernel<float>, dim3(nsub), dim3(FB), 0, st, P->d_desc, ax,
-                           P->d_subtab, P->d_ksq, P->n, reinterpret_cast<zf*>(P->d_fac),
-                           P->d_flag);
-    else
-        hipLaunchKernelGGL(factor2d_kernel<double>, dim3(nsub), dim3(FB), 0, st, P->d_desc,
-                           ax, P->d_subtab, P->d_ksq, P->n, reinterpret_cast<zd*>(P->d_fac),
-                           P->d_flag);
+    const bool wide = std::max(P->LR_M, P->LR_RL) > 32;
+    if (P->prec != ASP_PREC_FP64) {
+        auto k = wide ? factor2d_kernel<float, MAXL> : factor2d_kernel<float, 32>;
+        hipLaunchKernelGGL(k, dim3(nsub), dim3(FB), 0, st, P->d_desc, ax, P->d_subtab, P->d_ksq,
+                           P->n, reinterpret_cast<zf*>(P->d_fac), P->d_flag);
+    } else {
+        auto k = wide ? factor2d_kernel<double, MAXL> : factor2d_kernel<double, 32>;
+        hipLaunchKernelGGL(k, dim3(nsub), dim3(FB), 0, st, P->d_desc, ax, P->d_subtab, P->d_ksq,
+                           P->n, reinterpret_cast<zd*>(P->d_fac), P->d_flag);
+    }
     return hipGetLastError();
 }
 
@@ -988,7 +1000,8 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     if (B > P->y_waves) return hipErrorInvalidValue;   // scratch too small
     const int blocks = (int)(((B + 7) / 8) * 8);
     if (LR == 16) return launch_solve_mode<16>(P, a, blocks, st);
-    return launch_solve_mode<32>(P, a, blocks, st);
+    if (LR == 32) return launch_solve_mode<32>(P, a, blocks, st);
+    return launch_solve_mode<64>(P, a, blocks, st);
 }
 
 static int sweep_slots(int nact) { return (nact + SW_RT - 1) / SW_RT * SW_RT; }

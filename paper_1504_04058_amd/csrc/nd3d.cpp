@@ -88,7 +88,7 @@ int build_tree(std::vector<TNode>& T, int n, int x0, int x1, int y0, int y1, int
 
 template <typename T>
 asp_status nd_alloc(asp_plan* P, T** p, size_t bytes) {
-    if (hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(bytes, 16)) != hipSuccess) {
+    if (devmem_alloc(reinterpret_cast<void**>(p), std::max<size_t>(bytes, 16)) != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return plan_fail(P, ASP_ERR_OOM, "device allocation failed");
@@ -329,7 +329,7 @@ asp_status nd_factor(asp_plan* P) {
             (s = nd_alloc(P, &rb0, (size_t)P->nd_rbuf * e)) != ASP_OK ||
             (s = nd_alloc(P, &db0, (size_t)P->nd_dbuf * NDT * NDT * e)) != ASP_OK) {
             for (void* b : {(void*)lb0, (void*)lb1, (void*)rb0})
-                if (b) (void)hipFree(b);
+                devmem_free(b);
             return s;
         }
         P->d_nd_lb[0] = lb0;
@@ -411,7 +411,7 @@ asp_status nd_ensure_ws(asp_plan* P, int nrhs) {
     ASP_HIP(P, hipStreamSynchronize(P->stream));
     void* old[] = {P->d_U, P->d_stage, P->d_w3, P->d_nd_v, P->d_nd_x};
     for (void* b : old)
-        if (b) (void)hipFree(b);
+        devmem_free(b);
     P->d_U = P->d_stage = P->d_w3 = nullptr;
     P->d_nd_v = P->d_nd_x = nullptr;
     P->ws_rhs = 0;

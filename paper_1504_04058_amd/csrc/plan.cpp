@@ -53,7 +53,7 @@ void fill_tables(int lo, int hi, double phi, double psi, int g_lo, int g_hi, con
 
 template <typename T>
 asp_status upload(asp_plan* P, T** dst, const T* src, size_t count) {
-    if (hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T)) != hipSuccess)
+    if (devmem_alloc(reinterpret_cast<void**>(dst), count * sizeof(T)) != hipSuccess)
         return plan_fail(P, ASP_ERR_OOM, "hipMalloc of a plan table failed");
     ASP_HIP(P, hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, P->stream));
     return ASP_OK;
@@ -136,7 +136,7 @@ static void build_subproblems(asp_plan* P) {
     }
 }
 
-static int rows_per_wave(int L) { return L <= 16 ? 16 : 32; }
+static int rows_per_wave(int L) { return L <= 16 ? 16 : L <= 32 ? 32 : 64; }
 
 extern "C" void asp_default_opts(asp_opts* o) {
     if (!o) return;
@@ -241,9 +241,12 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
         else maxL_RL = std::max(maxL_RL, d.L);
     }
     P->max_L = std::max(maxL_M, maxL_RL);
-    if (dim == 2 && P->max_L > 32) {
-        return fail(ASP_ERR_ARG, "2D auxiliary problems are limited to 32 sweep lines (widest layer + 2(pml_eta-1) <= 32)");
-    }
+    if (dim == 2 && P->prec == ASP_PREC_FP64 && P->max_L > max_lines_2d<double>(64))
+        return fail(ASP_ERR_ARG, "2D auxiliary problems are limited to 48 sweep lines in FP64 "
+                                 "(widest layer + 2(pml_eta-1) <= 48)");
+    if (dim == 2 && P->max_L > max_lines_2d<float>(64))
+        return fail(ASP_ERR_ARG, "2D auxiliary problems are limited to 64 sweep lines "
+                                 "(widest layer + 2(pml_eta-1) <= 64)");
     P->LR_M = rows_per_wave(maxL_M);
     P->LR_RL = rows_per_wave(maxL_RL > 0 ? maxL_RL : 1);
     long long fac_off = 0, tab_off = 0, tr_off = 0, vec_off = 0;
@@ -358,9 +361,9 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
     }
     if (P->nd && (st = nd_upload(P)) != ASP_OK) return fail(st, P->err.c_str());
     if (P->rec && (st = rec_upload(P)) != ASP_OK) return fail(st, P->err.c_str());
-    if (hipMalloc(reinterpret_cast<void**>(&P->d_flag), sizeof(int)) != hipSuccess)
+    if (devmem_alloc(reinterpret_cast<void**>(&P->d_flag), sizeof(int)) != hipSuccess)
         return fail(ASP_ERR_OOM, "hipMalloc failed");
-    if (hipMalloc(reinterpret_cast<void**>(&P->d_sink), SINK_ELEMS * sizeof(zd)) != hipSuccess)
+    if (devmem_alloc(reinterpret_cast<void**>(&P->d_sink), SINK_ELEMS * sizeof(zd)) != hipSuccess)
         return fail(ASP_ERR_OOM, "hipMalloc failed");
     // the host vectors above are released on return: finish the copies first
     if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(ASP_ERR_DEVICE, "upload failed");
@@ -383,7 +386,7 @@ extern "C" void asp_destroy(asp_plan* P) {
                     P->d_rec_g, P->d_rec_y};
     (void)hipStreamSynchronize(P->stream);
     for (void* b : bufs)
-        if (b) (void)hipFree(b);
+        devmem_free(b);
     for (hipEvent_t e : P->tpool) (void)hipEventDestroy(e);
     delete P;
 }

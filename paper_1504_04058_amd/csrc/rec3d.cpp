@@ -26,7 +26,7 @@ size_t esz(const asp_plan* P) { return P->prec != ASP_PREC_FP64 ? sizeof(zf) : s
 
 template <typename T>
 asp_status ralloc(asp_plan* P, T** p, size_t bytes) {
-    if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) {
+    if (devmem_alloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return plan_fail(P, ASP_ERR_OOM, "device allocation failed");
@@ -35,7 +35,7 @@ asp_status ralloc(asp_plan* P, T** p, size_t bytes) {
 }
 
 void rfree(void* p) {
-    if (p) (void)hipFree(p);
+    devmem_free(p);
 }
 
 int nsub_of(const asp_plan* P) { return (int)P->subs.size(); }

@@ -114,7 +114,7 @@ class Backend:
 class AspBackend(Backend):
     """The HIP library: one plan per key, each on its own device stream."""
 
-    def __init__(self, prec=1, tol=1e-6, restart=20, maxit=400, keep_u=True):
+    def __init__(self, prec=1, tol=1e-6, restart=20, maxit=400, keep_u=True, cache_bytes=None):
         import torch
 
         from . import asp
@@ -122,6 +122,9 @@ class AspBackend(Backend):
         self.asp, self.torch = asp, torch
         self.prec, self.tol, self.restart, self.maxit = prec, tol, restart, maxit
         self.keep_u = keep_u
+        # device memory the library keeps for reuse across plans (None: leave
+        # the library's setting); given back by close()
+        self._cache_prev = None if cache_bytes is None else asp.asp_set_cache_limit(cache_bytes)
         self._hosts = {}      # shape -> host-only plan (sizes only, no device state)
         self._ws = {}         # (shape, nrhs) -> workspace bytes
         self._lock = threading.Lock()
@@ -168,6 +171,9 @@ class AspBackend(Backend):
             for h, _ in self._hosts.values():
                 self.asp.asp_destroy(h)
             self._hosts.clear()
+            if self._cache_prev is not None:
+                self.asp.asp_set_cache_limit(self._cache_prev)
+                self._cache_prev = None
 
     def solve(self, handle, f):
         torch = self.torch

@@ -145,9 +145,9 @@ def test_arbitrary_layer_widths_match_oracle(dim, n, gamma, w):
 
 
 @pytest.mark.parametrize("w,frag", [([3, 7, 1, 5, 6, 7], "sum"), ([3, 0, 28], ">= 1"),
-                                    ([31, -1], ">= 1"), ([30, 3], "32 sweep lines")])
+                                    ([31, -1], ">= 1"), ([60, 3], "sweep lines")])
 def test_bad_layer_widths_rejected(L, w, frag):
-    n, gamma = 40 if frag != "32 sweep lines" else 43, 6
+    n, gamma = 40 if frag != "sweep lines" else 73, 6
     with pytest.raises(asp.AspError) as ei:
         asp.asp_setup(2, np.ones(n * n), 10.0, n, w, gamma, host_only=True)
     assert ei.value.status == asp.ASP_ERR_ARG and frag in str(ei.value)
@@ -158,13 +158,49 @@ def test_bad_layer_widths_rejected(L, w, frag):
     ((2, 20, 4, 12), "n too small"),
     ((2, 63, 0, 12), "layer_b"),
     ((2, 63, 4, 1), "pml_eta"),
-    ((2, 63, 40, 12), "32 sweep lines"),
+    ((2, 127, 50, 12), "sweep lines"),
 ])
 def test_bad_arguments_rejected(L, args, frag):
     dim, n, b, gamma = args
     with pytest.raises(asp.AspError) as ei:
         asp.asp_setup(dim, np.ones(max(n, 1) ** min(dim, 3)), 10.0, n, b, gamma, host_only=True)
     assert ei.value.status == asp.ASP_ERR_ARG and frag in str(ei.value)
+
+
+def test_wide_2d_layers(L):
+    """2D auxiliary problems of 33 to 64 lines take blocks of 64 rows; FP64
+    plans stop at 48 lines, FP32 and bf16-split plans at 64."""
+    gamma = 12
+    for w, ok64, ok32 in (((26, 4, 20, 8, 26), True, True), ((27, 4, 20), False, True),
+                          ((42, 4, 30), False, True), ((43, 4), False, False)):
+        n = sum(w) + 2 * (gamma - 1)
+        for prec, ok in ((asp.ASP_PREC_FP64, ok64), (asp.ASP_PREC_FP32, ok32),
+                         (asp.ASP_PREC_BF16X3, ok32)):
+            if not ok:
+                with pytest.raises(asp.AspError) as ei:
+                    asp.asp_setup(2, np.ones(n * n), 10.0, n, list(w), gamma, prec=prec, host_only=True)
+                assert ei.value.status == asp.ASP_ERR_ARG and "sweep lines" in str(ei.value)
+                continue
+            plan = asp.asp_setup(2, np.ones(n * n), 10.0, n, list(w), gamma, prec=prec, host_only=True)
+            try:
+                info = asp.asp_info(plan)
+                assert info["max_lines"] == max(w) + 2 * (gamma - 1)
+                lay = asp.asp_layers(plan)
+                # factor: n blocks of L x 64 per problem (every problem of a kind
+                # shares the row count of its widest member), plus the maps
+                ref = partition.subproblems(n, list(w), gamma)
+                m = len(w)
+                want = 0
+                for kind in ("M", "R", "L"):
+                    LR = max(16 if s.L <= 16 else 32 if s.L <= 32 else 64
+                             for s in (ref["M"] if kind == "M" else ref["R"] + ref["L"]))
+                    for s in ref[kind]:
+                        want += n * s.L * LR + (-(-n // 16) * 16 * n if kind != "M" and 1 < s.p < m else 0)
+                esz = 16 if prec == asp.ASP_PREC_FP64 else 8
+                assert info["factor_bytes"] == want * esz
+                assert lay is not None
+            finally:
+                asp.asp_destroy(plan)
 
 
 def test_bad_velocity_and_omega(L):

@@ -144,3 +144,48 @@ def test_unequal_widths_with_thin_auxiliary_pml(d, n, gamma, aux, w):
         z = host(plan.apply(dev(r)))
     for k in range(2):
         assert rel(z[k], M.apply(r[k])) < 1e-11
+
+
+# 2D layers wider than 32 - 2 (gamma - 1) lines at gamma = 12: auxiliary
+# problems of 33 to 64 lines run on blocks of 64 rows (FP64 up to 48 lines).
+# Twenty right-hand sides: two workgroups of 16 per problem, the second ragged.
+# Bounds about ten times the measured errors (FP32 1.4e-6 for operators and
+# apply; bf16 split 1.7e-5 and 2.1e-5).
+WIDE = [(asp.ASP_PREC_FP64, 1e-11, 1e-11, (26, 4, 20, 8, 26)),
+        (asp.ASP_PREC_FP32, 1.5e-5, 1.5e-5, (40, 4, 30, 8, 42)),
+        (asp.ASP_PREC_BF16X3, 2e-4, 2e-4, (40, 4, 30, 8, 42))]
+
+
+@pytest.mark.parametrize("prec,tol_op,tol_apply,w", WIDE, ids=["fp64", "fp32", "bf16x3"])
+def test_wide_layers_2d(prec, tol_op, tol_apply, w):
+    gamma = 12
+    n = sum(w) + 2 * (gamma - 1)
+    print(f"wide layers 2D n={n} gamma={gamma} w={w} prec={prec}", flush=True)
+    P = _problem(2, n, gamma, w)
+    X = partition.layers(n, list(w), gamma)
+    subs = partition.subproblems(n, list(w), gamma)
+    m = len(X)
+    kinds = {"M": asp.ASP_SUB_M, "R": asp.ASP_SUB_R, "L": asp.ASP_SUB_L}
+    rng = np.random.default_rng(17)
+    M = Preconditioner(P)
+    r = rng.standard_normal((20, P.N)) + 1j * rng.standard_normal((20, P.N))
+    with _plan(P, prec) as plan:
+        plan.factor()
+        for kind, ps in {"M": range(1, m + 1), "R": range(2, m + 1), "L": range(1, m)}.items():
+            for p in ps:
+                sub = [s for s in subs[kind] if s.p == p][0]
+                ref = Subproblem(P, sub, X[p - 1])
+                Np = P.S * (X[p - 1][1] - X[p - 1][0] + 1)
+                k_in = Np if kind == "M" else P.S
+                data = rng.standard_normal((2, k_in)) + 1j * rng.standard_normal((2, k_in))
+                out = host(plan.subsolve(kinds[kind], p, dev(data), Np)).reshape(2, Np)
+                for q in range(2):
+                    e = rel(out[q], ref.G(data[q]))
+                    print(f"wide G~{kind}_{p} (L={sub.L}) prec={prec}: rel err {e:.2e}", flush=True)
+                    assert e < tol_op, (kind, p)
+        z = host(plan.apply(dev(r)))
+    worst = 0.0
+    for k in range(20):
+        worst = max(worst, rel(z[k], M.apply(r[k])))
+    print(f"wide apply prec={prec}: max rel err {worst:.2e} over 20 right-hand sides", flush=True)
+    assert worst < tol_apply

@@ -113,3 +113,35 @@ def test_served_equals_alone_with_3d_keys():
         u1, it1, _ = _alone(d, asp.ASP_PREC_FP32)
         assert np.array_equal(it1, r.iters), d["rid"]
         assert np.array_equal(u1, r.u), d["rid"]
+
+
+def test_served_equals_alone_with_reused_memory():
+    """The library's device-memory reuse (asp_set_cache_limit) under a budget
+    that forces evictions, so that factors, work buffers and workspaces of one
+    key land in blocks another key gave back: every request still agrees
+    bitwise with its solve alone in a fresh plan; the kept bytes never exceed
+    the limit and go back to the driver when the limit returns to 0."""
+    descs = workloads.request_stream(count=20, rate=400.0, seed=17,
+                                     sizes=((2, 47), (2, 63), (3, 19)), max_rhs=5)
+    reqs = [serve.Request.from_description(d) for d in descs]
+    limit = 1 << 30
+    backend = serve.AspBackend(prec=asp.ASP_PREC_FP32, tol=1e-6, restart=20, maxit=400,
+                               cache_bytes=limit)
+    try:
+        big = max(reqs, key=lambda r: r.n ** r.dim)
+        budget = 2 * backend.factor_bytes(big) + backend.factor_work_bytes(big) + \
+            backend.workspace_bytes(big, 16)
+        srv = serve.Server(backend, budget_bytes=budget, max_rhs=16, workers=3)
+        res, summ = srv.run(reqs)
+        print(summ, "kept", asp.asp_cached_bytes(), flush=True)
+        assert summ["completed"] == len(reqs), [r.status for r in res]
+        assert summ["evictions"] > 0
+        assert 0 < asp.asp_cached_bytes() <= limit
+    finally:
+        backend.close()
+    assert asp.asp_cached_bytes() == 0
+    for d, r in zip(descs, res):
+        assert r.status == "ASP_OK" and np.all(r.relres <= 1e-6)
+        u1, it1, _ = _alone(d, asp.ASP_PREC_FP32)
+        assert np.array_equal(it1, r.iters), d["rid"]
+        assert np.array_equal(u1, r.u), d["rid"]

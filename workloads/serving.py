@@ -80,8 +80,17 @@ def sources_of(desc):
     """(nrhs, n**d) complex128 Gaussian sources, each row column-major."""
     d, n = desc["d"], desc["n"]
     cents = seeded_centres(desc["nrhs"], d, desc["source_seed"])
-    return np.stack([flat(gaussian_source(n, d, desc["omega"], x0)) for x0 in cents]
-                    ).astype(np.complex128)
+    out = np.zeros((len(cents), n ** d), dtype=np.complex128)
+    t = np.arange(1, n + 1, dtype=np.float64) / (n + 1)
+    a = 4.0 * desc["omega"] / math.pi
+    for k, x0 in enumerate(cents):
+        # gaussian_source's factors and products, built with the last axis
+        # outermost so that C order is the column-major order of the grid
+        g = np.exp(-(a * a) * (t - x0[0]) ** 2)
+        for c in x0[1:d]:
+            g = np.multiply.outer(np.exp(-(a * a) * (t - c) ** 2), g)
+        out[k].real = g.reshape(-1)
+    return out
 
 
 def materialize(desc):
