@@ -376,7 +376,9 @@ class Server:
         t0 = time.perf_counter()
         self._t0 = t0
         for r in requests:
-            self._results[r.rid] = Result(r.rid, r.key, r.nrhs, r.arrival)
+            # without real-time arrivals every request is queued at the start,
+            # and its latency counts from there
+            self._results[r.rid] = Result(r.rid, r.key, r.nrhs, r.arrival if self.realtime else 0.0)
         pool = [threading.Thread(target=self._worker, args=(t0,), daemon=True)
                 for _ in range(self.workers)]
         for th in pool:

@@ -16,8 +16,8 @@ sides) the layer solves write through plain stores instead of buffer
 resources; a 129-RHS apply there must give bitwise the same vectors as the
 same right-hand sides applied in batches of 64 (same kernels, buffer path).
 
-Mixed precision (Algorithm 2 with FP32 layer factors; Algorithm 4 with FP32
-and with bf16-split Schur updates).  Two valid GMRES solutions at tol 1e-6 can
+Mixed precision (Algorithm 2 with FP32 layer factors and with bf16-split
+products; Algorithm 4 with FP32 and with bf16-split Schur updates).  Two valid GMRES solutions at tol 1e-6 can
 differ by up to cond(A) 1e-6, so the solution gate runs both sides to tol
 1e-10 and then asks for a relative difference <= 1e-6 against the FP64
 oracle's solution; at tol 1e-6 the iteration counts must be within one of the

@@ -206,6 +206,18 @@ def test_stream_through_fake_backend(realtime):
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
 
 
+def test_saturated_latency_counts_from_the_start():
+    """Without real-time arrivals every request is queued at the start: its
+    latency runs from there, whatever arrival time the stream gave it."""
+    s = workloads.request_stream(count=20, rate=0.5, seed=2, sizes=((2, 15),), max_rhs=2)
+    assert max(d["arrival"] for d in s) > 5.0
+    reqs = [Request.from_description(d) for d in s]
+    res, summ = Server(FakeBackend(solve_s=0.001, create_s=0.001), budget_bytes=10 ** 9,
+                       realtime=False).run(reqs)
+    assert summ["completed"] == 20 and summ["wall_s"] < 5.0
+    assert all(0.0 < r.done - r.arrival <= summ["wall_s"] for r in res)
+
+
 def test_factorization_work_buffers_are_reserved_while_creating():
     """A plan's creation needs its factors plus the factorization's work
     buffers; the server reserves both and returns the work buffers when the
