@@ -71,31 +71,38 @@ class Preconditioner:
         return self._G(self.L[p], w)
 
     # -- Algorithm 2 / 4 -------------------------------------------------------------------
+    def _sweep(self, u_qq, order, G, exit_line):
+        """One directional sweep of Section 2.1 ("Accumulating the boundary
+        values"): walking the layers in `order`, the first layer hands on the
+        exit line of its own local solution; every later layer p solves its
+        auxiliary problem with the accumulated line as boundary data (the part
+        of u~_p due to the sources behind it) and hands on the exit line of that
+        part plus that of u~_{p,p}.  Returns {p: part of u~_p from behind}."""
+        part = {}
+        line = exit_line(u_qq[order[0]])
+        for p in order[1:]:
+            part[p] = G(p, line)
+            line = exit_line(part[p]) + exit_line(u_qq[p])
+        return part
+
     def apply(self, f):
-        """u~ = M^-1 f, step by step as in Algorithms 2 and 4."""
+        """u~ = M^-1 f (Algorithms 2 and 4): the local solves u~_{p,p} = G~^M_p f_p,
+        the two sweeps, and u~_p as the sum of the local part and the parts
+        arriving from either side (one of them at the first and last layer)."""
         m = self.m
         f = np.asarray(f, dtype=np.complex128)
         u_qq = {q: self.GM(q, self.layer(f, q)) for q in range(1, m + 1)}
-        # right-going waves: u~_{p,1:p-1} and the accumulated boundary value u~^R_{p,1:p}
-        u_rt = {}
-        acc_R = self.right(u_qq[1])                      # u~^R_{1,1:1} = u~^R_{1,1}
-        for p in range(2, m + 1):
-            u_rt[p] = self.GR(p, acc_R)                  # u~_{p,1:p-1} = G~^R_p u~^R_{p-1,1:p-1}
-            acc_R = self.right(u_rt[p]) + self.right(u_qq[p])
-        # left-going waves: u~_{p,p+1:m} and u~^L_{p,p:m}
-        u_lt = {}
-        acc_L = self.left(u_qq[m])                       # u~^L_{m,m:m} = u~^L_{m,m}
-        for p in range(m - 1, 0, -1):
-            u_lt[p] = self.GL(p, acc_L)                  # u~_{p,p+1:m} = G~^L_p u~^L_{p+1,p+1:m}
-            acc_L = self.left(u_qq[p]) + self.left(u_lt[p])
-        # u~_p = u~_{p,1:p-1} + u~_{p,p} + u~_{p,p+1:m} (two terms at the ends)
+        # right-going: data enters R_p on its first line, leaves on the last
+        from_left = self._sweep(u_qq, list(range(1, m + 1)), self.GR, self.right)
+        # left-going: data enters L_p on its last line, leaves on the first
+        from_right = self._sweep(u_qq, list(range(m, 0, -1)), self.GL, self.left)
         out = []
         for p in range(1, m + 1):
             v = u_qq[p].copy()
             if p > 1:
-                v = u_rt[p] + v
+                v = from_left[p] + v
             if p < m:
-                v = v + u_lt[p]
+                v = v + from_right[p]
             out.append(v)
         return np.concatenate(out)
 
