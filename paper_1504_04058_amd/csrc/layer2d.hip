@@ -398,22 +398,25 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // (shm, ism: s at line k - 1/2 and 1 / s^2 at line k - 1 of axis 1).  The
     // data term is g_k (grid rows of X), g_k times the Dirichlet coupling
     // (boundary data on the carrying row) or the coupling alone (unit data on
-    // the carrying row at step slot + 1), selected by per-lane weights.
-    double wg[4], wb[4];
-    bool wu[4];
+    // the carrying row at step slot + 1), selected per lane; each input mode
+    // forms only its own term (a select where the mode needs no product).
+    bool carry[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        wg[v] = (INM == IN_GRID && inX[v]) ? 1.0 : 0.0;
-        wb[v] = (INM == IN_BOUNDARY && rowv[v] && row[v] == grow) ? 1.0 : 0.0;
-        wu[v] = INM == IN_UNIT && rowv[v] && row[v] == grow;
-    }
+    for (int v = 0; v < 4; ++v) carry[v] = rowv[v] && row[v] == grow;
     auto put_input = [&](int k, const zd (&g)[4], const cplx<T> (&y)[4], zd shm, zd ism) {
-        const zd cin = -(coupl * ism);
         const cplx<T> shc = ccast<T>(shm);
+        zd cin = mk(0.0, 0.0);
+        if constexpr (INM != IN_GRID) cin = -(coupl * ism);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const zd dv = g[v] * (mk(wg[v], 0.0) + wb[v] * cin);
-            cplx<T> t = ccast<T>((wu[v] && slot == k - 1) ? cin : dv);
+            zd dv;
+            if constexpr (INM == IN_GRID)
+                dv = csel(inX[v], g[v], mk(0.0, 0.0));
+            else if constexpr (INM == IN_BOUNDARY)
+                dv = csel(carry[v], g[v] * cin, mk(0.0, 0.0));
+            else
+                dv = csel(carry[v] && slot == k - 1, cin, mk(0.0, 0.0));
+            cplx<T> t = ccast<T>(dv);
             t = t - (shc * sinv2[v]) * y[v];              // y = 0 at the first step
             tb[k & 1][row[v]][rloc] = rowv[v] ? t : mk<T>(0, 0);
         }
