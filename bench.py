@@ -75,6 +75,9 @@ def parse():
                          "at saturation, then at fractions of the saturated request rate")
     ap.add_argument("--serve-fractions", default="0.5,0.8",
                     help="offered loads of --serve-spec as fractions of the saturated rate")
+    ap.add_argument("--serve-sat-rate", type=float, default=0.0, metavar="REQ_PER_S",
+                    help="with --serve-spec: skip the saturation run and take this saturated "
+                         "request rate (from an earlier run) for the offered loads")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0,
                     help="device memory the served factors and workspaces may hold")
     ap.add_argument("--cpu-sample", type=int, default=64,
@@ -336,7 +339,7 @@ def serving_run(count, prec_name):
     return summ
 
 
-def serving_spec(prec_name, count, fractions, budget_gb, cache_gb=48.0):
+def serving_spec(prec_name, count, fractions, budget_gb, cache_gb=48.0, sat_rate=0.0):
     """The full serving mix: a seeded Poisson stream of `count` requests (2D
     n = 127, 255, 511, 1023 and 3D n = 31, 63 with omega = 2 pi n / 8; constant,
     lens and random velocities; 1-32 right-hand sides; each request repeats an
@@ -363,9 +366,12 @@ def serving_spec(prec_name, count, fractions, budget_gb, cache_gb=48.0):
         summ["batches"] = len(srv.batches)
         return summ
 
-    print(f"serve-spec: {count} requests, saturation run", flush=True)
-    sat = one(1.0, False)
-    sat_rate = sat["completed"] / sat["wall_s"]
+    if sat_rate > 0:
+        sat = {"given_request_rate_per_s": sat_rate}
+    else:
+        print(f"serve-spec: {count} requests, saturation run", flush=True)
+        sat = one(1.0, False)
+        sat_rate = sat["completed"] / sat["wall_s"]
     out = {"stream": {"requests": count, "seed": 5, "sizes": "2D n = 127, 255, 511, 1023; 3D n = 31, 63",
                       "rhs_per_request": "1-32", "repeat": 0.5, "budget_gb": budget_gb,
                       "reuse_cache_gb": cache_gb,
@@ -550,7 +556,8 @@ def main():
         return
     if args.serve_spec:
         spec = serving_spec(args.prec, args.serve_spec,
-                            [float(x) for x in args.serve_fractions.split(",")], args.serve_budget_gb)
+                            [float(x) for x in args.serve_fractions.split(",")], args.serve_budget_gb,
+                            sat_rate=args.serve_sat_rate)
         print(json.dumps({"serving_spec": spec}), flush=True)
         return
     if args.gpus != 1:
