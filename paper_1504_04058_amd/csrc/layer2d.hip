@@ -749,11 +749,13 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
     const int per = (n + 16 * SW_W - 1) / (16 * SW_W) * 16;
     const int cb = wv * per, ce = min(cb + per, n);
     // one output per thread (tile t2o, lane l2, element v_); its u~ value is
-    // read now, ahead of the products
+    // read now, ahead of the products.  Column li of tile t2 is right-hand side
+    // 2 li + t2, so that a lane's two right-hand sides of a column of W are
+    // adjacent (one 16-byte load in FP32).
     const int tid = threadIdx.x;
     const int v_ = tid & 3, l2 = (tid >> 2) & 63, t2o = tid >> 8;
     const int ko = k0 + Mfma<T>::row(l2, v_);
-    const int slot = s0 + 16 * t2o + (l2 & 15);
+    const int slot = s0 + 2 * (l2 & 15) + t2o;
     const bool okout = ko < n && slot < a.nact;
     const int id = okout ? (a.act ? a.act[slot] : slot) : 0;
     const zd uval = a.Ugrid[(long long)id * a.N + (long long)n * (a.line[side] - 1) + (okout ? ko : 0)];
@@ -777,7 +779,7 @@ __global__ __launch_bounds__(64 * SW_W) void sweep_step_kernel(SweepArgs a) {
             const int cc = min(c, ce - 1);
             B.av[u] = Tt[(long long)cc * 16];
 #pragma unroll
-            for (int t2 = 0; t2 < 2; ++t2) B.bv[u][t2] = Wi[(long long)cc * ws + s0 + 16 * t2 + li];
+            for (int t2 = 0; t2 < 2; ++t2) B.bv[u][t2] = Wi[(long long)cc * ws + s0 + 2 * li + t2];
             B.ok[u] = c < ce;
         }
     };
