@@ -477,9 +477,7 @@ extern "C" asp_status asp_workspace_estimate(const asp_plan* P, int nrhs, int re
     const double esz = elem_bytes(P);
     if (P->dim == 3) {
         const double vec3 = (double)nrhs * P->N * sizeof(zd);
-        const double kr3 = vec3 * (2.0 * restart + 2.0) +
-                           (double)nrhs * krylov_blocks(P->N) * 8 * sizeof(zd) +
-                           (double)nrhs * 257 * sizeof(zd);
+        const double kr3 = vec3 * (2.0 * restart + 2.0) + krylov_small_bytes(P->N, nrhs);
         *bytes = (P->rec ? rec_workspace_estimate(P, nrhs)
                   : P->nd ? nd_workspace_estimate(P, nrhs) : workspace_estimate3(P, nrhs)) + (size_t)kr3;
         return ASP_OK;
@@ -488,9 +486,7 @@ extern "C" asp_status asp_workspace_estimate(const asp_plan* P, int nrhs, int re
     const double wrows = (double)std::max(2 * P->m - 2, 1) * nrhs * P->n * sizeof(zd);
     const double wt = (double)sweep_wt_len(P, nrhs) * esz;
     const double y = (double)apply_groups(P, nrhs) * solve_scratch_per_block(P) * esz;
-    const double krylov = vec * (2.0 * restart + 2.0) +
-                          (double)nrhs * krylov_blocks(P->N) * 8 * sizeof(zd) +
-                          (double)nrhs * 257 * sizeof(zd);
+    const double krylov = vec * (2.0 * restart + 2.0) + krylov_small_bytes(P->N, nrhs);
     *bytes = (size_t)(2.0 * vec + wrows + wt + y + krylov);
     return ASP_OK;
 }

@@ -457,9 +457,16 @@ struct KTimer {
 hipError_t launch_scale_by_s(const asp_plan* P, const zd* f, zd* b, int nrhs, hipStream_t st);
 // partial[r][blk][i] = sum conj(V_i[r]) w[r] for i in [i0, i1)
 int krylov_blocks(long long N);
-// fused Gram-Schmidt passes (modes: 0 dots, 1 update then dots, 2 update then
-// norm) over nv <= CGS_MAXV basis vectors; partial sums [rhs][block][CGS_MAXV]
+// fused Gram-Schmidt passes (modes: 0 dots, 1 update then dots and norm) over
+// nv <= CGS_MAXV basis vectors; partial sums [rhs][block][CGS_SLOTS]
 constexpr int CGS_MAXV = 24;
+constexpr int CGS_SLOTS = CGS_MAXV + 1;
+// the second Gram-Schmidt pass from the Gram matrix of the basis (E: per
+// right-hand side CGS_MAXV x CGS_MAXV, column j written at step j)
+hipError_t launch_gram(zd* small, int small_stride, int off_h1, int off_h2, int off_coef, int off_d,
+                       const zd* scal, zd* E, int j, const int* act, int nact, hipStream_t st);
+// device bytes of the GMRES partial sums, small arrays and Gram columns
+double krylov_small_bytes(long long N, int nrhs);
 // partial sums of |v|^2 per right-hand side, reduced by launch_reduce (one value)
 hipError_t launch_norms(const zd* v, long long N, const int* act, int nact, zd* partial,
                         hipStream_t st);

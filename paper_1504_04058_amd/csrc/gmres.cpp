@@ -3,7 +3,8 @@
 // form: the preconditioned vectors z_j = M^-1 v_j are kept and x = x0 + Z y, so
 // the Arnoldi relation A Z_j = V_{j+1} Hbar_j holds whatever precision M^-1
 // runs in.  Arnoldi uses classical Gram-Schmidt applied twice, in complex
-// double, on the device; the Hessenberg least-squares problem (Givens
+// double, on the device (the second pass's coefficients from the Gram matrix
+// of the basis, so the basis is read twice per step); the Hessenberg least-squares problem (Givens
 // rotations) runs on the host in double.  Each right-hand side has its own
 // Krylov space; right-hand sides that stop are dropped from every later launch.
 #include <hip/hip_runtime.h>
@@ -21,9 +22,16 @@ using cd = std::complex<double>;
 constexpr int CH = 8;          // vectors per multi-dot / multi-axpy launch
 constexpr int SMALL = 256;     // per-RHS slots of the small device array
 // layout of the small array per RHS: [0,64) first Gram-Schmidt pass,
-// [64,128) second pass, [128] |w|^2, [192,256) update coefficients
-constexpr int OFF_H1 = 0, OFF_H2 = 64, OFF_NRM = 128, OFF_COEF = 192;
+// [64,128) second pass, [128] |w|^2, [129,129+CGS_SLOTS) the dots and |w|^2
+// after the fused second pass, [192,256) update coefficients
+constexpr int OFF_H1 = 0, OFF_H2 = 64, OFF_NRM = 128, OFF_D = 129, OFF_COEF = 192;
+static_assert(OFF_D + CGS_SLOTS <= OFF_COEF, "small-array layout");
 constexpr int MAX_RESTART = 64;
+
+// elements of the partial-sum buffer per right-hand side
+size_t krylov_red_elems(long long N) {
+    return std::max((size_t)krylov_blocks(N) * CH, (size_t)cgs_blocks(N) * CGS_SLOTS);
+}
 
 template <typename T>
 asp_status dev_alloc(asp_plan* P, T** p, size_t count) {
@@ -46,17 +54,19 @@ asp_status ensure_krylov_ws(asp_plan* P, int nrhs, int restart) {
     P->kr_rhs = P->kr_restart = 0;
     P->kr_bytes = 0;
     const size_t vec = (size_t)nrhs * P->N;
-    const int nblk = krylov_blocks(P->N);
     if (dev_alloc(P, &P->d_V, vec * (restart + 1)) != ASP_OK) return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_Z, vec * restart) != ASP_OK) return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_b, vec) != ASP_OK) return ASP_ERR_OOM;
-    const size_t red = std::max((size_t)nblk * CH, (size_t)cgs_blocks(P->N) * CGS_MAXV);
+    const size_t red = krylov_red_elems(P->N);
     if (dev_alloc(P, &P->d_red, (size_t)nrhs * red) != ASP_OK) return ASP_ERR_OOM;
-    if (dev_alloc(P, &P->d_small, (size_t)nrhs * SMALL + nrhs) != ASP_OK) return ASP_ERR_OOM;
+    // small array, the scales 1/beta, the Gram-matrix columns of each basis
+    if (dev_alloc(P, &P->d_small, (size_t)nrhs * (SMALL + 1 + CGS_MAXV * CGS_MAXV)) != ASP_OK)
+        return ASP_ERR_OOM;
     if (dev_alloc(P, &P->d_act, (size_t)nrhs) != ASP_OK) return ASP_ERR_OOM;
     P->kr_rhs = nrhs;
     P->kr_restart = restart;
-    P->kr_bytes = vec * (2 * restart + 2) * sizeof(zd) + (size_t)nrhs * red * sizeof(zd);
+    P->kr_bytes = vec * (2 * restart + 2) * sizeof(zd) + (size_t)nrhs * red * sizeof(zd) +
+                  (size_t)nrhs * (SMALL + 1 + CGS_MAXV * CGS_MAXV) * sizeof(zd);
     return ASP_OK;
 }
 
@@ -95,6 +105,7 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
     zd* b = P->d_b;
     zd* small = P->d_small;
     zd* scal = P->d_small + (size_t)nrhs * SMALL;
+    zd* gram = scal + nrhs;   // [rhs][CGS_MAXV][CGS_MAXV]
     const int nblk = krylov_blocks(N);
     std::vector<zd> hsmall((size_t)nrhs * SMALL + nrhs);
     std::vector<int> act;
@@ -199,22 +210,24 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
             if ((s = apply_internal(P, vj, zj, P->d_act, ni)) != ASP_OK) return s;
             ASP_TIMED(P, ASP_K_STENCIL, 32.0 * ni * N + 8.0 * N, 40.0 * ni * N,
                       launch_stencil(P, zj, w, P->d_act, ni, st));
-            // two passes of classical Gram-Schmidt against v_0..v_j
-            if (j + 1 <= CGS_MAXV) {
-                // fused: h1 = V^H w; w -= V h1 and h2 = V^H w; w -= V h2 and |w|^2
+            // classical Gram-Schmidt applied twice against v_0..v_j
+            const bool fused = j + 1 <= CGS_MAXV;
+            if (fused) {
+                // two reads of the basis: h1 = V^H w; the second pass's
+                // coefficients h2 = -E h1 from the Gram matrix of the basis
+                // (launch_gram); w -= V (h1 + h2) with V^H w (the Gram column of
+                // the next basis vector) and |w|^2
                 const int nv = j + 1, cb = cgs_blocks(N);
                 const double vb = 16.0 * ni * N;
                 ASP_TIMED(P, ASP_K_KRYLOV, vb * (nv + 1), 8.0 * nv * ni * N,
                           launch_cgs(0, nv, V, vs, nullptr, 0, w, N, P->d_act, ni, P->d_red, st));
                 ASP_HIP(P, launch_cgs_reduce(P->d_red, cb, nv, P->d_act, ni, small + OFF_H1, SMALL, st));
-                ASP_TIMED(P, ASP_K_KRYLOV, vb * (nv + 2), 16.0 * nv * ni * N,
-                          launch_cgs(1, nv, V, vs, small + OFF_H1, SMALL, w, N, P->d_act, ni,
+                ASP_HIP(P, launch_gram(small, SMALL, OFF_H1, OFF_H2, OFF_COEF, OFF_D, scal, gram, j,
+                                       P->d_act, ni, st));
+                ASP_TIMED(P, ASP_K_KRYLOV, vb * (nv + 2), 16.0 * nv * ni * N + 4.0 * ni * N,
+                          launch_cgs(1, nv, V, vs, small + OFF_COEF, SMALL, w, N, P->d_act, ni,
                                      P->d_red, st));
-                ASP_HIP(P, launch_cgs_reduce(P->d_red, cb, nv, P->d_act, ni, small + OFF_H2, SMALL, st));
-                ASP_TIMED(P, ASP_K_KRYLOV, vb * (nv + 2), 8.0 * nv * ni * N + 4.0 * ni * N,
-                          launch_cgs(2, nv, V, vs, small + OFF_H2, SMALL, w, N, P->d_act, ni,
-                                     P->d_red, st));
-                ASP_HIP(P, launch_cgs_reduce(P->d_red, cb, 1, P->d_act, ni, small + OFF_NRM, SMALL, st));
+                ASP_HIP(P, launch_cgs_reduce(P->d_red, cb, nv + 1, P->d_act, ni, small + OFF_D, SMALL, st));
             } else {
                 for (int pass = 0; pass < 2; ++pass) {
                     const int off = pass == 0 ? OFF_H1 : OFF_H2;
@@ -243,7 +256,7 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
                 cd* Hc = q.H.data() + (size_t)j * (restart + 1);   // column j
                 for (int i = 0; i <= j; ++i)
                     Hc[i] = cd(hs[OFF_H1 + i].x, hs[OFF_H1 + i].y) + cd(hs[OFF_H2 + i].x, hs[OFF_H2 + i].y);
-                const double hnext = std::sqrt(hs[OFF_NRM].x);
+                const double hnext = std::sqrt(fused ? hs[OFF_D + j + 1].x : hs[OFF_NRM].x);
                 Hc[j + 1] = hnext;
                 if (!std::isfinite(hnext)) return plan_fail(P, ASP_ERR_BREAKDOWN, "asp_gmres: non-finite Arnoldi vector");
                 // apply the previous rotations, then a new one that zeroes H(j+1, j)
@@ -324,4 +337,8 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
     }
     if (!all) return plan_fail(P, ASP_ERR_NOCONV, "asp_gmres: maxit reached before tol");
     return ASP_OK;
+}
+
+double krylov_small_bytes(long long N, int nrhs) {
+    return (double)nrhs * (double)(krylov_red_elems(N) + SMALL + 1 + CGS_MAXV * CGS_MAXV) * sizeof(zd);
 }

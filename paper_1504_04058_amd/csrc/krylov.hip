@@ -204,15 +204,15 @@ __global__ __launch_bounds__(BS) void axpy_multi_kernel(const zd* __restrict__ V
 // ----------------------------------------------------------------------------
 // Fused classical Gram-Schmidt passes over the basis v_0 .. v_{nv-1} (nv <=
 // CGS_MAXV), one right-hand side per grid row:
-//   CGS_DOT:     p_k = sum conj(v_k) w
-//   CGS_UPD_DOT: w -= sum_k c_k v_k, then p_k = sum conj(v_k) w   (one read of V)
-//   CGS_UPD_NRM: w -= sum_k c_k v_k, then |w|^2
-// Two passes of Gram-Schmidt then read the basis three times.  Each thread
-// walks its elements with a fixed stride; the per-block sums are reduced
-// through a fixed butterfly inside each wavefront and a fixed order across
-// the four wavefronts, so results do not depend on the other right-hand sides.
+//   CGS_DOT:         p_k = sum conj(v_k) w
+//   CGS_UPD_DOT_NRM: w -= sum_k c_k v_k, then p_k = sum conj(v_k) w and
+//                    p_nv = |w|^2   (one read of V)
+// Each thread walks its elements with a fixed stride; the per-block sums are
+// reduced through a fixed butterfly inside each wavefront and a fixed order
+// across the four wavefronts, so results do not depend on the other
+// right-hand sides.
 // ----------------------------------------------------------------------------
-constexpr int CGS_DOT = 0, CGS_UPD_DOT = 1, CGS_UPD_NRM = 2;
+constexpr int CGS_DOT = 0, CGS_UPD_DOT_NRM = 1;
 
 template <int NV, int MODE>
 __global__ __launch_bounds__(BS) void cgs_kernel(const zd* __restrict__ V, long long vstride,
@@ -220,7 +220,8 @@ __global__ __launch_bounds__(BS) void cgs_kernel(const zd* __restrict__ V, long 
                                                 zd* __restrict__ w, long long N,
                                                 const int* __restrict__ act,
                                                 zd* __restrict__ partial) {
-    constexpr int NO = (MODE == CGS_UPD_NRM) ? 1 : NV;   // sums per block
+    constexpr int NO = (MODE == CGS_UPD_DOT_NRM) ? NV + 1 : NV;   // sums per block
+    static_assert(NO <= CGS_SLOTS, "partial sums per block");
     __shared__ zd red[BS / 64][NO];
     const int rhs = act ? act[blockIdx.y] : (int)blockIdx.y;
     const int nblk = gridDim.x;
@@ -244,12 +245,9 @@ __global__ __launch_bounds__(BS) void cgs_kernel(const zd* __restrict__ V, long 
             for (int k = 0; k < NV; ++k) x = x - cf[k] * vv[k];
             wr[idx] = x;
         }
-        if (MODE == CGS_UPD_NRM) {
-            acc[0].x += abs2(x);
-        } else {
 #pragma unroll
-            for (int k = 0; k < NV; ++k) acc[k] = cfma_conj(vv[k], x, acc[k]);
-        }
+        for (int k = 0; k < NV; ++k) acc[k] = cfma_conj(vv[k], x, acc[k]);
+        if constexpr (MODE == CGS_UPD_DOT_NRM) acc[NV].x += abs2(x);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
@@ -267,7 +265,7 @@ __global__ __launch_bounds__(BS) void cgs_kernel(const zd* __restrict__ V, long 
         zd t = red[0][threadIdx.x];
 #pragma unroll
         for (int q = 1; q < BS / 64; ++q) t = t + red[q][threadIdx.x];
-        partial[((long long)rhs * nblk + blockIdx.x) * CGS_MAXV + threadIdx.x] = t;
+        partial[((long long)rhs * nblk + blockIdx.x) * CGS_SLOTS + threadIdx.x] = t;
     }
 }
 
@@ -275,12 +273,12 @@ __global__ __launch_bounds__(BS) void cgs_kernel(const zd* __restrict__ V, long 
 __global__ __launch_bounds__(64) void cgs_reduce_kernel(const zd* __restrict__ partial, int nblk,
                                                       int nv, const int* __restrict__ act,
                                                       zd* __restrict__ out, int out_stride) {
-    __shared__ zd sh[CGS_MAXV][65];
+    __shared__ zd sh[CGS_SLOTS][65];
     const int rhs = act ? act[blockIdx.x] : (int)blockIdx.x;
     const int t = threadIdx.x;
     for (int k = 0; k < nv; ++k) {
         zd a = mk(0.0, 0.0);
-        for (int b = t; b < nblk; b += 64) a = a + partial[((long long)rhs * nblk + b) * CGS_MAXV + k];
+        for (int b = t; b < nblk; b += 64) a = a + partial[((long long)rhs * nblk + b) * CGS_SLOTS + k];
         sh[k][t] = a;
     }
     __syncthreads();
@@ -288,6 +286,40 @@ __global__ __launch_bounds__(64) void cgs_reduce_kernel(const zd* __restrict__ p
         zd a = sh[t][0];
         for (int q = 1; q < 64; ++q) a = a + sh[t][q];
         out[(long long)rhs * out_stride + t] = a;
+    }
+}
+
+// The second Gram-Schmidt pass from the Gram matrix of the basis.  For the
+// basis V = [v_0 .. v_j] with G = V^H V, the second pass's coefficients
+// V^H (w - V h1) equal h1 - G h1; with unit vectors that is -E h1, E the
+// off-diagonal part of G, whose entries are dot products of stored basis
+// vectors (small, computed directly, so no cancellation).  The second pass
+// then needs no read of V: w -= V (h1 + h2) in one pass, whose dots with V
+// give the next column of E.  Per right-hand side: column j of E (upper
+// triangle, E[i][j] = conj(v_i) . v_j) from the previous pass's dots d and the
+// scale 1/beta that made v_j = w / beta; then h2 = -E h1 and c = h1 + h2.
+// One workgroup per right-hand side, every sum in a fixed order.
+__global__ __launch_bounds__(64) void gram_kernel(zd* __restrict__ small, int small_stride, int off_h1,
+                                                 int off_h2, int off_coef, int off_d,
+                                                 const zd* __restrict__ scal, zd* __restrict__ E,
+                                                 int j, const int* __restrict__ act) {
+    const int rhs = act ? act[blockIdx.x] : (int)blockIdx.x;
+    zd* sm = small + (long long)rhs * small_stride;
+    zd* Er = E + (long long)rhs * CGS_MAXV * CGS_MAXV;
+    const int t = threadIdx.x;
+    if (j >= 1 && t < j) Er[t * CGS_MAXV + j] = scal[rhs].x * sm[off_d + t];
+    __syncthreads();
+    if (t <= j) {
+        zd acc = mk(0.0, 0.0);
+        for (int k = 0; k <= j; ++k) {
+            if (k == t) continue;
+            // E[t][k] for k > t; the Hermitian mirror conj(E[k][t]) below
+            acc = k > t ? cfma(Er[t * CGS_MAXV + k], sm[off_h1 + k], acc)
+                        : cfma_conj(Er[k * CGS_MAXV + t], sm[off_h1 + k], acc);
+        }
+        const zd h2 = mk(-acc.x, -acc.y);
+        sm[off_h2 + t] = h2;
+        sm[off_coef + t] = sm[off_h1 + t] + h2;
     }
 }
 
@@ -454,18 +486,23 @@ hipError_t launch_cgs(int mode, int nv, const zd* V, long long vstride, const zd
     if (mode == CGS_DOT)
         return launch_cgs_mode<CGS_DOT>(nv, V, vstride, coef, coef_stride, w, N, act, nact,
                                         partial, st);
-    if (mode == CGS_UPD_DOT)
-        return launch_cgs_mode<CGS_UPD_DOT>(nv, V, vstride, coef, coef_stride, w, N, act, nact,
+    return launch_cgs_mode<CGS_UPD_DOT_NRM>(nv, V, vstride, coef, coef_stride, w, N, act, nact,
                                             partial, st);
-    return launch_cgs_mode<CGS_UPD_NRM>(nv, V, vstride, coef, coef_stride, w, N, act, nact,
-                                        partial, st);
 }
 
 hipError_t launch_cgs_reduce(const zd* partial, int nblk, int nv, const int* act, int nact,
                              zd* out, int out_stride, hipStream_t st) {
-    if (nv < 1 || nv > CGS_MAXV) return hipErrorInvalidValue;
+    if (nv < 1 || nv > CGS_SLOTS) return hipErrorInvalidValue;
     hipLaunchKernelGGL(cgs_reduce_kernel, dim3(nact), dim3(64), 0, st, partial, nblk, nv, act,
                        out, out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram(zd* small, int small_stride, int off_h1, int off_h2, int off_coef, int off_d,
+                       const zd* scal, zd* E, int j, const int* act, int nact, hipStream_t st) {
+    if (j < 0 || j >= CGS_MAXV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gram_kernel, dim3(nact), dim3(64), 0, st, small, small_stride, off_h1, off_h2,
+                       off_coef, off_d, scal, E, j, act);
     return hipGetLastError();
 }
 

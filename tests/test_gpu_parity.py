@@ -267,3 +267,28 @@ def test_gmres_sequential_sweep_counts():
         x_ref, it_ref, _, _ = oracle_gmres(lambda v: A @ v, M.apply, b, 1e-6, 20, 200)
         assert abs(int(it[k]) - it_ref) <= 1
         assert rel(u[k], x_ref) < 1e-6
+
+
+def test_gmres_long_cycle():
+    """A hard case (2D n = 63, random velocity at 3 points per wavelength,
+    GMRES(40) to 1e-10): the oracle needs 52 iterations, so one cycle runs
+    past the 24 basis vectors of the fused Gram-Schmidt passes into the
+    chunked ones, then restarts.  FP64 factors: the count within one of the
+    oracle's, the true residual at the tolerance, the solution close."""
+    n = 63
+    w = workloads.workload("2d_n1023_random", n=n, nrhs=2)
+    P = Problem(2, n, 2 * math.pi * (n + 1) / 3, 12, 25.0, 4, w["c"])
+    A, M = P.A(), Preconditioner(P)
+    with _plan(P) as plan:
+        u, it, rr, st = plan.gmres(dev(w["f"]), tol=1e-10, restart=40, maxit=400)
+        u = host(u)
+    assert st == asp.ASP_OK
+    for k in range(2):
+        b = w["f"][k] / P.scale()
+        x_ref, it_ref, _, _ = oracle_gmres(lambda v: A @ v, M.apply, b, 1e-10, 40, 400)
+        e = rel(u[k], x_ref)
+        print(f"long cycle rhs {k}: iters {int(it[k])} (oracle {it_ref}), error {e:.2e}", flush=True)
+        assert it_ref > 40
+        assert abs(int(it[k]) - it_ref) <= 1
+        assert np.linalg.norm(b - A @ u[k]) / np.linalg.norm(b) <= 1e-10 * (1 + 1e-6)
+        assert e < 1e-7
