@@ -38,10 +38,6 @@ long long apply_groups(const asp_plan* P, int nrhs) {
                     (long long)std::max(2 * P->m - 2, 1) * groups_of(nrhs, P->LR_RL));
 }
 
-// the boundary maps are computed in launches of at least this many workgroups
-// (two per CU), or all of them when fewer
-constexpr long long TRANSFER_GROUPS = 512;
-
 // forward-substitution scratch for at least `waves` workgroups
 asp_status ensure_y(asp_plan* P, long long waves) {
     if (waves <= P->y_waves) return ASP_OK;
@@ -79,18 +75,11 @@ size_t solve_scratch_bytes(const asp_plan* P) {
     return (size_t)P->y_waves * solve_scratch_per_block(P) * elem_bytes(P);
 }
 
-// workgroups of one boundary-map launch: all the unit-data solves, at most
-// TRANSFER_GROUPS at a time
-static long long transfer_groups(const asp_plan* P) {
-    return std::min<long long>(TRANSFER_GROUPS,
-                               (long long)std::max(2 * P->m - 4, 1) * groups_of(P->n, P->LR_RL));
-}
-
 size_t factor_work_estimate(const asp_plan* P) {
     if (P->dim == 3)
         return P->rec ? rec_factor_work_estimate(P)
                       : P->nd ? nd_factor_work_estimate(P) : factor3d_work_estimate(P);
-    return (size_t)transfer_groups(P) * solve_scratch_per_block(P) * elem_bytes(P);
+    return 0;   // 2D: the factorization and the boundary maps use no work buffers
 }
 
 double factor_bytes_of(const asp_plan* P, const SubDesc& d) {
@@ -324,26 +313,49 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
 
 // boundary-to-boundary maps: T^R_p = (G~^R_p e_c) on the last line of X_p and
 // T^L_p = (G~^L_p e_c) on the first line of X_p, c = 1..n, for 1 < p < m
+// The boundary maps T^R_p, T^L_p (1 < p < m): column c of a map is the outgoing
+// line of G~ applied to unit data at i1 = c + 1.  With the forward factors
+// S_k^-1 and the diagonal blocks G_k of H^-1 (launch_rgf2d), the solution for
+// unit data at block c + 1 is the coupling times column grow of G_{c+1} there
+// and, towards block 1, x_k = -S_k^-1 E_k x_{k+1}: the map entries on and
+// above the diagonal (IN_TWIST kind 0).  The entries below it come from the
+// solutions for unit data on the outgoing line (column jout of G_{r+1}), read
+// on the data line, since H is complex symmetric (kind 1).  No forward sweep
+// and no scratch: a chunk of columns is one chain of at most (ch + 1) SRB steps.
 static asp_status compute_transfer(asp_plan* P) {
     const int m = P->m;
     if (m < 3) return ASP_OK;
-    const int per_job = groups_of(P->n, P->LR_RL);
-    const long long chunk = std::max<long long>(1, P->y_waves / per_job);
+    const double esz = elem_bytes(P);
     for (int side = 0; side < 2; ++side) {
         const int first = side == 0 ? P->idx_R(2) : P->idx_L(2);
-        for (int j0 = 0; j0 < m - 2; j0 += (int)chunk) {
-            const int nj = (int)std::min<long long>(chunk, m - 2 - j0);
+        const int nj = m - 2;
+        double fb = 0, fl = 0, L2 = 0;
+        for (int s = first; s < first + nj; ++s) {
+            const SubDesc& d = P->subs[s];
+            fb += factor_bytes_of(P, d);
+            fl += (double)P->n * 2.0 * d.L * d.L * d.L * 8.0;   // two L^3 complex products per block
+            L2 += (double)d.L * d.L;
+        }
+        {
+            KTimer t(P, ASP_K_TRANSFER, fb + (double)nj * P->n * 2 * P->LR_RL * esz, fl);
+            ASP_HIP(P, launch_rgf2d(P, first, nj, P->stream));
+            t.end();
+        }
+        for (int kind = 0; kind < 2; ++kind) {
             SolveLaunch L;
-            L.job0 = first + j0;
+            L.job0 = first;
             L.njobs = nj;
             L.rl = true;
             L.nact = P->n;
-            L.in_mode = IN_UNIT;
+            L.in_mode = IN_TWIST;
             L.out_mode = OUT_LINE;
-            double by, fl;
-            solve_cost(P, L.job0, nj, P->n, 0.0, &by, &fl);
-            by += (double)nj * P->n * P->n * elem_bytes(P);
-            KTimer t(P, ASP_K_TRANSFER, by, fl);
+            L.twist_kind = kind;
+            // about n^2 / 2 block steps of L^2 complex MACs per problem and kind;
+            // the factor read once per chunk over half the blocks on average
+            const double chunks = (P->n + solve_rhs_per_block(P->LR_RL) - 1) / solve_rhs_per_block(P->LR_RL);
+            const double by = 0.5 * chunks * fb + 0.5 * (double)nj * P->n * P->n * esz;
+            const double flk = 0.5 * (double)P->n * P->n * L2 * 8.0;
+            KTimer t(P, ASP_K_TRANSFER, by, flk);
             ASP_HIP(P, launch_solve2d(P, L, P->stream));
             t.end();
         }
@@ -377,8 +389,7 @@ extern "C" asp_status asp_factor(asp_plan* P) {
         if (dev_alloc(P, &t, P->t_bytes) != ASP_OK) return ASP_ERR_OOM;
         P->d_T = t;
     }
-    asp_status s = ensure_y(P, transfer_groups(P));
-    if (s != ASP_OK) return s;
+    asp_status s = ASP_OK;
     ASP_HIP(P, hipMemsetAsync(P->d_flag, 0, sizeof(int), P->stream));
     {
         double fb = 0, fl = 0;

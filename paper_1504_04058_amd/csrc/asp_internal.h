@@ -97,6 +97,8 @@ struct SubDesc {
     long long fac_off;   // offset of block k = 1 in the factor buffer (complex entries)
     long long tab_off;   // offset of this problem's tables in the table buffer
     long long tr_off;    // offset of its boundary-to-boundary map (R_p, L_p with 1 < p < m), else -1
+    long long g_off;     // map problems: offset (in the map buffer) of the columns of the
+                         // diagonal blocks of H^-1 the maps start from, [k][2][LR]; else -1
     int wrow;            // R/L problems: row of its boundary data in the sweep buffer, else -1
     long long vec_off;   // 3D: offset of this problem's per-entry vectors (B entries each)
     long long xoff;      // 3D nested dissection: this problem's slab vector (n^2 L x 16 per chunk)
@@ -141,7 +143,7 @@ struct RecDesc {
 };
 
 // solve launch modes
-enum { IN_GRID = 0, IN_BOUNDARY = 1, IN_UNIT = 2 };
+enum { IN_GRID = 0, IN_BOUNDARY = 1, IN_UNIT = 2, IN_TWIST = 3 };
 enum { OUT_GRID_STORE = 0, OUT_GRID_ADD_U = 1, OUT_GRID_ACC = 2, OUT_LINE = 3 };
 
 // Per-problem sweep-axis tables, complex double, at tab_off:
@@ -354,8 +356,15 @@ struct SolveLaunch {
     // a launch over R and L problems: the L problems write here instead (NULL: out)
     int out_mode_L = OUT_GRID_STORE;
     zd* out_L = nullptr;
+    // IN_TWIST: 0 = solutions for unit data at column slot (map columns on and
+    // above the diagonal), 1 = for unit data on the map's output line at row
+    // slot (the entries below the diagonal, by the symmetry of H)
+    int twist_kind = 0;
 };
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st);
+// columns grow and jout of the diagonal blocks of H^-1 of the map problems
+// jobs[job0 .. job0 + njobs) (R_p or L_p with 1 < p < m, after asp_factor)
+hipError_t launch_rgf2d(const asp_plan* P, int job0, int njobs, hipStream_t st);
 // device memory of the library (devmem.cpp): blocks may be cached and handed
 // to another plan, so a block is freed only once no work is pending on it
 // (after a synchronization of the owning plan's stream)

@@ -198,6 +198,102 @@ __global__ __launch_bounds__(FB) void factor2d_kernel(const SubDesc* __restrict_
 }
 
 // ----------------------------------------------------------------------------
+// The diagonal blocks G_k of H^-1 of a map problem (R_p or L_p, 1 < p < m),
+// from the stored S_k^-1: G_n = S_n^-1 and, towards block 1,
+//   G_k = S_k^-1 + S_k^-1 E_k G_{k+1} E_k S_k^-1,
+// E_k the diagonal coupling of blocks k and k+1 (H, S_k^-1 and G_k are complex
+// symmetric).  The boundary maps then start from two columns of every G_k
+// (IN_TWIST solves).  One 256-thread workgroup per problem, k from n down to 1;
+// thread (j, g) holds rows g RPL .. of column j of G in double, the two
+// products of a step go through LDS.  Columns grow and jout of each G_k are
+// stored (type TS) at the problem's g_off in the map buffer, [k][2][LR].
+// ----------------------------------------------------------------------------
+template <typename TS, int LR>
+__device__ __forceinline__ void rgf2d_body(const SubDesc& d, AxisTables ax, const zd* __restrict__ subtab,
+                                           int n, const cplx<TS>* __restrict__ fac, cplx<TS>* __restrict__ tbuf,
+                                           zd (*A)[LR + 1], zd (*Bm)[LR + 1]) {
+    constexpr int G = FB / LR, RPL = LR / G;
+    const int L = d.L;
+    const int t = threadIdx.x, j = t % LR, g = t / LR;
+    const zd* sinv2 = subtab + d.tab_off + L + 1;        // 1/(s h^2) on lines lo..hi
+    const zd ecol = j < L ? sinv2[min(j, L - 1)] : mk(0.0, 0.0);
+    zd erow[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int r = g * RPL + q;
+        erow[q] = r < L ? sinv2[min(r, L - 1)] : mk(0.0, 0.0);
+    }
+    const int grow = (d.kind == ASP_SUB_R) ? 0 : L - 1;
+    const int jout = (d.kind == ASP_SUB_R) ? (d.xe - d.lo) : (d.xs - d.lo);
+    const cplx<TS>* F = fac + d.fac_off;
+    cplx<TS>* Gout = tbuf + d.g_off;
+    zd Gv[RPL], sv[RPL];
+    for (int k = n; k >= 1; --k) {
+        // S_k^-1 (block k - 1, column-major, rows past L zero): column j
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int r = g * RPL + q;
+            sv[q] = (j < L && r < L) ? ccast<double>(F[(long long)(k - 1) * L * LR + (long long)j * LR + r])
+                                     : mk(0.0, 0.0);
+        }
+        if (k == n) {
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) Gv[q] = sv[q];
+        } else {
+            const zd sh = ax.sh[k];                            // s at the half line k + 1/2
+            // A = G_{k+1} E_k, Bm = S_k^-1
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int r = g * RPL + q;
+                A[r][j] = Gv[q] * (sh * ecol);
+                Bm[r][j] = sv[q];
+            }
+            __syncthreads();
+            // X = E_k (A Bm) = E_k G_{k+1} E_k S_k^-1
+            zd xv[RPL];
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int r = g * RPL + q;
+                zd acc = mk(0.0, 0.0);
+                for (int l = 0; l < L; ++l) acc = cfma(A[r][l], Bm[l][j], acc);
+                xv[q] = (sh * erow[q]) * acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) A[g * RPL + q][j] = xv[q];
+            __syncthreads();
+            // G_k = S_k^-1 + S_k^-1 X, with (S_k^-1)[r][l] = Bm[l][r] (symmetric)
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int r = g * RPL + q;
+                zd acc = mk(0.0, 0.0);
+                for (int l = 0; l < L; ++l) acc = cfma(Bm[l][r], A[l][j], acc);
+                Gv[q] = sv[q] + acc;
+            }
+            __syncthreads();   // A and Bm are written again at the next step
+        }
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int r = g * RPL + q;
+            if (r < L && j == grow) Gout[(long long)(k - 1) * 2 * LR + r] = ccast<TS>(Gv[q]);
+            if (r < L && j == jout) Gout[(long long)(k - 1) * 2 * LR + LR + r] = ccast<TS>(Gv[q]);
+        }
+    }
+}
+
+template <typename TS, int LR>
+__global__ __launch_bounds__(FB) void rgf2d_kernel(const SubDesc* __restrict__ desc,
+                                                  const int* __restrict__ jobs, AxisTables ax,
+                                                  const zd* __restrict__ subtab, int n,
+                                                  const cplx<TS>* __restrict__ fac,
+                                                  cplx<TS>* __restrict__ tbuf) {
+    __shared__ zd A[LR][LR + 1];
+    __shared__ zd Bm[LR][LR + 1];
+    const SubDesc d = desc[jobs[blockIdx.x]];
+    rgf2d_body<TS, LR>(d, ax, subtab, n, fac, tbuf, A, Bm);
+}
+
+// ----------------------------------------------------------------------------
 // batched solves on the matrix cores: one 256-thread workgroup per (auxiliary
 // problem, chunk of 1024 / LR right-hand sides).  A block step is the product
 // of S_k^-1 (L x L, staged in an LDS ring; the next block's load overlaps the
@@ -244,6 +340,7 @@ struct SolveArgs {
     long long y_per_wave;   // scratch entries per workgroup
     zd* sink;               // discard buffer: four entries per thread
     int buf_ok;             // output byte offsets fit the 31-bit buffer range
+    int twist_kind;         // IN_TWIST: 0 map columns on and above the diagonal, 1 below
     int n;
     long long N;
 };
@@ -255,7 +352,9 @@ constexpr int SB = 256;        // threads per solve workgroup: four wavefronts, 
 template <typename T, int LR, int INM, bool SPL = false>
 __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     static_assert(!SPL || std::is_same<T, float>::value, "the split products take FP32 operands");
-    static_assert(INM == IN_GRID || INM == IN_BOUNDARY || INM == IN_UNIT, "input mode");
+    static_assert(INM == IN_GRID || INM == IN_BOUNDARY || INM == IN_UNIT || INM == IN_TWIST,
+                  "input mode");
+    constexpr bool NOSTAGE = INM == IN_UNIT || INM == IN_TWIST;   // map outputs: no staging
     constexpr int SRB = 1024 / LR;          // right-hand sides per workgroup
     constexpr int NCT = SRB / 16;           // right-hand-side tiles
     static_assert((LR / 16) * NCT == 4, "four 16 x 16 tiles, one per wavefront");
@@ -268,7 +367,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // grid outputs of the first SROW lines of X for KO steps, by group parity
     constexpr int KO = sizeof(T) == 4 ? 8 : 4;
     constexpr int SROW = 4;
-    __shared__ cplx<T> stg[INM == IN_UNIT ? 1 : 2 * KO * SROW * SRB];
+    __shared__ cplx<T> stg[NOSTAGE ? 1 : 2 * KO * SROW * SRB];
 
     // XCD-aware order: the chunks of one problem are consecutive work items
     const int nchunk = (a.nact + SRB - 1) / SRB;
@@ -445,65 +544,75 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) yk[v] = mk<T>(0, 0);
 
-    // forward sweep: y_k = S_k^-1 t_k; block k-1 (S_k^-1) sits in ring slot
-    // k & 1.  Slot of step k: the input g_{k+1}, the couplings of lines k, k+1
-    // and block k, all used at the end of step k.  The last step stashes block
-    // n-2 (already in its ring slot) and forms an input nobody reads: the
-    // backward pass finds block n-2 where it expects it and overwrites tb.
-    struct FwdSlot {
-        cplx<T> pf[FPT];
-        zd g[4];
-        zd sh, ism;
-    };
-    auto prefetch_f = [&](FwdSlot& S, int k) {
-        load_in(min(k + 1, n), S.g);
-        fetch_to(S.pf, k <= n - 1 ? k : max(n - 2, 0));
-        const int kc = min(k, n - 1);
-        S.sh = a.ax.sh[kc];
-        S.ism = a.ax.inv_sh2[kc];
-    };
-    FwdSlot fsl[2];
-    {
-        zd g0[4];
-        load_in(kstart, g0);
-        fetch_to(fsl[0].pf, kstart - 1);
-        const zd sh0 = a.ax.sh[kstart - 1], ism0 = a.ax.inv_sh2[kstart - 1];
-        stash_from(fsl[0].pf, kstart & 1);
-        put_input(kstart, g0, yk, sh0, ism0);
-    }
-    prefetch_f(fsl[0], kstart);
-    prefetch_f(fsl[1], kstart + 1);
-    // one full wait before the loop: with nothing outstanding on entry, the
-    // waits inside the loop count only the loop's own operations (otherwise the
-    // compiler merges in the prologue's shorter history and waits for all)
-    __builtin_amdgcn_s_waitcnt(0);
-    auto fwd_step = [&](int k, FwdSlot& S, auto pre) {
-        const int buf = k & 1;
-        __syncthreads();
-        const CTile<T> acc = product(buf, buf);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            yk[v] = mk<T>(acc.re[v], acc.im[v]);
-            Y[((long long)(k - 1) * LR + row[v]) * SRB + rloc] = yk[v];   // rows past L: zero
+    // IN_TWIST has no forward sweep: the maps' solutions start from columns of
+    // the diagonal blocks of H^-1 and only propagate towards block 1
+    if constexpr (INM != IN_TWIST) {
+        // forward sweep: y_k = S_k^-1 t_k; block k-1 (S_k^-1) sits in ring slot
+        // k & 1.  Slot of step k: the input g_{k+1}, the couplings of lines k, k+1
+        // and block k, all used at the end of step k.  The last step stashes block
+        // n-2 (already in its ring slot) and forms an input nobody reads: the
+        // backward pass finds block n-2 where it expects it and overwrites tb.
+        struct FwdSlot {
+            cplx<T> pf[FPT];
+            zd g[4];
+            zd sh, ism;
+        };
+        auto prefetch_f = [&](FwdSlot& S, int k) {
+            load_in(min(k + 1, n), S.g);
+            fetch_to(S.pf, k <= n - 1 ? k : max(n - 2, 0));
+            const int kc = min(k, n - 1);
+            S.sh = a.ax.sh[kc];
+            S.ism = a.ax.inv_sh2[kc];
+        };
+        FwdSlot fsl[2];
+        {
+            zd g0[4];
+            load_in(kstart, g0);
+            fetch_to(fsl[0].pf, kstart - 1);
+            const zd sh0 = a.ax.sh[kstart - 1], ism0 = a.ax.inv_sh2[kstart - 1];
+            stash_from(fsl[0].pf, kstart & 1);
+            put_input(kstart, g0, yk, sh0, ism0);
         }
-        stash_from(S.pf, (k + 1) & 1);                               // block k
-        put_input(k + 1, S.g, yk, S.sh, S.ism);
-        // the slot's next loads after its last use, so that they reuse its registers
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (decltype(pre)::value) prefetch_f(S, k + 2);
-    };
-    int kf = kstart;
-    for (; kf + 1 <= n; kf += 2) {
-        fwd_step(kf, fsl[0], std::true_type{});
-        fwd_step(kf + 1, fsl[1], std::true_type{});
+        prefetch_f(fsl[0], kstart);
+        prefetch_f(fsl[1], kstart + 1);
+        // one full wait before the loop: with nothing outstanding on entry, the
+        // waits inside the loop count only the loop's own operations (otherwise the
+        // compiler merges in the prologue's shorter history and waits for all)
+        __builtin_amdgcn_s_waitcnt(0);
+        auto fwd_step = [&](int k, FwdSlot& S, auto pre) {
+            const int buf = k & 1;
+            __syncthreads();
+            const CTile<T> acc = product(buf, buf);
+    #pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                yk[v] = mk<T>(acc.re[v], acc.im[v]);
+                Y[((long long)(k - 1) * LR + row[v]) * SRB + rloc] = yk[v];   // rows past L: zero
+            }
+            stash_from(S.pf, (k + 1) & 1);                               // block k
+            put_input(k + 1, S.g, yk, S.sh, S.ism);
+            // the slot's next loads after its last use, so that they reuse its registers
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (decltype(pre)::value) prefetch_f(S, k + 2);
+        };
+        int kf = kstart;
+        for (; kf + 1 <= n; kf += 2) {
+            fwd_step(kf, fsl[0], std::true_type{});
+            fwd_step(kf + 1, fsl[1], std::true_type{});
+        }
+        if (kf <= n) fwd_step(kf, fsl[0], std::false_type{});   // the last step: nothing to fetch
     }
-    if (kf <= n) fwd_step(kf, fsl[0], std::false_type{});   // the last step: nothing to fetch
 
     // backward sweep: v_n = y_n, v_k = y_k - S_k^-1 E_k v_{k+1}; block k-1 in
     // ring slot k & 1.  Slot of step k: y_k, the values its outputs add to and
     // the coupling of lines k-1, k (used in step k), and block k-2 (stashed at
     // the end of step k).  Step 1 stashes and forms data nobody reads.
     const int jout = (d.kind == ASP_SUB_R) ? (d.xe - d.lo) : (d.xs - d.lo);   // OUT_LINE row
+    // IN_TWIST: the solutions of this chunk start at blocks slot + 1 <= kmax
+    // and are zero above; kind 0 reads its map entries on line jout, kind 1
+    // (unit data on line jout) on the data line grow
+    const int kmax = (INM == IN_TWIST) ? min((ch + 1) * SRB, n) : n;
+    const bool tw1 = INM == IN_TWIST && a.twist_kind == 1;
+    const int jrow = tw1 ? grow : jout;
     const int omode = (d.kind == ASP_SUB_L) ? a.out_mode_L : a.out_mode;
     zd* const outp = (d.kind == ASP_SUB_L) ? a.out_L : a.out;
     const bool set_u = (omode == OUT_GRID_ADD_U) ||
@@ -516,7 +625,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // the other lines of X (the first and last layers are wider) are written
     // at every step.
     const bool bufo = a.buf_ok != 0;
-    const bool staging = INM != IN_UNIT && grid_out && bufo;
+    const bool staging = !NOSTAGE && grid_out && bufo;
     int xr[4];
     bool stgd[4];
 #pragma unroll
@@ -539,24 +648,43 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) av[v] = addp[v][(long long)(k - 1) * addk[v]];
     };
+    // IN_TWIST: y_k is the starting vector of the solution that starts at
+    // block k (slot = k - 1), zero otherwise: column grow (kind 0, times the
+    // unit data's coupling) or jout (kind 1) of G_k, the diagonal block of H^-1
+    const cplx<T>* const Gcol = reinterpret_cast<const cplx<T>*>(a.Tout) +
+                                (INM == IN_TWIST ? d.g_off : 0) + (tw1 ? LR : 0);
+    const cplx<T> cin_s = tw1 ? mk<T>(T(1), T(0))
+                              : ccast<T>(-(coupl * a.ax.inv_sh2[min(slot, n - 1)]));
     auto load_y = [&](int k, cplx<T> (&yv)[4]) {
-        const long long kk = max(k, kstart);     // blocks before kstart: y = 0
+        if constexpr (INM == IN_TWIST) {
+            const long long kk = max(k, 1);
+            const bool st = valid && slot == k - 1;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const cplx<T> y0 = Y[((kk - 1) * LR + row[v]) * SRB + rloc];
-            yv[v] = (k >= kstart) ? y0 : mk<T>(0, 0);
+            for (int v = 0; v < 4; ++v) {
+                const cplx<T> g0 = Gcol[(kk - 1) * 2 * LR + row[v]];
+                yv[v] = (st && rowv[v]) ? cin_s * g0 : mk<T>(0, 0);
+            }
+        } else {
+            const long long kk = max(k, kstart);     // blocks before kstart: y = 0
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const cplx<T> y0 = Y[((kk - 1) * LR + row[v]) * SRB + rloc];
+                yv[v] = (k >= kstart) ? y0 : mk<T>(0, 0);
+            }
         }
     };
     // the one entry of this lane on the OUT_LINE row, if any
     int jsel = -1;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-        if (rowv[e] && row[e] == jout) jsel = e;
+        if (rowv[e] && row[e] == jrow) jsel = e;
     // boundary maps in row tiles of 16: entry (row r, column c) at (r / 16) n 16 +
     // 16 c + r % 16, so that a sweep workgroup's 16 rows are one contiguous run
     cplx<T>* const Tbase = reinterpret_cast<cplx<T>*>(a.Tout) + d.tr_off;
     const bool tkeep = valid && jsel >= 0;
     auto tidx = [&](int k) { return ((long long)((k - 1) >> 4) * n + slot) * 16 + ((k - 1) & 15); };
+    // IN_TWIST kind 1: the entry (row slot, column k - 1)
+    auto tidx1 = [&](int k) { return ((long long)(slot >> 4) * n + (k - 1)) * 16 + (slot & 15); };
     bool keep[4];
     zd* gout[4];
 #pragma unroll
@@ -582,13 +710,26 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
             cplx<T> x = v[0];
 #pragma unroll
             for (int e = 1; e < 4; ++e) x = csel(jsel == e, v[e], x);
+            bool kp = tkeep;
+            long long ti = tidx(k);
+            if constexpr (INM == IN_TWIST) {
+                if (tw1) {
+                    // entry (slot, k - 1) below the diagonal, with the unit data's
+                    // coupling of column k - 1
+                    kp = kp && k - 1 < slot;
+                    ti = tidx1(k);
+                    x = ccast<T>(-(coupl * a.ax.inv_sh2[k - 1])) * x;
+                } else {
+                    kp = kp && k - 1 <= slot;   // on and above the diagonal
+                }
+            }
             if (bufo)
-                buf_store(rs, tkeep ? (unsigned)(tidx(k) * sizeof(cplx<T>)) : BUF_OOB, x);
+                buf_store(rs, kp ? (unsigned)(ti * sizeof(cplx<T>)) : BUF_OOB, x);
             else
-                *(tkeep ? Tbase + tidx(k) : sinkT) = x;
+                *(kp ? Tbase + ti : sinkT) = x;
             return;
         }
-        if constexpr (INM != IN_UNIT) {
+        if constexpr (!NOSTAGE) {
             if (staging) {
                 cplx<T>* sg = stg + ((((k - 1) / KO) & 1) * KO + (k - 1) % KO) * SROW * SRB;
 #pragma unroll
@@ -619,7 +760,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc(
         static_cast<void*>(set_u ? const_cast<zd*>(a.Ugrid) : outp), 0, 0x7fffffff, BUF_DW3);
     auto flush = [&](int g) {
-        if constexpr (INM != IN_UNIT) {
+        if constexpr (!NOSTAGE) {
             const cplx<T>* sg = stg + (g & 1) * KO * SROW * SRB + fx * SRB + frl;
             zd av[KO];
 #pragma unroll
@@ -657,14 +798,22 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     BwdSlot bsl[2];
     {
         zd an[4];
-        load_add(n, an);
-        const zd shn = a.ax.sh[max(n - 1, 0)];
-        emit(n, yk, an);
-        put_coupled(n - 1, yk, shn);    // n = 1: data nobody reads
+        load_add(kmax, an);
+        const zd shn = a.ax.sh[max(kmax - 1, 0)];
+        if constexpr (INM == IN_TWIST) {
+            // no forward sweep: the starting vectors at the top block, and block
+            // kmax - 2 (S_{kmax-1}^-1) into the ring slot the first step reads
+            load_y(kmax, yk);
+            cplx<T> pf0[FPT];
+            fetch_to(pf0, max(kmax - 2, 0));
+            stash_from(pf0, (kmax - 1) & 1);
+        }
+        emit(kmax, yk, an);
+        put_coupled(kmax - 1, yk, shn);    // kmax = 1: data nobody reads
     }
     cplx<T> (&vk)[4] = yk;
-    prefetch_b(bsl[0], n - 1);
-    prefetch_b(bsl[1], n - 2);
+    prefetch_b(bsl[0], kmax - 1);
+    prefetch_b(bsl[1], kmax - 2);
     __builtin_amdgcn_s_waitcnt(0);
     auto bwd_step = [&](int k, BwdSlot& S, auto pre) {
         const int buf = k & 1;
@@ -679,7 +828,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (decltype(pre)::value) prefetch_b(S, k - 2);
     };
-    int kb = n - 1;
+    int kb = kmax - 1;
     for (; kb - 1 >= 1; kb -= 2) {
         bwd_step(kb, bsl[0], std::true_type{});
         bwd_step(kb - 1, bsl[1], std::true_type{});
@@ -939,6 +1088,29 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename TS>
+static hipError_t launch_rgf_t(const asp_plan* P, const int* jobs, int njobs, hipStream_t st) {
+    AxisTables ax{P->d_axis, P->d_axis + (P->n + 1), P->d_axis + (2 * P->n + 1)};
+    const cplx<TS>* fac = reinterpret_cast<const cplx<TS>*>(P->d_fac);
+    cplx<TS>* tb = reinterpret_cast<cplx<TS>*>(P->d_T);
+    if (P->LR_RL == 16)
+        hipLaunchKernelGGL((rgf2d_kernel<TS, 16>), dim3(njobs), dim3(FB), 0, st, P->d_desc, jobs, ax,
+                           P->d_subtab, P->n, fac, tb);
+    else if (P->LR_RL == 32)
+        hipLaunchKernelGGL((rgf2d_kernel<TS, 32>), dim3(njobs), dim3(FB), 0, st, P->d_desc, jobs, ax,
+                           P->d_subtab, P->n, fac, tb);
+    else
+        hipLaunchKernelGGL((rgf2d_kernel<TS, 64>), dim3(njobs), dim3(FB), 0, st, P->d_desc, jobs, ax,
+                           P->d_subtab, P->n, fac, tb);
+    return hipGetLastError();
+}
+
+hipError_t launch_rgf2d(const asp_plan* P, int job0, int njobs, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    if (P->prec != ASP_PREC_FP64) return launch_rgf_t<float>(P, P->d_jobs + job0, njobs, st);
+    return launch_rgf_t<double>(P, P->d_jobs + job0, njobs, st);
+}
+
 // one kernel per (precision, row count, input mode): the M-solves, the R/L
 // solves and the transfer-map solves are separate kernels
 template <int LR, int INM>
@@ -958,6 +1130,7 @@ static hipError_t launch_solve_mode(const asp_plan* P, const SolveArgs& a, int b
     if (a.in_mode == IN_GRID) return launch_solve_lr<LR, IN_GRID>(P, a, blocks, st);
     if (a.in_mode == IN_BOUNDARY) return launch_solve_lr<LR, IN_BOUNDARY>(P, a, blocks, st);
     if (a.in_mode == IN_UNIT) return launch_solve_lr<LR, IN_UNIT>(P, a, blocks, st);
+    if (a.in_mode == IN_TWIST) return launch_solve_lr<LR, IN_TWIST>(P, a, blocks, st);
     return hipErrorInvalidValue;
 }
 
@@ -994,15 +1167,18 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
         const size_t esz = P->prec != ASP_PREC_FP64 ? sizeof(zf) : sizeof(zd);
         const long long lim = 1LL << 31;
         const long long grid_bytes = (long long)std::max(P->ws_rhs, L.nact) * P->N * (long long)sizeof(zd);
-        const long long line_bytes = (long long)P->n * P->n * (long long)esz;
-        a.buf_ok = (grid_bytes < lim && line_bytes < lim) ? 1 : 0;
+        const long long line_bytes = (long long)((P->n + 15) / 16 * 16) * P->n * (long long)esz;
+        // map outputs (OUT_LINE) address the map only
+        a.buf_ok = ((L.out_mode == OUT_LINE || grid_bytes < lim) && line_bytes < lim) ? 1 : 0;
     }
+    a.twist_kind = L.twist_kind;
     a.n = P->n;
     a.N = P->N;
     const int LR = L.rl ? P->LR_RL : P->LR_M;   // every job of one launch shares its row count
     const int srb = solve_rhs_per_block(LR);
     const long long B = (long long)L.njobs * ((L.nact + srb - 1) / srb);
-    if (B > P->y_waves) return hipErrorInvalidValue;   // scratch too small
+    // IN_TWIST uses no forward-result scratch
+    if (L.in_mode != IN_TWIST && B > P->y_waves) return hipErrorInvalidValue;
     const int blocks = (int)(((B + 7) / 8) * 8);
     if (LR == 16) return launch_solve_mode<16>(P, a, blocks, st);
     if (LR == 32) return launch_solve_mode<32>(P, a, blocks, st);

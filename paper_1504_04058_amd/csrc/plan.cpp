@@ -258,6 +258,7 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
         tab_off += sub_table_len(d.L);
         d.wrow = (d.kind == ASP_SUB_M) ? -1 : (int)s - P->m;
         d.tr_off = -1;
+        d.g_off = -1;
         d.vec_off = -1;
         if (dim == 2) {
             d.LR = (d.kind == ASP_SUB_M) ? P->LR_M : P->LR_RL;
@@ -294,6 +295,13 @@ extern "C" asp_status asp_setup(asp_plan** out, int dim, const double* c, double
         asp_status s_rec = rec_setup(P);
         if (s_rec != ASP_OK) return fail(s_rec, P->err.c_str());
     }
+    // after the maps: per map problem, columns grow and jout of the diagonal
+    // blocks of H^-1 (the boundary maps are built from them)
+    for (SubDesc& d : P->subs)
+        if (dim == 2 && d.tr_off >= 0) {
+            d.g_off = tr_off;
+            tr_off += (long long)n * 2 * d.LR;
+        }
     P->t_elems = tr_off;
     P->t_bytes = (size_t)tr_off * esz;
 

@@ -138,7 +138,10 @@ def test_arbitrary_layer_widths_match_oracle(dim, n, gamma, w):
                 group = ref["M"] if kind == "M" else ref["R"] + ref["L"]   # one row count per group
                 LR = 16 if max(s.L for s in group) <= 16 else 32
                 for s in ref[kind]:
-                    want += n * s.L * LR + (-(-n // 16) * 16 * n if kind != "M" and 1 < s.p < m else 0)
+                    # map problems: the map (rows padded to 16) and two columns
+                    # of each diagonal block of H^-1
+                    want += n * s.L * LR + ((-(-n // 16) * 16 + 2 * LR) * n
+                                            if kind != "M" and 1 < s.p < m else 0)
             assert info["factor_bytes"] == want * 8
     finally:
         asp.asp_destroy(plan)
@@ -195,7 +198,8 @@ def test_wide_2d_layers(L):
                     LR = max(16 if s.L <= 16 else 32 if s.L <= 32 else 64
                              for s in (ref["M"] if kind == "M" else ref["R"] + ref["L"]))
                     for s in ref[kind]:
-                        want += n * s.L * LR + (-(-n // 16) * 16 * n if kind != "M" and 1 < s.p < m else 0)
+                        want += n * s.L * LR + ((-(-n // 16) * 16 + 2 * LR) * n
+                                                if kind != "M" and 1 < s.p < m else 0)
                 esz = 16 if prec == asp.ASP_PREC_FP64 else 8
                 assert info["factor_bytes"] == want * esz
                 assert lay is not None
@@ -265,7 +269,8 @@ def test_empty_and_bad_solve_arguments_rejected(L):
                                                 (3, 63, 4, 8, 1), (3, 31, 4, 8, 0)])
 def test_planned_factor_bytes(dim, n, b, gamma, prec):
     """The planned factor size: 2D, n blocks of L x LR per problem (LR = 16 or
-    32 rows) plus an n x n boundary map for R_p, L_p with 1 < p < m; 3D with the
+    32 rows) plus, for R_p and L_p with 1 < p < m, an n x n boundary map and
+    two columns of each of the n diagonal blocks of H^-1; 3D with the
     block recurrence, n dense blocks of B x B with B = n L rounded up to a
     multiple of 64."""
     c = np.ones(n ** dim)
@@ -286,6 +291,7 @@ def test_planned_factor_bytes(dim, n, b, gamma, prec):
                 want += n * L * LR
                 if kind != "M" and 1 < s.p < m:
                     want += -(-n // 16) * 16 * n     # boundary map, rows padded to 16
+                    want += 2 * LR * n               # two columns of each diagonal block of H^-1
             else:
                 B = -(-n * L // 64) * 64
                 want += n * B * B
@@ -343,7 +349,8 @@ def test_bf16_split_precision_storage(L):
 
 def test_sequential_sweep_plan(L):
     """opts.sweep2d (Algorithm 2 as stated): the same partition and layer
-    factors as the default, without the n x n boundary maps; 3D plans ignore
+    factors as the default, without the n x n boundary maps and the columns of
+    the diagonal blocks of H^-1 they are built from; 3D plans ignore
     the field; unknown values are rejected."""
     n, b, gamma = 255, 4, 12
     c = np.ones(n * n)
@@ -354,7 +361,10 @@ def test_sequential_sweep_plan(L):
         a, s_ = asp.asp_info(maps), asp.asp_info(seq)
         m = a["m"]
         assert s_["m"] == m and s_["n_sub"] == a["n_sub"]
-        assert a["factor_bytes"] - s_["factor_bytes"] == 2 * (m - 2) * (-(-n // 16) * 16) * n * 8
+        subs = partition.subproblems(n, b, gamma)
+        lr_rl = 16 if max(sb.L for k in "RL" for sb in subs[k]) <= 16 else 32
+        assert a["factor_bytes"] - s_["factor_bytes"] == \
+            2 * (m - 2) * ((-(-n // 16) * 16) + 2 * lr_rl) * n * 8
     finally:
         asp.asp_destroy(maps)
         asp.asp_destroy(seq)
