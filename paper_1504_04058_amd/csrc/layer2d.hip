@@ -618,7 +618,9 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const bool set_u = (omode == OUT_GRID_ADD_U) ||
                        (omode == OUT_GRID_ACC && d.kind == ASP_SUB_L && d.p == 1);
     const bool add_out = !set_u && omode == OUT_GRID_ACC;
-    const bool grid_out = omode != OUT_LINE;
+    // map modes write the outgoing line only (known at compile time, so the
+    // grid-output state takes no registers)
+    const bool grid_out = NOSTAGE ? false : omode != OUT_LINE;
     const bool use_add = set_u || add_out;
     // Grid outputs on the first SROW lines of X are staged in LDS and written
     // KO steps at a time (whole 128-byte lines per right-hand side and line);
@@ -646,7 +648,8 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     }
     auto load_add = [&](int k, zd (&av)[4]) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) av[v] = addp[v][(long long)(k - 1) * addk[v]];
+        for (int v = 0; v < 4; ++v)
+            av[v] = NOSTAGE ? mk(0.0, 0.0) : addp[v][(long long)(k - 1) * addk[v]];
     };
     // IN_TWIST: y_k is the starting vector of the solution that starts at
     // block k (slot = k - 1), zero otherwise: column grow (kind 0, times the
