@@ -247,7 +247,6 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
             L.out_L = P->d_stage;
             L.W = P->d_W;
             L.w_rhs = w_rhs;
-            L.Ugrid = P->d_U;
             ASP_HIP(P, launch_solve2d(P, L, st));
             if (s < m - 1)
                 ASP_HIP(P, launch_sweep_hand(
@@ -296,7 +295,6 @@ asp_status apply_internal(asp_plan* P, const zd* r, zd* z, const int* act, int n
         L.out_L = P->d_stage;
         L.W = P->d_W;
         L.w_rhs = w_rhs;
-        L.Ugrid = P->d_U;
         solve_cost(P, L.job0, 2 * m - 2, nact, 2.0, &by, &fl);
         KTimer t(P, ASP_K_SOLVE_RL, by, fl);
         ASP_HIP(P, launch_solve2d(P, L, st));

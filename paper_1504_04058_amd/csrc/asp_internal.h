@@ -143,7 +143,7 @@ struct RecDesc {
 };
 
 // solve launch modes
-enum { IN_GRID = 0, IN_BOUNDARY = 1, IN_UNIT = 2, IN_TWIST = 3 };
+enum { IN_GRID = 0, IN_BOUNDARY = 1, IN_TWIST = 2 };
 enum { OUT_GRID_STORE = 0, OUT_GRID_ADD_U = 1, OUT_GRID_ACC = 2, OUT_LINE = 3 };
 
 // Per-problem sweep-axis tables, complex double, at tab_off:
@@ -337,11 +337,11 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st);
 // batched layer solves for the jobs d_jobs[job0 .. job0+njobs) (all M, or all
 // R/L: rl) and the right-hand sides act[0..nact) (NULL: 0..nact-1).
 //   in_mode   IN_GRID: data = r on X_p;  IN_BOUNDARY: boundary data from the
-//             W rows of the problems;  IN_UNIT: unit data at i1 = slot + 1
-//             (nact virtual right-hand sides, act ignored)
-//   out_mode  OUT_GRID_STORE: out = v on X_p;  OUT_GRID_ADD_U: out = U + v;
-//             OUT_GRID_ACC: out += v (out = U + v for L_1);  OUT_LINE: the
-//             outgoing boundary line into the problem's transfer map
+//             W rows of the problems;  IN_TWIST: the boundary-map solutions
+//             (nact = n virtual right-hand sides, act ignored)
+//   out_mode  OUT_GRID_STORE: out = v on X_p (IN_GRID, IN_BOUNDARY);
+//             OUT_LINE: the outgoing boundary line into the problem's
+//             boundary map (IN_TWIST); other modes are refused
 struct SolveLaunch {
     int job0 = 0, njobs = 0;
     bool rl = false;
@@ -352,7 +352,6 @@ struct SolveLaunch {
     const zd* W = nullptr;
     int w_rhs = 0;
     zd* out = nullptr;
-    const zd* Ugrid = nullptr;
     // a launch over R and L problems: the L problems write here instead (NULL: out)
     int out_mode_L = OUT_GRID_STORE;
     zd* out_L = nullptr;

@@ -35,12 +35,6 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
     __builtin_memcpy(&d, &v, sizeof(d));
     __builtin_amdgcn_raw_buffer_store_b128(d, r, off, 0, 0);
 }
-__device__ __forceinline__ zd buf_load_zd(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    const u32x4 d = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
-    zd v;
-    __builtin_memcpy(&v, &d, sizeof(v));
-    return v;
-}
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, zf v) {
     u32x2 d;
     __builtin_memcpy(&d, &v, sizeof(d));
@@ -333,8 +327,7 @@ struct SolveArgs {
     const zd* r;         // IN_GRID: grid vectors
     const zd* W;         // IN_BOUNDARY: boundary data per (problem, rhs)
     int w_rhs;           // right-hand-side stride of W (in n-vectors)
-    zd* out;             // OUT_GRID_*: grid vectors
-    const zd* Ugrid;     // OUT_GRID_ADD_U / ACC: u~_{p,p}
+    zd* out;             // OUT_GRID_STORE: grid vectors
     void* Tout;          // OUT_LINE: boundary-to-boundary maps
     void* y;
     long long y_per_wave;   // scratch entries per workgroup
@@ -352,9 +345,8 @@ constexpr int SB = 256;        // threads per solve workgroup: four wavefronts, 
 template <typename T, int LR, int INM, bool SPL = false>
 __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     static_assert(!SPL || std::is_same<T, float>::value, "the split products take FP32 operands");
-    static_assert(INM == IN_GRID || INM == IN_BOUNDARY || INM == IN_UNIT || INM == IN_TWIST,
-                  "input mode");
-    constexpr bool NOSTAGE = INM == IN_UNIT || INM == IN_TWIST;   // map outputs: no staging
+    static_assert(INM == IN_GRID || INM == IN_BOUNDARY || INM == IN_TWIST, "input mode");
+    constexpr bool NOSTAGE = INM == IN_TWIST;   // map outputs: no staging
     constexpr int SRB = 1024 / LR;          // right-hand sides per workgroup
     constexpr int NCT = SRB / 16;           // right-hand-side tiles
     static_assert((LR / 16) * NCT == 4, "four 16 x 16 tiles, one per wavefront");
@@ -471,9 +463,8 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     zd* const sink = a.sink + tid * 4;
     cplx<T>* const sinkT = reinterpret_cast<cplx<T>*>(sink);
 
-    // step data of this lane's rows (complex128): grid data (IN_GRID), the
-    // boundary data of its right-hand side (IN_BOUNDARY), or a dummy valid
-    // address (IN_UNIT, stride 0)
+    // step data of this lane's rows (complex128): grid data (IN_GRID) or the
+    // boundary data of its right-hand side (IN_BOUNDARY)
     // Rows whose data the step ignores read a fixed table entry instead (stride
     // 0), so that they cost no memory traffic.
     const zd* inp[4];
@@ -496,8 +487,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     // t_k = g_k - E_{k-1} y_{k-1} for this lane's entries into tb[k & 1]
     // (shm, ism: s at line k - 1/2 and 1 / s^2 at line k - 1 of axis 1).  The
     // data term is g_k (grid rows of X), g_k times the Dirichlet coupling
-    // (boundary data on the carrying row) or the coupling alone (unit data on
-    // the carrying row at step slot + 1), selected per lane; each input mode
+    // (boundary data on the carrying row), selected per lane; each input mode
     // forms only its own term (a select where the mode needs no product).
     bool carry[4];
 #pragma unroll
@@ -511,20 +501,14 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
             zd dv;
             if constexpr (INM == IN_GRID)
                 dv = csel(inX[v], g[v], mk(0.0, 0.0));
-            else if constexpr (INM == IN_BOUNDARY)
-                dv = csel(carry[v], g[v] * cin, mk(0.0, 0.0));
             else
-                dv = csel(carry[v] && slot == k - 1, cin, mk(0.0, 0.0));
+                dv = csel(carry[v], g[v] * cin, mk(0.0, 0.0));
             cplx<T> t = ccast<T>(dv);
             t = t - (shc * sinv2[v]) * y[v];              // y = 0 at the first step
             tb[k & 1][row[v]][rloc] = rowv[v] ? t : mk<T>(0, 0);
         }
     };
 
-    // unit data enters at i1 = slot + 1 >= ch SRB + 1: the forward results of
-    // the blocks before the chunk's first column are zero, so the forward pass
-    // starts there and the backward pass reads no results before it
-    const int kstart = (INM == IN_UNIT) ? min(ch * SRB + 1, n) : 1;
     // The loads of a step are issued two steps ahead into one of two register
     // slots; the step loops run in pairs so that the slots stay in fixed
     // registers (a register copy would wait for its load).
@@ -567,14 +551,14 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         FwdSlot fsl[2];
         {
             zd g0[4];
-            load_in(kstart, g0);
-            fetch_to(fsl[0].pf, kstart - 1);
-            const zd sh0 = a.ax.sh[kstart - 1], ism0 = a.ax.inv_sh2[kstart - 1];
-            stash_from(fsl[0].pf, kstart & 1);
-            put_input(kstart, g0, yk, sh0, ism0);
+            load_in(1, g0);
+            fetch_to(fsl[0].pf, 0);
+            const zd sh0 = a.ax.sh[0], ism0 = a.ax.inv_sh2[0];
+            stash_from(fsl[0].pf, 1);
+            put_input(1, g0, yk, sh0, ism0);
         }
-        prefetch_f(fsl[0], kstart);
-        prefetch_f(fsl[1], kstart + 1);
+        prefetch_f(fsl[0], 1);
+        prefetch_f(fsl[1], 2);
         // one full wait before the loop: with nothing outstanding on entry, the
         // waits inside the loop count only the loop's own operations (otherwise the
         // compiler merges in the prologue's shorter history and waits for all)
@@ -594,7 +578,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
             __builtin_amdgcn_sched_barrier(0);
             if constexpr (decltype(pre)::value) prefetch_f(S, k + 2);
         };
-        int kf = kstart;
+        int kf = 1;
         for (; kf + 1 <= n; kf += 2) {
             fwd_step(kf, fsl[0], std::true_type{});
             fwd_step(kf + 1, fsl[1], std::true_type{});
@@ -615,13 +599,9 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const int jrow = tw1 ? grow : jout;
     const int omode = (d.kind == ASP_SUB_L) ? a.out_mode_L : a.out_mode;
     zd* const outp = (d.kind == ASP_SUB_L) ? a.out_L : a.out;
-    const bool set_u = (omode == OUT_GRID_ADD_U) ||
-                       (omode == OUT_GRID_ACC && d.kind == ASP_SUB_L && d.p == 1);
-    const bool add_out = !set_u && omode == OUT_GRID_ACC;
     // map modes write the outgoing line only (known at compile time, so the
-    // grid-output state takes no registers)
+    // grid-output state takes no registers); the others store v on X_p
     const bool grid_out = NOSTAGE ? false : omode != OUT_LINE;
-    const bool use_add = set_u || add_out;
     // Grid outputs on the first SROW lines of X are staged in LDS and written
     // KO steps at a time (whole 128-byte lines per right-hand side and line);
     // the other lines of X (the first and last layers are wider) are written
@@ -635,22 +615,6 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         xr[v] = d.lo + row[v] - d.xs;
         stgd[v] = staging && inX[v] && xr[v] < SROW;
     }
-    // values the outputs add to, on the rows this lane writes at every step
-    // (others: a fixed table entry, stride 0)
-    const zd* addp[4];
-    int addk[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const bool used = use_add && grid_out && valid && inX[v] && !stgd[v];
-        addp[v] = used ? (set_u ? a.Ugrid : outp) + (long long)rid * N + (long long)n * (lcl[v] - 1)
-                       : a.subtab;
-        addk[v] = used ? 1 : 0;
-    }
-    auto load_add = [&](int k, zd (&av)[4]) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            av[v] = NOSTAGE ? mk(0.0, 0.0) : addp[v][(long long)(k - 1) * addk[v]];
-    };
     // IN_TWIST: y_k is the starting vector of the solution that starts at
     // block k (slot = k - 1), zero otherwise: column grow (kind 0, times the
     // unit data's coupling) or jout (kind 1) of G_k, the diagonal block of H^-1
@@ -668,11 +632,11 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
                 yv[v] = (st && rowv[v]) ? cin_s * g0 : mk<T>(0, 0);
             }
         } else {
-            const long long kk = max(k, kstart);     // blocks before kstart: y = 0
+            const long long kk = max(k, 1);     // blocks before the first: y = 0
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const cplx<T> y0 = Y[((kk - 1) * LR + row[v]) * SRB + rloc];
-                yv[v] = (k >= kstart) ? y0 : mk<T>(0, 0);
+                yv[v] = (k >= 1) ? y0 : mk<T>(0, 0);
             }
         }
     };
@@ -708,7 +672,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
                                   ? (unsigned)(((long long)rid * N + (long long)n * (lcl[e] - 1)) * 16)
                                   : BUF_OOB)
                            : BUF_OOB;   // OUT_LINE offsets are formed per step
-    auto emit = [&](int k, const cplx<T> (&v)[4], const zd (&av)[4]) {
+    auto emit = [&](int k, const cplx<T> (&v)[4]) {
         if (!grid_out) {
             cplx<T> x = v[0];
 #pragma unroll
@@ -742,7 +706,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const zd x = use_add ? ccast<double>(v[e]) + av[e] : ccast<double>(v[e]);
+            const zd x = ccast<double>(v[e]);
             if (bufo)
                 buf_store(rs, boff[e] + (unsigned)(k - 1) * 16u, x);
             else
@@ -750,9 +714,8 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         }
     };
     // write out the staged steps g KO + 1 .. g KO + KO: thread (line, rhs) of
-    // the staged block writes KO consecutive entries (the values its outputs
-    // add to read the same way); lanes past the block pass offsets past the
-    // range
+    // the staged block writes KO consecutive entries; lanes past the block
+    // pass offsets past the range
     const int fx = min(tid / SRB, SROW - 1), frl = tid % SRB;
     const int fslot = ch * SRB + frl;
     const int nxs = min(d.xe - d.xs + 1, SROW);
@@ -760,23 +723,14 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     const int frid = fvalid ? (a.act ? a.act[fslot] : fslot) : 0;
     const unsigned fbase =
         fvalid ? (unsigned)(((long long)frid * N + (long long)n * (d.xs + fx - 1)) * 16) : BUF_OOB;
-    const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc(
-        static_cast<void*>(set_u ? const_cast<zd*>(a.Ugrid) : outp), 0, 0x7fffffff, BUF_DW3);
     auto flush = [&](int g) {
         if constexpr (!NOSTAGE) {
             const cplx<T>* sg = stg + (g & 1) * KO * SROW * SRB + fx * SRB + frl;
-            zd av[KO];
 #pragma unroll
             for (int q = 0; q < KO; ++q) {
                 const int st = g * KO + 1 + q;
                 const unsigned off = (st <= n) ? fbase + (unsigned)(st - 1) * 16u : BUF_OOB;
-                av[q] = use_add ? buf_load_zd(rsa, off) : mk(0.0, 0.0);
-            }
-#pragma unroll
-            for (int q = 0; q < KO; ++q) {
-                const int st = g * KO + 1 + q;
-                const unsigned off = (st <= n) ? fbase + (unsigned)(st - 1) * 16u : BUF_OOB;
-                buf_store(rs, off, ccast<double>(sg[q * SROW * SRB]) + av[q]);
+                buf_store(rs, off, ccast<double>(sg[q * SROW * SRB]));
             }
         }
     };
@@ -789,19 +743,15 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     struct BwdSlot {
         cplx<T> pf[FPT];
         cplx<T> y[4];
-        zd av[4];
         zd sh;
     };
     auto prefetch_b = [&](BwdSlot& S, int k) {
         load_y(k, S.y);
-        load_add(max(k, 1), S.av);
         fetch_to(S.pf, max(k - 2, 0));
         S.sh = a.ax.sh[max(k - 1, 0)];
     };
     BwdSlot bsl[2];
     {
-        zd an[4];
-        load_add(kmax, an);
         const zd shn = a.ax.sh[max(kmax - 1, 0)];
         if constexpr (INM == IN_TWIST) {
             // no forward sweep: the starting vectors at the top block, and block
@@ -811,7 +761,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
             fetch_to(pf0, max(kmax - 2, 0));
             stash_from(pf0, (kmax - 1) & 1);
         }
-        emit(kmax, yk, an);
+        emit(kmax, yk);
         put_coupled(kmax - 1, yk, shn);    // kmax = 1: data nobody reads
     }
     cplx<T> (&vk)[4] = yk;
@@ -825,7 +775,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
         const CTile<T> acc = product(buf, buf);
 #pragma unroll
         for (int e = 0; e < 4; ++e) vk[e] = S.y[e] - mk<T>(acc.re[e], acc.im[e]);
-        emit(k, vk, S.av);
+        emit(k, vk);
         stash_from(S.pf, (k - 1) & 1);                               // block k-2
         put_coupled(k - 1, vk, S.sh);
         __builtin_amdgcn_sched_barrier(0);
@@ -1132,7 +1082,6 @@ static hipError_t launch_solve_mode(const asp_plan* P, const SolveArgs& a, int b
                                     hipStream_t st) {
     if (a.in_mode == IN_GRID) return launch_solve_lr<LR, IN_GRID>(P, a, blocks, st);
     if (a.in_mode == IN_BOUNDARY) return launch_solve_lr<LR, IN_BOUNDARY>(P, a, blocks, st);
-    if (a.in_mode == IN_UNIT) return launch_solve_lr<LR, IN_UNIT>(P, a, blocks, st);
     if (a.in_mode == IN_TWIST) return launch_solve_lr<LR, IN_TWIST>(P, a, blocks, st);
     return hipErrorInvalidValue;
 }
@@ -1144,6 +1093,11 @@ long long solve_scratch_per_block(const asp_plan* P) { return (long long)P->n * 
 
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st) {
     if (L.njobs <= 0 || L.nact <= 0) return hipSuccess;
+    // the map solves write the outgoing line, the others store v on X_p
+    const bool twist = L.in_mode == IN_TWIST;
+    if (twist ? L.out_mode != OUT_LINE
+              : (L.out_mode != OUT_GRID_STORE || (L.out_L && L.out_mode_L != OUT_GRID_STORE)))
+        return hipErrorInvalidValue;
     SolveArgs a;
     a.desc = P->d_desc;
     a.jobs = P->d_jobs + L.job0;
@@ -1161,7 +1115,6 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     a.W = L.W;
     a.w_rhs = L.w_rhs;
     a.out = L.out;
-    a.Ugrid = L.Ugrid;
     a.Tout = P->d_T;
     a.y = P->d_y;
     a.y_per_wave = solve_scratch_per_block(P);
@@ -1181,7 +1134,7 @@ hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t s
     const int srb = solve_rhs_per_block(LR);
     const long long B = (long long)L.njobs * ((L.nact + srb - 1) / srb);
     // IN_TWIST uses no forward-result scratch
-    if (L.in_mode != IN_TWIST && B > P->y_waves) return hipErrorInvalidValue;
+    if (!twist && B > P->y_waves) return hipErrorInvalidValue;
     const int blocks = (int)(((B + 7) / 8) * 8);
     if (LR == 16) return launch_solve_mode<16>(P, a, blocks, st);
     if (LR == 32) return launch_solve_mode<32>(P, a, blocks, st);
