@@ -361,13 +361,25 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     constexpr int SROW = 4;
     __shared__ cplx<T> stg[NOSTAGE ? 1 : 2 * KO * SROW * SRB];
 
-    // XCD-aware order: the chunks of one problem are consecutive work items
     const int nchunk = (a.nact + SRB - 1) / SRB;
     const int B = a.njobs * nchunk;
-    const int per = (B + 7) / 8;
-    const int w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-    if (w >= B) return;
-    const int jl = w / nchunk, ch = w % nchunk;
+    int w, jl, ch;
+    if constexpr (INM == IN_TWIST) {
+        // chunk ch of a map problem is a chain of min((ch + 1) SRB, n) steps:
+        // the longest chains of every problem first, in dispatch order (and so
+        // spread over the XCDs), so that no long chain starts near the end
+        w = (int)blockIdx.x;
+        if (w >= B) return;
+        ch = nchunk - 1 - w / a.njobs;
+        jl = w % a.njobs;
+    } else {
+        // XCD-aware order: the chunks of one problem are consecutive work items
+        const int per = (B + 7) / 8;
+        w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+        if (w >= B) return;
+        jl = w / nchunk;
+        ch = w % nchunk;
+    }
     const SubDesc d = a.desc[a.jobs[jl]];
     const int L = d.L, n = a.n;
     const long long N = a.N;
