@@ -324,20 +324,29 @@ static asp_status compute_transfer(asp_plan* P) {
     const int m = P->m;
     if (m < 3) return ASP_OK;
     const double esz = elem_bytes(P);
+    const int nj = m - 2;
+    // the diagonal blocks of H^-1 of both sweeps' map problems in one launch
+    {
+        double fb = 0, fl = 0;
+        for (int side = 0; side < 2; ++side) {
+            const int first = side == 0 ? P->idx_R(2) : P->idx_L(2);
+            for (int s = first; s < first + nj; ++s) {
+                const SubDesc& d = P->subs[s];
+                fb += factor_bytes_of(P, d);
+                fl += (double)P->n * 2.0 * d.L * d.L * d.L * 8.0;   // two L^3 complex products per block
+            }
+        }
+        KTimer t(P, ASP_K_TRANSFER, fb + 2.0 * nj * P->n * 2 * P->LR_RL * esz, fl);
+        ASP_HIP(P, launch_rgf2d(P, P->idx_R(2), P->idx_L(2), nj, P->stream));
+        t.end();
+    }
     for (int side = 0; side < 2; ++side) {
         const int first = side == 0 ? P->idx_R(2) : P->idx_L(2);
-        const int nj = m - 2;
-        double fb = 0, fl = 0, L2 = 0;
+        double fb = 0, L2 = 0;
         for (int s = first; s < first + nj; ++s) {
             const SubDesc& d = P->subs[s];
             fb += factor_bytes_of(P, d);
-            fl += (double)P->n * 2.0 * d.L * d.L * d.L * 8.0;   // two L^3 complex products per block
             L2 += (double)d.L * d.L;
-        }
-        {
-            KTimer t(P, ASP_K_TRANSFER, fb + (double)nj * P->n * 2 * P->LR_RL * esz, fl);
-            ASP_HIP(P, launch_rgf2d(P, first, nj, P->stream));
-            t.end();
         }
         for (int kind = 0; kind < 2; ++kind) {
             SolveLaunch L;

@@ -362,8 +362,9 @@ struct SolveLaunch {
 };
 hipError_t launch_solve2d(const asp_plan* P, const SolveLaunch& L, hipStream_t st);
 // columns grow and jout of the diagonal blocks of H^-1 of the map problems
-// jobs[job0 .. job0 + njobs) (R_p or L_p with 1 < p < m, after asp_factor)
-hipError_t launch_rgf2d(const asp_plan* P, int job0, int njobs, hipStream_t st);
+// jobs[job0 .. job0 + njobs) and, if job1 >= 0, jobs[job1 .. job1 + njobs)
+// in the same launch (R_p or L_p with 1 < p < m, after asp_factor)
+hipError_t launch_rgf2d(const asp_plan* P, int job0, int job1, int njobs, hipStream_t st);
 // device memory of the library (devmem.cpp): blocks may be cached and handed
 // to another plan, so a block is freed only once no work is pending on it
 // (after a synchronization of the owning plan's stream)

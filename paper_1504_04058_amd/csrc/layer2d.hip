@@ -60,7 +60,7 @@ __device__ __forceinline__ void factor2d_body(const SubDesc& d, AxisTables ax,
                                               const zd* __restrict__ subtab,
                                               const double* __restrict__ ksq, int n,
                                               cplx<TS>* __restrict__ fac, int* __restrict__ flag,
-                                              zd (&rowbuf)[2][ML], zd (&colbuf)[2][ML],
+                                              zd (&rowbuf)[2][ML + 1], zd (&colbuf)[2][ML],
                                               zd (&srow)[ML]) {
     constexpr int G = FB / LR, RPL = LR / G;
     const int L = d.L;
@@ -136,24 +136,31 @@ __device__ __forceinline__ void factor2d_body(const SubDesc& d, AxisTables ax,
                 if (kk >= L) continue;
                 const int b = pc & 1;
                 ++pc;
-                if (g == gb) rowbuf[b][j] = v[pq];
-                if (j == kk)
+                const bool jp = j == kk, gp = g == gb;
+                if (gp) rowbuf[b][j] = v[pq];
+                if (jp)
 #pragma unroll
                     for (int q = 0; q < RPL; ++q) colbuf[b][g * RPL + q] = v[q];
+                // the pivot's owner checks it and publishes 1 / p
+                if (jp && gp) {
+                    const zd p = v[pq];
+                    const double pa = abs2(p);
+                    if (!(pa > 1e-300) || !isfinite(pa)) bad = true;
+                    rowbuf[b][ML] = cinv(p);
+                }
                 __syncthreads();
-                const zd p = colbuf[b][kk];
-                const double pa = abs2(p);
-                if (!(pa > 1e-300) || !isfinite(pa)) bad = true;
-                const zd pinv = cinv(p);
-                const zd rp = rowbuf[b][j] * pinv;            // A[kk][j] / p
-                const bool jp = j == kk, gp = g == gb;
+                const zd pinv = rowbuf[b][ML];
+                // A[kk][j] / p; the pivot column is scaled by 1 / p instead
+                const zd rp = csel(jp, pinv, rowbuf[b][j] * pinv);
+                // A[i][j] - A[i][kk] A[kk][j] / p off the pivot row and column,
+                // -A[i][kk] / p on the pivot column, A[kk][j] / p on the pivot
+                // row and 1 / p at the pivot
 #pragma unroll
                 for (int q = 0; q < RPL; ++q) {
                     const zd ci = colbuf[b][g * RPL + q];     // A[i][kk]
-                    zd x = v[q] - ci * rp;
+                    zd x = csel(jp, mk(0.0, 0.0), v[q]) - ci * rp;
                     if (q == pq) x = csel(gp, rp, x);
-                    const zd xc = csel(q == pq && gp, pinv, -(ci * pinv));
-                    v[q] = csel(jp, xc, x);
+                    v[q] = x;
                 }
             }
         }
@@ -179,7 +186,7 @@ __global__ __launch_bounds__(FB) void factor2d_kernel(const SubDesc* __restrict_
                                                      cplx<TS>* __restrict__ fac,
                                                      int* __restrict__ flag) {
     static_assert(ML == 32 || ML == MAXL, "row counts");
-    __shared__ zd rowbuf[2][ML];
+    __shared__ zd rowbuf[2][ML + 1];   // pivot row; [ML]: the pivot's reciprocal
     __shared__ zd colbuf[2][ML];
     __shared__ zd srow[ML];
     const SubDesc d = desc[blockIdx.x];
@@ -277,13 +284,15 @@ __device__ __forceinline__ void rgf2d_body(const SubDesc& d, AxisTables ax, cons
 
 template <typename TS, int LR>
 __global__ __launch_bounds__(FB) void rgf2d_kernel(const SubDesc* __restrict__ desc,
-                                                  const int* __restrict__ jobs, AxisTables ax,
+                                                  const int* __restrict__ jobs0,
+                                                  const int* __restrict__ jobs1, AxisTables ax,
                                                   const zd* __restrict__ subtab, int n,
                                                   const cplx<TS>* __restrict__ fac,
                                                   cplx<TS>* __restrict__ tbuf) {
     __shared__ zd A[LR][LR + 1];
     __shared__ zd Bm[LR][LR + 1];
-    const SubDesc d = desc[jobs[blockIdx.x]];
+    // blockIdx.y picks one of two job lists (the map problems of the two sweeps)
+    const SubDesc d = desc[(blockIdx.y ? jobs1 : jobs0)[blockIdx.x]];
     rgf2d_body<TS, LR>(d, ax, subtab, n, fac, tbuf, A, Bm);
 }
 
@@ -1054,26 +1063,31 @@ hipError_t launch_factor2d(const asp_plan* P, hipStream_t st) {
 }
 
 template <typename TS>
-static hipError_t launch_rgf_t(const asp_plan* P, const int* jobs, int njobs, hipStream_t st) {
+static hipError_t launch_rgf_t(const asp_plan* P, const int* jobs0, const int* jobs1, int nlists,
+                               int njobs, hipStream_t st) {
     AxisTables ax{P->d_axis, P->d_axis + (P->n + 1), P->d_axis + (2 * P->n + 1)};
     const cplx<TS>* fac = reinterpret_cast<const cplx<TS>*>(P->d_fac);
     cplx<TS>* tb = reinterpret_cast<cplx<TS>*>(P->d_T);
+    const dim3 grid(njobs, nlists);
     if (P->LR_RL == 16)
-        hipLaunchKernelGGL((rgf2d_kernel<TS, 16>), dim3(njobs), dim3(FB), 0, st, P->d_desc, jobs, ax,
+        hipLaunchKernelGGL((rgf2d_kernel<TS, 16>), grid, dim3(FB), 0, st, P->d_desc, jobs0, jobs1, ax,
                            P->d_subtab, P->n, fac, tb);
     else if (P->LR_RL == 32)
-        hipLaunchKernelGGL((rgf2d_kernel<TS, 32>), dim3(njobs), dim3(FB), 0, st, P->d_desc, jobs, ax,
+        hipLaunchKernelGGL((rgf2d_kernel<TS, 32>), grid, dim3(FB), 0, st, P->d_desc, jobs0, jobs1, ax,
                            P->d_subtab, P->n, fac, tb);
     else
-        hipLaunchKernelGGL((rgf2d_kernel<TS, 64>), dim3(njobs), dim3(FB), 0, st, P->d_desc, jobs, ax,
+        hipLaunchKernelGGL((rgf2d_kernel<TS, 64>), grid, dim3(FB), 0, st, P->d_desc, jobs0, jobs1, ax,
                            P->d_subtab, P->n, fac, tb);
     return hipGetLastError();
 }
 
-hipError_t launch_rgf2d(const asp_plan* P, int job0, int njobs, hipStream_t st) {
+hipError_t launch_rgf2d(const asp_plan* P, int job0, int job1, int njobs, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
-    if (P->prec != ASP_PREC_FP64) return launch_rgf_t<float>(P, P->d_jobs + job0, njobs, st);
-    return launch_rgf_t<double>(P, P->d_jobs + job0, njobs, st);
+    const int* j0 = P->d_jobs + job0;
+    const int* j1 = job1 >= 0 ? P->d_jobs + job1 : j0;
+    const int nl = job1 >= 0 ? 2 : 1;
+    if (P->prec != ASP_PREC_FP64) return launch_rgf_t<float>(P, j0, j1, nl, njobs, st);
+    return launch_rgf_t<double>(P, j0, j1, nl, njobs, st);
 }
 
 // one kernel per (precision, row count, input mode): the M-solves, the R/L
