@@ -171,6 +171,25 @@ def test_single_and_two_layers():
             assert rel(z, direct.solve(P.A(), r)) < 1e-10
 
 
+@pytest.mark.parametrize("prec,tol", [(asp.ASP_PREC_FP64, 1e-11), (asp.ASP_PREC_FP32, 8e-6)])
+def test_three_and_four_layers(prec, tol):
+    """m = 3 and 4: one and two boundary-map problems per sweep (the
+    smallest launches of the diagonal-block recurrence and of the map
+    solves), against the oracle."""
+    for n, gamma, b, m in [(25, 5, 8, 3), (33, 5, 8, 4)]:
+        P = _problem(n, gamma, b)
+        M = Preconditioner(P)
+        assert M.m == m
+        r = np.random.default_rng(1).standard_normal((3, P.N)) + 1j * np.random.default_rng(2).standard_normal((3, P.N))
+        with _plan(P, prec) as plan:
+            plan.factor()
+            z = host(plan.apply(dev(r)))
+        for k in range(3):
+            e = rel(z[k], M.apply(r[k]))
+            print(f"2D apply m={m} n={n} prec={prec}: rel err {e:.2e}", flush=True)
+            assert e < tol
+
+
 def _oracle_solve(P, b, tol, restart):
     A = P.A()
     M = Preconditioner(P)
