@@ -136,10 +136,11 @@ typedef struct {
                                  buffers, which stay between factorizations */
     int factored;             /* nonzero once asp_factor has succeeded */
     size_t factor_work_bytes; /* device bytes of the work buffers asp_factor allocates besides
-                                 the factors: the forward-substitution scratch of the 2D
-                                 boundary-map solves, the 3D level, panel and pivot buffers.
-                                 They stay allocated (and are counted in workspace_bytes)
-                                 until asp_release_workspace; known right after asp_setup */
+                                 the factors: the 3D level, panel and pivot buffers (2D
+                                 plans need none: the boundary maps are built without
+                                 scratch).  They stay allocated (and are counted in
+                                 workspace_bytes) until asp_release_workspace; known right
+                                 after asp_setup */
 } asp_plan_info;
 
 /* Fill *opts with the defaults (C = 25, FP64, null stream, device plan). */
