@@ -159,24 +159,20 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
         if (act.empty()) break;
         if ((s = upload_act(act)) != ASP_OK) return s;
         const int na = (int)act.size();
-        if (first) {
-            for (int r : act) hsmall[(size_t)nrhs * SMALL + r] = mk(1.0, 0.0);
-            ASP_HIP(P, hipMemcpyAsync(scal, hsmall.data() + (size_t)nrhs * SMALL, nrhs * sizeof(zd),
-                                      hipMemcpyHostToDevice, st));
-            ASP_TIMED(P, ASP_K_KRYLOV, 32.0 * na * N, 0.0,
-                      launch_scale_vec(b, V, scal, N, P->d_act, na, st));  // V_0 = b (x0 = 0)
-            if ((s = norms(V, na)) != ASP_OK) return s;
-        } else {
+        // the first cycle's residual is b itself (x0 = 0): its norm is |b|,
+        // already known, and v_0 = b / |b| is formed straight from b below
+        const bool from_b = first;
+        if (!from_b) {
             int nb = 0;
             ASP_TIMED(P, ASP_K_STENCIL, 64.0 * na * N + 8.0 * N, 48.0 * na * N,
                       launch_residual(P, b, x, V, P->d_act, na, P->d_red, &nb, st));
             ASP_HIP(P, launch_reduce(P->d_red, nb, 1, P->d_act, na, small + OFF_NRM, SMALL, st));
+            if ((s = download_small()) != ASP_OK) return s;
         }
         first = false;
-        if ((s = download_small()) != ASP_OK) return s;
         std::vector<int> cyc;
         for (int r : act) {
-            const double beta = std::sqrt(hsmall[(size_t)r * SMALL + OFF_NRM].x);
+            const double beta = from_b ? R[r].bnorm : std::sqrt(hsmall[(size_t)r * SMALL + OFF_NRM].x);
             R[r].relres = beta / R[r].bnorm;
             if (!std::isfinite(beta)) return plan_fail(P, ASP_ERR_BREAKDOWN, "asp_gmres: non-finite residual");
             if (R[r].relres <= tol || R[r].iters >= maxit) {
@@ -197,7 +193,7 @@ extern "C" asp_status asp_gmres(asp_plan* P, const void* f_, void* u_, int nrhs,
         ASP_HIP(P, hipMemcpyAsync(scal, hsmall.data() + (size_t)nrhs * SMALL, nrhs * sizeof(zd),
                                   hipMemcpyHostToDevice, st));
         ASP_TIMED(P, ASP_K_KRYLOV, 32.0 * cyc.size() * N, 6.0 * cyc.size() * N,
-                  launch_scale_vec(V, V, scal, N, P->d_act, (int)cyc.size(), st));
+                  launch_scale_vec(from_b ? b : V, V, scal, N, P->d_act, (int)cyc.size(), st));
 
         std::vector<int> inner = cyc;
         for (int j = 0; j < restart && !inner.empty(); ++j) {
