@@ -366,7 +366,7 @@ __global__ __launch_bounds__(SB) void solve2d_kernel(SolveArgs a) {
     __shared__ cplx<T> Fs[2][FMAX];
     __shared__ cplx<T> tb[2][LR][TBS];      // step vectors [row][rhs]
     // grid outputs of the first SROW lines of X for KO steps, by group parity
-    constexpr int KO = sizeof(T) == 4 ? 8 : 4;
+    constexpr int KO = sizeof(T) == 4 ? 8 : 2;
     constexpr int SROW = 4;
     __shared__ cplx<T> stg[NOSTAGE ? 1 : 2 * KO * SROW * SRB];
 
