@@ -133,8 +133,10 @@ __global__ __launch_bounds__(BS) void multidot_kernel(const zd* __restrict__ V, 
             if (k < ni) acc[k] = cfma_conj(V[(long long)(i0 + k) * vstride + (long long)rhs * N + idx], wv, acc[k]);
     }
     block_reduce<CHUNK>(acc, sh);
+    // the sums sit in sh[k BS] for every thread (read from LDS: indexing the
+    // register array by thread would put it in scratch memory)
     if (threadIdx.x < CHUNK)
-        partial[((long long)rhs * nblk + blockIdx.x) * CHUNK + threadIdx.x] = acc[threadIdx.x];
+        partial[((long long)rhs * nblk + blockIdx.x) * CHUNK + threadIdx.x] = sh[threadIdx.x * BS];
 }
 
 __global__ __launch_bounds__(64) void reduce_kernel(const zd* __restrict__ partial, int nblk,

@@ -48,6 +48,31 @@ __device__ __forceinline__ void load_tile(cplx<T>* S, const cplx<T>* A, long lon
     }
 }
 
+// half tiles for the trailing update: S[r][k] = A(r0 + r, c0 + k), 64 rows by
+// 32 columns with row stride KLD, and S[k][c] = A(r0 + k, c0 + c), 32 rows by
+// 64 columns with row stride LDT (column-major sources, leading dimension ld)
+constexpr int KLD = TB / 2 + 1;
+template <typename T>
+__device__ __forceinline__ void load_half_cols(cplx<T>* S, const cplx<T>* A, long long ld, int r0,
+                                               int c0) {
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+#pragma unroll 4
+    for (int e = 0; e < 8; ++e) {
+        const int c = cg + 4 * e;
+        S[r * KLD + c] = A[(long long)(c0 + c) * ld + r0 + r];
+    }
+}
+template <typename T>
+__device__ __forceinline__ void load_half_rows(cplx<T>* S, const cplx<T>* A, long long ld, int r0,
+                                               int c0) {
+    const int r = threadIdx.x & 31, cg = threadIdx.x >> 5;
+#pragma unroll 4
+    for (int e = 0; e < 8; ++e) {
+        const int c = cg + 8 * e;
+        S[r * LDT + c] = A[(long long)(c0 + c) * ld + r0 + r];
+    }
+}
+
 // C = P Q for tiles in LDS (P[r][k], Q[k][c]).  Wave w computes rows
 // 32 (w / 2) .. + 32 and columns 32 (w % 2) .. + 32 as four transposed 16 x 16
 // blocks: acc[a][b], lane l, element v is C(R0 + 16 b + l % 16, C0 + 16 a +
@@ -56,7 +81,9 @@ __device__ __forceinline__ void load_tile(cplx<T>* S, const cplx<T>* A, long lon
 // p1 = 0, p2 = im, p3 = -re, then p1 += (q_r + q_i) p_r, p2 += q_r (p_i - p_r),
 // p3 += q_i (p_r + p_i), and re = p1 - p3, im = p1 + p2 (three real products
 // per complex one instead of four).
-template <typename T>
+// KL: the k extent (64, or 32 for half tiles); PLD, QLD: the LDS row strides
+// of P and Q.
+template <typename T, int KL = TB, int PLD = LDT, int QLD = LDT>
 __device__ __forceinline__ void tile_product(const cplx<T>* P, const cplx<T>* Q,
                                              CTile<T> acc[2][2]) {
     const int l = lane_id(), w = wave_id();
@@ -75,13 +102,13 @@ __device__ __forceinline__ void tile_product(const cplx<T>* P, const cplx<T>* Q,
                     p3[a][b][v] = -acc[a][b].re[v];
                 }
 #pragma unroll 2
-        for (int k0 = 0; k0 < TB; k0 += 4) {
+        for (int k0 = 0; k0 < KL; k0 += 4) {
             const int kq = k0 + lk;
             zf qa[2], pb[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) qa[a] = Q[kq * LDT + C0 + 16 * a + li];
+            for (int a = 0; a < 2; ++a) qa[a] = Q[kq * QLD + C0 + 16 * a + li];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) pb[b] = P[(R0 + 16 * b + li) * LDT + kq];
+            for (int b = 0; b < 2; ++b) pb[b] = P[(R0 + 16 * b + li) * PLD + kq];
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 const float qs = qa[a].x + qa[a].y;
@@ -104,13 +131,13 @@ __device__ __forceinline__ void tile_product(const cplx<T>* P, const cplx<T>* Q,
                 }
     } else {
 #pragma unroll 2
-        for (int k0 = 0; k0 < TB; k0 += 4) {
+        for (int k0 = 0; k0 < KL; k0 += 4) {
             const int kq = k0 + lk;
             cplx<T> qa[2], pb[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) qa[a] = Q[kq * LDT + C0 + 16 * a + li];
+            for (int a = 0; a < 2; ++a) qa[a] = Q[kq * QLD + C0 + 16 * a + li];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) pb[b] = P[(R0 + 16 * b + li) * LDT + kq];
+            for (int b = 0; b < 2; ++b) pb[b] = P[(R0 + 16 * b + li) * PLD + kq];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -374,10 +401,39 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
 
 // Trailing update of panel jp: A[I,C] += A[I,J] R[J,C] for I, C outside the
 // panel; the pivot tile becomes D^-1.
+// acc += P Q for the trailing update, P = Pm(pr0.., pc0..) (64 x 64, leading
+// dimension pld) and Q = Qm(0.., qc0..) (leading dimension TB): whole tiles, or
+// (HALVES) the k range in two halves of 32 through half-size LDS copies
+template <typename T, bool HALVES>
+__device__ __forceinline__ void gj_update_product(cplx<T>* sP, cplx<T>* sQ, const cplx<T>* Pm, long long pld,
+                                                  int pr0, int pc0, const cplx<T>* Qm, int qc0,
+                                                  CTile<T> (&acc)[2][2]) {
+    if constexpr (HALVES) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();   // the previous half's reads are done
+            load_half_cols(sP, Pm, pld, pr0, pc0 + (TB / 2) * h);
+            load_half_rows(sQ, Qm, TB, (TB / 2) * h, qc0);
+            __syncthreads();
+            tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
+        }
+    } else {
+        __syncthreads();   // the previous product's reads are done
+        load_tile(sP, Pm, pld, pr0, pc0);
+        load_tile(sQ, Qm, TB, 0, qc0);
+        __syncthreads();
+        tile_product(sP, sQ, acc);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
-    __shared__ cplx<T> sP[TB * LDT];
-    __shared__ cplx<T> sQ[TB * LDT];
+    // FP64: the products run over the panel in two halves of 32, so that the
+    // LDS copies take half a tile each and two workgroups share a CU (whole
+    // tiles would take 133 KB); FP32 keeps whole tiles (66.5 KB)
+    constexpr bool HALVES = sizeof(T) == 8;
+    __shared__ cplx<T> sP[HALVES ? TB * KLD : TB * LDT];
+    __shared__ cplx<T> sQ[HALVES ? (TB / 2) * LDT : TB * LDT];
     const int js = blockIdx.y;
     const GjMat gm = gj_mat(a, js);
     const int Bp = gm.Bp, nt = Bp / TB;
@@ -409,21 +465,32 @@ __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
     if (!narrow && a.fr && ti >= gm.npiv && tj < a.jp) return;
     const long long slot = (long long)Bp * TB;
     const cplx<T>* R = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff + a.rsel * slot;
-    load_tile(sP, A, Bp, ti * TB, J0);
-    load_tile(sQ, R, TB, 0, tj * TB);
+    // the tiles' loads are issued before the accumulators', so that their LDS
+    // copies wait for them alone
     CTile<T> acc[2][2];
-    load_acc(acc, A, Bp, ti * TB, tj * TB);
-    __syncthreads();
-    tile_product(sP, sQ, acc);
+    if constexpr (HALVES) {
+        load_half_cols(sP, A, Bp, ti * TB, J0);
+        load_half_rows(sQ, R, TB, 0, tj * TB);
+        load_acc(acc, A, Bp, ti * TB, tj * TB);
+        __syncthreads();
+        tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
+        __syncthreads();
+        load_half_cols(sP, A, Bp, ti * TB, J0 + TB / 2);
+        load_half_rows(sQ, R, TB, TB / 2, tj * TB);
+        __syncthreads();
+        tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
+    } else {
+        load_tile(sP, A, Bp, ti * TB, J0);
+        load_tile(sQ, R, TB, 0, tj * TB);
+        load_acc(acc, A, Bp, ti * TB, tj * TB);
+        __syncthreads();
+        tile_product(sP, sQ, acc);
+    }
     if (a.mode == GJ_COMBINED && ti != a.jp - 1 && tj != a.jp - 1) {
         // the deferred update of panel J1 = jp - 1: its columns (slot 2) times
         // its rows (slot 0)
         const cplx<T>* R1 = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff;
-        __syncthreads();
-        load_tile(sP, R1 + 2 * slot, Bp, ti * TB, 0);
-        load_tile(sQ, R1, TB, 0, tj * TB);
-        __syncthreads();
-        tile_product(sP, sQ, acc);
+        gj_update_product<T, HALVES>(sP, sQ, R1 + 2 * slot, Bp, ti * TB, 0, R1, tj * TB, acc);
     }
     store_acc(A, Bp, ti * TB, tj * TB, acc, T(1));
 }
