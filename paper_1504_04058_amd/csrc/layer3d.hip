@@ -402,38 +402,29 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
 // Trailing update of panel jp: A[I,C] += A[I,J] R[J,C] for I, C outside the
 // panel; the pivot tile becomes D^-1.
 // acc += P Q for the trailing update, P = Pm(pr0.., pc0..) (64 x 64, leading
-// dimension pld) and Q = Qm(0.., qc0..) (leading dimension TB): whole tiles, or
-// (HALVES) the k range in two halves of 32 through half-size LDS copies
-template <typename T, bool HALVES>
+// dimension pld) and Q = Qm(0.., qc0..) (leading dimension TB), the k range in
+// two halves of 32 through half-size LDS copies
+template <typename T>
 __device__ __forceinline__ void gj_update_product(cplx<T>* sP, cplx<T>* sQ, const cplx<T>* Pm, long long pld,
                                                   int pr0, int pc0, const cplx<T>* Qm, int qc0,
                                                   CTile<T> (&acc)[2][2]) {
-    if constexpr (HALVES) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            __syncthreads();   // the previous half's reads are done
-            load_half_cols(sP, Pm, pld, pr0, pc0 + (TB / 2) * h);
-            load_half_rows(sQ, Qm, TB, (TB / 2) * h, qc0);
-            __syncthreads();
-            tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
-        }
-    } else {
-        __syncthreads();   // the previous product's reads are done
-        load_tile(sP, Pm, pld, pr0, pc0);
-        load_tile(sQ, Qm, TB, 0, qc0);
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();   // the previous half's reads are done
+        load_half_cols(sP, Pm, pld, pr0, pc0 + (TB / 2) * h);
+        load_half_rows(sQ, Qm, TB, (TB / 2) * h, qc0);
         __syncthreads();
-        tile_product(sP, sQ, acc);
+        tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
-    // FP64: the products run over the panel in two halves of 32, so that the
-    // LDS copies take half a tile each and two workgroups share a CU (whole
-    // tiles would take 133 KB); FP32 keeps whole tiles (66.5 KB)
-    constexpr bool HALVES = sizeof(T) == 8;
-    __shared__ cplx<T> sP[HALVES ? TB * KLD : TB * LDT];
-    __shared__ cplx<T> sQ[HALVES ? (TB / 2) * LDT : TB * LDT];
+    // the products run over the panel in two halves of 32, so that the LDS
+    // copies take half a tile each (33.5 KB in FP32, 67 KB in FP64 instead of
+    // 66.5 and 133): more workgroups share a CU
+    __shared__ cplx<T> sP[TB * KLD];
+    __shared__ cplx<T> sQ[(TB / 2) * LDT];
     const int js = blockIdx.y;
     const GjMat gm = gj_mat(a, js);
     const int Bp = gm.Bp, nt = Bp / TB;
@@ -465,32 +456,24 @@ __global__ __launch_bounds__(NT) void gj_update_kernel(GjArgs a) {
     if (!narrow && a.fr && ti >= gm.npiv && tj < a.jp) return;
     const long long slot = (long long)Bp * TB;
     const cplx<T>* R = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff + a.rsel * slot;
-    // the tiles' loads are issued before the accumulators', so that their LDS
-    // copies wait for them alone
+    // the first half's loads are issued before the accumulators', so that its
+    // LDS copies wait for them alone
     CTile<T> acc[2][2];
-    if constexpr (HALVES) {
-        load_half_cols(sP, A, Bp, ti * TB, J0);
-        load_half_rows(sQ, R, TB, 0, tj * TB);
-        load_acc(acc, A, Bp, ti * TB, tj * TB);
-        __syncthreads();
-        tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
-        __syncthreads();
-        load_half_cols(sP, A, Bp, ti * TB, J0 + TB / 2);
-        load_half_rows(sQ, R, TB, TB / 2, tj * TB);
-        __syncthreads();
-        tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
-    } else {
-        load_tile(sP, A, Bp, ti * TB, J0);
-        load_tile(sQ, R, TB, 0, tj * TB);
-        load_acc(acc, A, Bp, ti * TB, tj * TB);
-        __syncthreads();
-        tile_product(sP, sQ, acc);
-    }
+    load_half_cols(sP, A, Bp, ti * TB, J0);
+    load_half_rows(sQ, R, TB, 0, tj * TB);
+    load_acc(acc, A, Bp, ti * TB, tj * TB);
+    __syncthreads();
+    tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
+    __syncthreads();
+    load_half_cols(sP, A, Bp, ti * TB, J0 + TB / 2);
+    load_half_rows(sQ, R, TB, TB / 2, tj * TB);
+    __syncthreads();
+    tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
     if (a.mode == GJ_COMBINED && ti != a.jp - 1 && tj != a.jp - 1) {
         // the deferred update of panel J1 = jp - 1: its columns (slot 2) times
         // its rows (slot 0)
         const cplx<T>* R1 = static_cast<const cplx<T>*>(a.Rbuf) + gm.roff;
-        gj_update_product<T, HALVES>(sP, sQ, R1 + 2 * slot, Bp, ti * TB, 0, R1, tj * TB, acc);
+        gj_update_product(sP, sQ, R1 + 2 * slot, Bp, ti * TB, 0, R1, tj * TB, acc);
     }
     store_acc(A, Bp, ti * TB, tj * TB, acc, T(1));
 }
