@@ -357,8 +357,10 @@ __global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
 // column-tile workgroups keep A[J,C] in Rbuf and set A[J,C] = D^-1 A[J,C].
 template <typename T>
 __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
-    __shared__ cplx<T> sD[TB * LDT];
-    __shared__ cplx<T> sA[TB * LDT];
+    // the products run over the panel in two halves of 32 through half-size LDS
+    // copies (33.5 KB in FP32, 67 KB in FP64 instead of 66.5 and 133)
+    __shared__ cplx<T> sP[TB * KLD];
+    __shared__ cplx<T> sQ[(TB / 2) * LDT];
     const int js = blockIdx.y;
     const GjMat gm = gj_mat(a, js);
     const int Bp = gm.Bp, nt = Bp / TB;
@@ -367,9 +369,8 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
     const int t = rowt ? blockIdx.x : blockIdx.x - a.ntmax;
     if (t >= nt || t == a.jp) return;
     cplx<T>* A = static_cast<cplx<T>*>(a.fac) + gm.off;
-    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
     const int J0 = a.jp * TB;
-    load_tile(sD, static_cast<const cplx<T>*>(a.Dbuf) + (long long)js * TB * TB, TB, 0, 0);
+    const cplx<T>* D = static_cast<const cplx<T>*>(a.Dbuf) + (long long)js * TB * TB;
     CTile<T> acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -379,22 +380,35 @@ __global__ __launch_bounds__(NT) void gj_panel_kernel(GjArgs a) {
     // J2, columns of J1), column-major with leading dimension 64 / Bp
     const long long slot = (long long)Bp * TB;
     if (rowt) {
-        load_tile(sA, A, Bp, t * TB, J0);
-        __syncthreads();
-        tile_product(sA, sD, acc);
+        // acc = A[t, J] D
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();
+            load_half_cols(sP, A, Bp, t * TB, J0 + (TB / 2) * h);
+            load_half_rows(sQ, D, TB, (TB / 2) * h, 0);
+            __syncthreads();
+            tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
+        }
         store_acc(A, Bp, t * TB, J0, acc, T(-1));
         if (a.save_c)
             store_acc(static_cast<cplx<T>*>(a.Rbuf) + gm.roff + 2 * slot, Bp, t * TB, 0, acc, T(-1));
     } else {
-        load_tile(sA, A, Bp, J0, t * TB);
-        __syncthreads();
+        // acc = D A[J, t]; A[J, t] also goes to the row buffer R
         cplx<T>* R = static_cast<cplx<T>*>(a.Rbuf) + gm.roff + a.rsel * slot;
+        const int rl = threadIdx.x & 31, cg = threadIdx.x >> 5;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();
+            load_half_cols(sP, D, TB, 0, (TB / 2) * h);
+            load_half_rows(sQ, A, Bp, J0 + (TB / 2) * h, t * TB);
+            __syncthreads();
 #pragma unroll 4
-        for (int e = 0; e < 16; ++e) {
-            const int c = cg + 4 * e;
-            R[(long long)(t * TB + c) * TB + r] = sA[r * LDT + c];
+            for (int e = 0; e < 8; ++e) {
+                const int c = cg + 8 * e;
+                R[(long long)(t * TB + c) * TB + (TB / 2) * h + rl] = sQ[rl * LDT + c];
+            }
+            tile_product<T, TB / 2, KLD, LDT>(sP, sQ, acc);
         }
-        tile_product(sD, sA, acc);
         store_acc(A, Bp, J0, t * TB, acc, T(1));
     }
 }
