@@ -69,99 +69,122 @@ struct AsmArgs {
     long long S;
 };
 
+constexpr int CPW = 16;      // front columns of one assembly / copy-out workgroup
+
 // F(r, c): the symmetric-form couplings of the 7-point operator between the
 // unknowns of rows r and c if one of them is a separator unknown, plus the
 // children's Schur complements on the pairs they share; identity / zero on
-// the padding.  One workgroup per front column c (what depends on c is
-// decoded once), threads over the rows.
+// the padding.  One workgroup per CPW consecutive front columns: what depends
+// on a column (its part and line, grid point, the children's columns) is
+// decoded once into LDS, each thread decodes a row once and writes it in all
+// CPW columns (one coalesced row segment per wave and column).
 template <typename T>
 __global__ __launch_bounds__(NT) void nd_assemble_kernel(AsmArgs a) {
     const long long fi = a.fbase + blockIdx.y;
     const NdFront F = a.fr[fi];
-    const int c = blockIdx.x;
-    if (c >= F.f) return;
+    const int c0 = blockIdx.x * CPW;
+    if (c0 >= F.f) return;
+    const int nc = min(CPW, F.f - c0);
     const NdNode nd = a.nodes[F.node];
     const int L = F.L;
-    const Part pc = decode(c, F.ipad, nd.nI, nd.nB, L);
-    cplx<T>* out = static_cast<cplx<T>*>(a.F) + F.foff + (long long)c * F.f;
-    if (pc.part >= 2) {
-        for (int r = threadIdx.x; r < F.f; r += NT)
-            out[r] = mk<T>((r == c && pc.part == 2) ? T(1) : T(0), T(0));
-        return;
-    }
     const SubDesc d = a.desc[F.sub];
-    const int colc = front_col(a.cols, nd, pc.c);
-    const int i1c = colc % a.n, i2c = colc / a.n;
-    const bool csep = pc.c < nd.nI;
     const zd* sh3 = a.subtab + d.tab_off;   // s3 at the half lines lo - 1/2 ..
     const zd* ish3 = sh3 + L + 1;           // 1 / (s3 h^2)
     const zd* is3 = sh3 + 2 * L + 1;        // 1 / s3
-    // the children's Schur complements: this column's position in each, if any
-    const cplx<T>* U[2] = {nullptr, nullptr};
-    int cc[2] = {-1, -1};
+    __shared__ int s_pk[CPW];               // part | line << 2
+    __shared__ int s_col[CPW];              // grid column, -1 padding
+    __shared__ int s_12[CPW];               // i1 | i2 << 16
+    __shared__ const cplx<T>* s_u[2][CPW];  // the children's columns from their row ipad, or null
+    int io[2] = {-1, -1};
     if (a.child0 >= 0) {
-        const long long base = a.child0 + (long long)F.sub * a.nnc;
+        io[0] = nd.inv_off[0];
+        io[1] = nd.inv_off[1];
+    }
+    if (threadIdx.x < nc) {
+        const int c = c0 + threadIdx.x;
+        const Part pc = decode(c, F.ipad, nd.nI, nd.nB, L);
+        s_pk[threadIdx.x] = pc.part | (pc.k << 2);
+        const int colc = pc.part < 2 ? front_col(a.cols, nd, pc.c) : -1;
+        s_col[threadIdx.x] = colc;
+        s_12[threadIdx.x] = colc < 0 ? 0 : (colc % a.n) | ((colc / a.n) << 16);
         for (int ch = 0; ch < 2; ++ch) {
-            const int io = nd.inv_off[ch];
-            cc[ch] = io < 0 ? -1 : a.inv[io + pc.c];
-            if (cc[ch] >= 0) {
-                const NdFront C = a.fr[base + nd.ch[ch]];
-                U[ch] = static_cast<const cplx<T>*>(a.Fc) + C.foff +
-                        (long long)(C.ipad + cc[ch] * L + pc.k) * C.f + C.ipad;
+            const cplx<T>* u = nullptr;
+            if (pc.part < 2 && io[ch] >= 0) {
+                const int cc = a.inv[io[ch] + pc.c];
+                if (cc >= 0) {
+                    const NdFront C = a.fr[a.child0 + (long long)F.sub * a.nnc + nd.ch[ch]];
+                    u = static_cast<const cplx<T>*>(a.Fc) + C.foff +
+                        (long long)(C.ipad + cc * L + pc.k) * C.f + C.ipad;
+                }
             }
+            s_u[ch][threadIdx.x] = u;
         }
     }
+    __syncthreads();
+    cplx<T>* out0 = static_cast<cplx<T>*>(a.F) + F.foff + (long long)c0 * F.f;
     for (int r = threadIdx.x; r < F.f; r += NT) {
         const Part pr = decode(r, F.ipad, nd.nI, nd.nB, L);
-        if (pr.part >= 2) {
-            out[r] = mk<T>((r == c && pr.part == 2) ? T(1) : T(0), T(0));
-            continue;
-        }
-        zd val = mk(0.0, 0.0);
-        if (csep || pr.c < nd.nI) {
-            const int colr = front_col(a.cols, nd, pr.c);
-            const int i1r = colr % a.n, i2r = colr / a.n;
-            if (colr == colc) {
-                const int k = pr.k;
-                if (pr.k == pc.k) {
-                    const zd s23 = a.ax.inv_s[i2r] * ish3[k];
-                    const zd s13 = a.ax.inv_s[i1r] * ish3[k];
-                    const zd s12 = a.ax.inv_s[i1r] * a.ax.inv_sh2[i2r];
-                    const zd c1 = (a.ax.sh[i1r + 1] + a.ax.sh[i1r]) * s23;
-                    const zd c2 = (a.ax.sh[i2r + 1] + a.ax.sh[i2r]) * s13;
-                    const zd c3 = (sh3[k + 1] + sh3[k]) * s12;
-                    const long long g = (long long)colr + a.S * (d.lo - 1 + k);
-                    val = ((a.ksq[g] * a.ax.inv_s[i1r]) * a.ax.inv_s[i2r]) * is3[k] - (c1 + c2 + c3);
-                } else if (pr.k - pc.k == 1 || pc.k - pr.k == 1) {
-                    val = sh3[max(pr.k, pc.k)] * (a.ax.inv_s[i1r] * a.ax.inv_sh2[i2r]);
-                }
-            } else if (pr.k == pc.k) {
-                const int k = pr.k;
-                if (i2r == i2c && (i1r - i1c == 1 || i1c - i1r == 1))
-                    val = a.ax.sh[max(i1r, i1c)] * (a.ax.inv_s[i2r] * ish3[k]);
-                else if (i1r == i1c && (i2r - i2c == 1 || i2c - i2r == 1))
-                    val = a.ax.sh[max(i2r, i2c)] * (a.ax.inv_s[i1r] * ish3[k]);
+        const int k = pr.k;
+        const bool live = pr.part < 2;
+        const bool rsep = pr.part == 0;
+        const int colr = live ? front_col(a.cols, nd, pr.c) : -1;
+        const int i1r = live ? colr % a.n : 0, i2r = live ? colr / a.n : 0;
+        const int cr0 = live && io[0] >= 0 ? a.inv[io[0] + pr.c] : -1;
+        const int cr1 = live && io[1] >= 0 ? a.inv[io[1] + pr.c] : -1;
+        for (int q = 0; q < nc; ++q) {
+            const int c = c0 + q;
+            const int cpk = s_pk[q], cpart = cpk & 3, ck = cpk >> 2;
+            cplx<T>* out = out0 + (long long)q * F.f;
+            if (cpart >= 2 || !live) {
+                const bool one = r == c && (cpart == 2 || (cpart < 2 && pr.part == 2));
+                out[r] = mk<T>(one ? T(1) : T(0), T(0));
+                continue;
             }
+            zd val = mk(0.0, 0.0);
+            if (cpart == 0 || rsep) {
+                const int colc = s_col[q];
+                if (colr == colc) {
+                    if (k == ck) {
+                        const zd s23 = a.ax.inv_s[i2r] * ish3[k];
+                        const zd s13 = a.ax.inv_s[i1r] * ish3[k];
+                        const zd s12 = a.ax.inv_s[i1r] * a.ax.inv_sh2[i2r];
+                        const zd cf1 = (a.ax.sh[i1r + 1] + a.ax.sh[i1r]) * s23;
+                        const zd cf2 = (a.ax.sh[i2r + 1] + a.ax.sh[i2r]) * s13;
+                        const zd cf3 = (sh3[k + 1] + sh3[k]) * s12;
+                        const long long g = (long long)colr + a.S * (d.lo - 1 + k);
+                        val = ((a.ksq[g] * a.ax.inv_s[i1r]) * a.ax.inv_s[i2r]) * is3[k] - (cf1 + cf2 + cf3);
+                    } else if (k - ck == 1 || ck - k == 1) {
+                        val = sh3[max(k, ck)] * (a.ax.inv_s[i1r] * a.ax.inv_sh2[i2r]);
+                    }
+                } else if (k == ck) {
+                    const int i1c = s_12[q] & 0xffff, i2c = s_12[q] >> 16;
+                    if (i2r == i2c && (i1r - i1c == 1 || i1c - i1r == 1))
+                        val = a.ax.sh[max(i1r, i1c)] * (a.ax.inv_s[i2r] * ish3[k]);
+                    else if (i1r == i1c && (i2r - i2c == 1 || i2c - i2r == 1))
+                        val = a.ax.sh[max(i2r, i2c)] * (a.ax.inv_s[i1r] * ish3[k]);
+                }
+            }
+            const cplx<T>* u0 = s_u[0][q];
+            const cplx<T>* u1 = s_u[1][q];
+            if (u0 && cr0 >= 0) val = val + ccast<double>(u0[cr0 * L + k]);
+            if (u1 && cr1 >= 0) val = val + ccast<double>(u1[cr1 * L + k]);
+            out[r] = ccast<T>(val);
         }
-        for (int ch = 0; ch < 2; ++ch) {
-            if (cc[ch] < 0) continue;
-            const int cr = a.inv[nd.inv_off[ch] + pr.c];
-            if (cr >= 0) val = val + ccast<double>(U[ch][cr * L + pr.k]);
-        }
-        out[r] = ccast<T>(val);
     }
 }
 
 // factor block [F_II^-1 | F_II^-1 F_IB] = the first ipad rows of the front;
-// one workgroup per front column
+// one workgroup per CPW consecutive front columns
 template <typename T>
 __global__ __launch_bounds__(NT) void nd_copyout_kernel(const NdFront* fr, const void* F, void* fac) {
     const NdFront f = fr[blockIdx.y];
-    const int c = blockIdx.x;
-    if (c >= f.f) return;
-    const cplx<T>* src = static_cast<const cplx<T>*>(F) + f.foff + (long long)c * f.f;
-    cplx<T>* dst = static_cast<cplx<T>*>(fac) + f.moff + (long long)c * f.ipad;
-    for (int r = threadIdx.x; r < f.ipad; r += NT) dst[r] = src[r];
+    const int c0 = blockIdx.x * CPW;
+    const int c1 = min(c0 + CPW, f.f);
+    const cplx<T>* src = static_cast<const cplx<T>*>(F) + f.foff;
+    cplx<T>* dst = static_cast<cplx<T>*>(fac) + f.moff;
+    for (int c = c0; c < c1; ++c)
+        for (int r = threadIdx.x; r < f.ipad; r += NT)
+            dst[(long long)c * f.ipad + r] = src[(long long)c * f.f + r];
 }
 
 struct SolveNdArgs {
@@ -457,7 +480,7 @@ hipError_t launch_nd_assemble(const asp_plan* P, const NdLevel& lv, int s0, int 
     a.n = P->n;
     a.S = P->S;
     const long long nfr = (long long)(s1 - s0) * lv.nn;
-    const unsigned gx = (unsigned)fmax;
+    const unsigned gx = (unsigned)((fmax + CPW - 1) / CPW);
     for (long long y0 = 0; y0 < nfr; y0 += YMAX) {
         a.fbase = lv.front0 + (long long)s0 * lv.nn + y0;
         dim3 grid(gx, (unsigned)std::min<long long>(YMAX, nfr - y0));
@@ -471,7 +494,7 @@ hipError_t launch_nd_assemble(const asp_plan* P, const NdLevel& lv, int s0, int 
 
 hipError_t launch_nd_copyout(const asp_plan* P, const NdFront* fr, int nfr, const void* Flevel,
                              int fmax, hipStream_t st) {
-    const unsigned gx = (unsigned)fmax;
+    const unsigned gx = (unsigned)((fmax + CPW - 1) / CPW);
     for (int y0 = 0; y0 < nfr; y0 += YMAX) {
         dim3 grid(gx, (unsigned)std::min(YMAX, nfr - y0));
         if (P->prec != ASP_PREC_FP64)
