@@ -288,13 +288,17 @@ __device__ __forceinline__ GjMat gj_mat(const GjArgs& a, int js) {
     return m;
 }
 
-// Pivot tile of panel jp: Dbuf = D^-1 for D = A[J,J], one 1024-thread
-// workgroup per job.  Gauss-Jordan elimination without pivoting: thread t holds
-// row t % 64, columns t / 64 + 16 e (e = 0..3); the pivot row and column pass
-// through LDS, double-buffered (one barrier per pivot).  A zero or non-finite
-// pivot sets the breakdown flag.
-template <typename T>
-__global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
+// Pivot tile of panel jp: Dbuf = D^-1 for D = A[J,J], one workgroup of PVG
+// waves per job.  Gauss-Jordan elimination without pivoting: thread t holds
+// row t % 64, columns t / 64 + PVG e (e = 0 .. PVE - 1); the pivot row and
+// column pass through LDS, double-buffered (one barrier per pivot).  Sixteen
+// waves give the shortest chain of 64 dependent pivots (few jobs per launch);
+// four waves do the same work with less per-entry overhead and several
+// workgroups per CU (many jobs per launch, the small fronts of nested
+// dissection).  A zero or non-finite pivot sets the breakdown flag.
+template <typename T, int PVG>
+__global__ __launch_bounds__(64 * PVG) void gj_pivot_kernel(GjArgs a) {
+    constexpr int PVE = TB / PVG;   // columns per thread
     __shared__ cplx<T> rowbuf[2][TB], colbuf[2][TB];
     __shared__ int bad;
     const int js = blockIdx.x;
@@ -302,12 +306,12 @@ __global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
     const int Bp = gm.Bp;
     if (a.jp >= gm.npiv) return;
     const cplx<T>* A = static_cast<const cplx<T>*>(a.fac) + gm.off;
-    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;     // cg = 0..15
+    const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;     // cg = 0 .. PVG - 1
     const int J0 = a.jp * TB;
     if (threadIdx.x == 0) bad = 0;
-    cplx<T> v[4];
+    cplx<T> v[PVE];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = A[(long long)(J0 + cg + 16 * e) * Bp + J0 + r];
+    for (int e = 0; e < PVE; ++e) v[e] = A[(long long)(J0 + cg + PVG * e) * Bp + J0 + r];
     const T tiny = sizeof(T) == 4 ? T(1e-36) : T(1e-300);
     __syncthreads();
     for (int piv = 0; piv < TB; ++piv) {
@@ -315,12 +319,12 @@ __global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
         cplx<T>* cb = colbuf[piv & 1];
         if (r == piv)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) rb[cg + 16 * e] = v[e];
-        if ((piv & 15) == cg) {
+            for (int e = 0; e < PVE; ++e) rb[cg + PVG * e] = v[e];
+        if (piv % PVG == cg) {
             cplx<T> pc = v[0];
 #pragma unroll
-            for (int e = 1; e < 4; ++e) {
-                const bool hit = e == (piv >> 4);
+            for (int e = 1; e < PVE; ++e) {
+                const bool hit = e == piv / PVG;
                 pc.x = hit ? v[e].x : pc.x;
                 pc.y = hit ? v[e].y : pc.y;
             }
@@ -332,15 +336,18 @@ __global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
         if (!(p2 > tiny) || !(p2 < T(1) / tiny)) bad = 1;
         const cplx<T> pinv = mk<T>(p.x / p2, -p.y / p2);
         // every entry: v -= (A[r][piv] / p) A[piv][c]; then the pivot row is
-        // A[piv][c] / p and the pivot column -A[r][piv] / p (1 / p at the pivot)
+        // A[piv][c] / p and the pivot column -A[r][piv] / p (1 / p at the pivot).
+        // Both row cases are one multiply-subtract: x = v' - m A[piv][c] with
+        // (v', m) = (0, -1 / p) on the pivot row, (v, A[r][piv] / p) elsewhere.
         const bool prow = r == piv;
         const cplx<T> crp = cb[r] * pinv;
         const cplx<T> colv = csel(prow, pinv, -crp);
+        const cplx<T> m = csel(prow, -pinv, crp);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const cplx<T> rc = rb[cg + 16 * e];
-            cplx<T> x = csel(prow, rc * pinv, v[e] - crp * rc);
-            const bool pcol = (cg + 16 * e) == piv;
+        for (int e = 0; e < PVE; ++e) {
+            const cplx<T> rc = rb[cg + PVG * e];
+            cplx<T> x = csel(prow, mk<T>(T(0), T(0)), v[e]) - m * rc;
+            const bool pcol = (cg + PVG * e) == piv;
             x.x = pcol ? colv.x : x.x;
             x.y = pcol ? colv.y : x.y;
             v[e] = x;
@@ -348,7 +355,7 @@ __global__ __launch_bounds__(1024) void gj_pivot_kernel(GjArgs a) {
     }
     cplx<T>* D = static_cast<cplx<T>*>(a.Dbuf) + (long long)js * TB * TB;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) D[(cg + 16 * e) * TB + r] = v[e];
+    for (int e = 0; e < PVE; ++e) D[(cg + PVG * e) * TB + r] = v[e];
     __syncthreads();
     if (threadIdx.x == 0 && bad) *a.flag = 1;
 }
@@ -885,17 +892,27 @@ hipError_t launch_form3d(const asp_plan* P, const int* jobs, int njobs, int k, h
 
 namespace {
 
+// jobs per launch above which the pivot tiles use the four-wave workgroups
+// (two sixteen-wave workgroups fit a CU: 512 run at once on 256 CUs)
+constexpr int PIVOT_MANY = 512;
+
 void launch_gj(const asp_plan* P, const GjArgs& a, int njobs, hipStream_t st) {
     dim3 g0(njobs), g1(2 * a.ntmax, njobs), g2(a.ntmax * a.ntmax, njobs);
     if (P->prec != ASP_PREC_FP64) {
-        hipLaunchKernelGGL(gj_pivot_kernel<float>, g0, dim3(1024), 0, st, a);
+        if (njobs > PIVOT_MANY)
+            hipLaunchKernelGGL((gj_pivot_kernel<float, 4>), g0, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((gj_pivot_kernel<float, 16>), g0, dim3(1024), 0, st, a);
         hipLaunchKernelGGL(gj_panel_kernel<float>, g1, dim3(NT), 0, st, a);
         if (P->prec == ASP_PREC_BF16X3)
             hipLaunchKernelGGL(gj_update_bf16x3_kernel, g2, dim3(NT), 0, st, a);
         else
             hipLaunchKernelGGL(gj_update_kernel<float>, g2, dim3(NT), 0, st, a);
     } else {
-        hipLaunchKernelGGL(gj_pivot_kernel<double>, g0, dim3(1024), 0, st, a);
+        if (njobs > PIVOT_MANY)
+            hipLaunchKernelGGL((gj_pivot_kernel<double, 4>), g0, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((gj_pivot_kernel<double, 16>), g0, dim3(1024), 0, st, a);
         hipLaunchKernelGGL(gj_panel_kernel<double>, g1, dim3(NT), 0, st, a);
         hipLaunchKernelGGL(gj_update_kernel<double>, g2, dim3(NT), 0, st, a);
     }
